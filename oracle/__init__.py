@@ -1,0 +1,207 @@
+"""CPU oracle for the batched Kalman-filter track fit -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product (the HIP library and its binding) never
+does.  The arithmetic lives in kf_oracle.cpp (plain FP64 C++, one track at a
+time, OpenMP over tracks); this module only marshals numpy arrays.
+
+All arrays are component-major ([component][item]) float64 / int32, the same
+layout the HIP library takes, so one generated event feeds both.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "kf_oracle.cpp")
+LIB = os.path.join(HERE, "libkf_oracle.so")
+
+# status codes (same meaning as the HIP library's per-track status byte)
+ST_OK, ST_NO_INTERSECT, ST_STEP_CAP, ST_NOT_SPD, ST_BAD_INPUT, ST_TOO_FEW = range(6)
+
+DEFAULT_TOL = 1e-4
+DEFAULT_LAND_TOL = 1e-10
+DEFAULT_MAX_STEPS = 1000
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (portable x86-64 code, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
+               SRC, "-o", LIB + ".tmp"]
+        subprocess.check_call(cmd)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        i, d = C.c_int, C.c_double
+        fit_args = [i, P, P, P, P, i, P, P, P, i, P, d, P, P, i, i, d, d, d, i]
+        L.kfo_fit.argtypes = fit_args + [P] * 12 + [i]
+        L.kfo_fit.restype = i
+        L.kfo_fit_vjp.argtypes = fit_args + [P] * 6 + [i]
+        L.kfo_fit_vjp.restype = i
+        L.kfo_count_ops.argtypes = fit_args + [P]
+        L.kfo_count_ops.restype = i
+        L.kfo_transport.argtypes = [i, P, P, P, i, P, d, d, d, d, i, i, i, P, P, P, P]
+        L.kfo_transport.restype = i
+        L.kfo_rkn_step.argtypes = [i, P, d, d, P, d, P, P]
+        L.kfo_rkn_step.restype = d
+        L.kfo_linear_smoother.argtypes = [i] + [P] * 11
+        L.kfo_linear_smoother.restype = i
+        L.kfo_ms_noise.argtypes = [i, P, P, P, i, P, d, P]
+        L.kfo_ms_noise.restype = i
+        L.kfo_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+@dataclass
+class FitResult:
+    par: np.ndarray        # (6, H) smoothed
+    cov: np.ndarray        # (21, H)
+    tgt_par: np.ndarray    # (6, N)
+    tgt_cov: np.ndarray    # (21, N)
+    chi2: np.ndarray       # (N,)
+    ndf: np.ndarray        # (N,)
+    status: np.ndarray     # (N,) u8
+    filt_par: np.ndarray | None = None
+    filt_cov: np.ndarray | None = None
+    pred_par: np.ndarray | None = None
+    pred_cov: np.ndarray | None = None
+    trials: np.ndarray | None = None
+
+
+class _Args:
+    """Common input marshalling for kfo_fit / kfo_fit_vjp / kfo_count_ops."""
+
+    def __init__(self, ev, detector=None, ms=None, mass=None, tol=DEFAULT_TOL, land_tol=DEFAULT_LAND_TOL,
+                 max_steps=DEFAULT_MAX_STEPS, loc=None, seed_par=None):
+        det = detector if detector is not None else ev.detector
+        self.keep = dict(
+            off=_i32(ev.hit_offsets), sid=_i32(ev.surface_id), loc=_f64(ev.loc if loc is None else loc),
+            cov=_f64(ev.cov), center=_f64(det.center), rot=_f64(det.rot), x0=_f64(det.x_over_X0),
+            b0=_f64(ev.field.b0), seed=_f64(ev.seed_par if seed_par is None else seed_par),
+            seed_cov=_f64(ev.seed_cov))
+        k = self.keep
+        self.N = ev.n_tracks
+        self.H = ev.n_hits
+        self.S = det.center.shape[1]
+        self.args = [self.N, _p(k["off"]), _p(k["sid"]), _p(k["loc"]), _p(k["cov"]), self.S, _p(k["center"]),
+                     _p(k["rot"]), _p(k["x0"]), int(ev.field.kind), _p(k["b0"]), float(ev.field.a),
+                     _p(k["seed"]), _p(k["seed_cov"]), int(ev.seed_surface),
+                     int(ev.multiple_scattering if ms is None else ms), float(ev.mass if mass is None else mass),
+                     float(tol), float(land_tol), int(max_steps)]
+
+
+def fit(ev, n_threads: int = 0, extras: bool = False, **kw) -> FitResult:
+    """Filter + RTS smoother for every track of `ev` (FP64)."""
+    a = _Args(ev, **kw)
+    N, H = a.N, a.H
+    out = FitResult(np.empty((6, H)), np.empty((21, H)), np.empty((6, N)), np.empty((21, N)),
+                    np.empty(N), np.empty(N, np.int32), np.empty(N, np.uint8))
+    if extras:
+        out.filt_par, out.filt_cov = np.empty((6, H)), np.empty((21, H))
+        out.pred_par, out.pred_cov = np.empty((6, H)), np.empty((21, H))
+        out.trials = np.empty(H, np.int32)
+    lib().kfo_fit(*a.args, _p(out.par), _p(out.cov), _p(out.tgt_par), _p(out.tgt_cov), _p(out.chi2),
+                  _p(out.ndf), _p(out.status), _p(out.filt_par), _p(out.filt_cov), _p(out.pred_par),
+                  _p(out.pred_cov), _p(out.trials), int(n_threads))
+    return out
+
+
+def fit_vjp(ev, g_chi2, g_par=None, g_tgt=None, n_threads: int = 0, **kw):
+    """Exact VJP (forward-mode duals) -> (g_meas (2,H), g_align (6,S), g_seed (6,N))."""
+    a = _Args(ev, **kw)
+    g_chi2 = _f64(g_chi2)
+    g_par = None if g_par is None else _f64(g_par)
+    g_tgt = None if g_tgt is None else _f64(g_tgt)
+    g_meas = np.zeros((2, a.H))
+    g_align = np.zeros((6, a.S))
+    g_seed = np.zeros((6, a.N))
+    lib().kfo_fit_vjp(*a.args, _p(g_chi2), _p(g_par), _p(g_tgt), _p(g_meas), _p(g_align), _p(g_seed),
+                      int(n_threads))
+    return g_meas, g_align, g_seed
+
+
+def count_ops(ev, **kw) -> np.ndarray:
+    """(N, 5) non-trivial op counts per track: add/sub, mul, div, sqrt, transcendental."""
+    a = _Args(ev, **kw)
+    out = np.zeros((a.N, 5), dtype=np.int64)
+    lib().kfo_count_ops(*a.args, _p(out))
+    return out
+
+
+def transport(det, field, sa, sb, x, mass=0.1056583755, tol=DEFAULT_TOL, land_tol=DEFAULT_LAND_TOL,
+              max_steps=DEFAULT_MAX_STEPS):
+    """Bound state x on surface sa -> (status, x' on sb, F = dx'/dx (6,6), trials)."""
+    center, rot, x0 = _f64(det.center), _f64(det.rot), _f64(det.x_over_X0)
+    b0 = _f64(field.b0)
+    xi = _f64(x)
+    xo = np.empty(6)
+    F = np.empty((6, 6))
+    tr = np.zeros(1, np.int32)
+    st = lib().kfo_transport(center.shape[1], _p(center), _p(rot), _p(x0), int(field.kind), _p(b0),
+                             float(field.a), float(mass), float(tol), float(land_tol), int(max_steps),
+                             int(sa), int(sb), _p(xi), _p(xo), _p(F), _p(tr))
+    return st, xo, F, int(tr[0])
+
+
+def rkn_step(field, F, h, mass=0.1056583755):
+    """One RKN step of the free state (x,y,z,t,Tx,Ty,Tz,q/p) -> (F', D (8,8), err)."""
+    b0 = _f64(field.b0)
+    Fi = _f64(F)
+    Fn = np.empty(8)
+    D = np.empty((8, 8))
+    e = lib().kfo_rkn_step(int(field.kind), _p(b0), float(field.a), float(mass), _p(Fi), float(h), _p(Fn), _p(D))
+    return Fn, D, e
+
+
+def linear_smoother(F, Q, m, V, x0, C0):
+    """Linear-Gaussian filter + RTS with the oracle's update/RTS routines.
+
+    F, Q: (n,6,6); m: (n,2); V: (n,3); x0: (6,); C0: (6,6).
+    Returns xs (n+1,6), Cs (n+1,6,6), xf (n,6), Cf (n,6,6), chi2 (n,)."""
+    n = F.shape[0]
+    F, Q, m, V, x0, C0 = map(_f64, (F, Q, m, V, x0, C0))
+    xs = np.empty((n + 1, 6)); Cs = np.empty((n + 1, 6, 6))
+    xf = np.empty((n, 6)); Cf = np.empty((n, 6, 6)); chi2 = np.empty(n)
+    st = lib().kfo_linear_smoother(n, _p(F), _p(Q), _p(m), _p(V), _p(x0), _p(C0), _p(xs), _p(Cs), _p(xf),
+                                   _p(Cf), _p(chi2))
+    if st:
+        raise RuntimeError(f"linear smoother status {st}")
+    return xs, Cs, xf, Cf, chi2
+
+
+def ms_noise(det, s, x, mass=0.1056583755):
+    """Process noise Q (6,6) of the thin scatterer on surface s for bound state x."""
+    center, rot, x0 = _f64(det.center), _f64(det.rot), _f64(det.x_over_X0)
+    xi = _f64(x)
+    Q = np.empty((6, 6))
+    lib().kfo_ms_noise(center.shape[1], _p(center), _p(rot), _p(x0), int(s), _p(xi), float(mass), _p(Q))
+    return Q

@@ -1,0 +1,193 @@
+"""Pins of the oracle's full track fit (filter + RTS smoother).
+
+  * noise-free hits and a seed at the truth give back the truth;
+  * field-free fit against a Gauss-Newton least-squares solution of the
+    straight-line model written out here (prior included);
+  * pulls of the fitted parameters have mean 0 and width 1 (Sect. 5.2, the
+    paper's own validation) at the target plane and at every hit plane;
+  * chi2 follows a chi2(ndf) distribution with a diffuse prior;
+  * the same with multiple scattering (Highland kicks in the generator);
+  * every failure status is produced for its cause, and other tracks in the
+    batch are untouched.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2105_01796_amd import synth
+
+DIAG = [0, 6, 11, 15, 18, 20]          # packed indices of the 6 variances
+
+
+def _noise_free(ev):
+    ev.loc = np.ascontiguousarray(ev.truth_hit[:2])
+    ev.seed_par = ev.truth_par0.copy()
+    return ev
+
+
+def test_noise_free_field_free_fit_returns_truth(oracle_lib):
+    ev = _noise_free(synth.telescope_event(50, 11, bz=0.0))
+    r = oracle_lib.fit(ev)
+    assert np.all(r.status == 0)
+    sig = np.sqrt(r.tgt_cov[DIAG])
+    assert np.max(np.abs(r.tgt_par - ev.truth_par0) / sig) < 1e-10
+    sh = np.sqrt(r.cov[DIAG])
+    assert np.max(np.abs(r.par - ev.truth_hit) / sh) < 1e-10
+    assert np.max(r.chi2) < 1e-18
+
+
+@pytest.mark.parametrize("cfg", [1, 3])
+def test_noise_free_fit_in_field_returns_truth_to_truncation(oracle_lib, cfg):
+    ev = _noise_free(synth.make_config(cfg, 200))
+    r = oracle_lib.fit(ev)
+    assert np.all(r.status == 0)
+    assert np.max(np.abs(r.tgt_par - ev.truth_par0) / np.sqrt(r.tgt_cov[DIAG])) < 1e-4
+    assert np.max(np.abs(r.par - ev.truth_hit) / np.sqrt(r.cov[DIAG])) < 1e-4
+    assert np.max(r.chi2) < 1e-6
+
+
+def _gauss_newton_straight(x_planes, m, V, seed, C0):
+    """min_p sum_k |m_k - h_k(p)|^2_V + |p - seed|^2_C0 over p = (l0, l1, phi, theta)."""
+    W0 = np.linalg.inv(C0[:4, :4])
+    p = seed[:4].copy()
+    for _ in range(50):
+        l0, l1, ph, th = p
+        A = np.zeros((4, 4))
+        b = -W0 @ (p - seed[:4])
+        for k, x in enumerate(x_planes):
+            h = np.array([l0 + x * np.tan(ph), l1 + x / (np.tan(th) * np.cos(ph))])
+            J = np.array([[1, 0, x / np.cos(ph) ** 2, 0],
+                          [0, 1, x * np.sin(ph) / (np.tan(th) * np.cos(ph) ** 2), -x / (np.sin(th) ** 2 * np.cos(ph))]])
+            Vi = np.linalg.inv([[V[0, k], V[1, k]], [V[1, k], V[2, k]]])
+            A += J.T @ Vi @ J
+            b += J.T @ Vi @ (m[:, k] - h)
+        A += W0
+        dp = np.linalg.solve(A, b)
+        p = p + dp
+        if np.max(np.abs(dp)) < 1e-15:
+            break
+    return p, np.linalg.inv(A)
+
+
+def _gn_gap(oracle_lib, seed_scale):
+    ev = synth.telescope_event(200, 12, bz=0.0)
+    ev.seed_par = ev.truth_par0 + seed_scale * (ev.seed_par - ev.truth_par0)
+    r = oracle_lib.fit(ev)
+    xs = ev.detector.center[0, 1:]
+    C = np.zeros((6, 6))
+    gaps, cov_gap = [], 0.0
+    for t in range(ev.n_tracks):
+        o = ev.hit_offsets[t]
+        k = 0
+        for i in range(6):
+            for j in range(i, 6):
+                C[i, j] = C[j, i] = ev.seed_cov[k, t]
+                k += 1
+        p, Cp = _gauss_newton_straight(xs, ev.loc[:, o:o + 10], ev.cov[:, o:o + 10], ev.seed_par[:, t], C)
+        sig = np.sqrt(np.diag(Cp))
+        gaps.append(np.max(np.abs(r.tgt_par[:4, t] - p) / sig))
+        Ct = np.array([[r.tgt_cov[_pk(min(i, j), max(i, j)), t] for j in range(4)] for i in range(4)])
+        cov_gap = max(cov_gap, np.max(np.abs(Ct - Cp) / np.outer(sig, sig)))
+    return np.array(gaps), cov_gap
+
+
+def test_field_free_fit_agrees_with_gauss_newton(oracle_lib):
+    """The extended Kalman filter linearises around its running estimate, so it
+    matches the least-squares optimum only up to second-order terms in the
+    distance between linearisation point and optimum: the gap shrinks with
+    the square of the seed error down to a floor set by the hit noise."""
+    gaps, cov_gap = _gn_gap(oracle_lib, 1.0)
+    assert gaps.max() < 2e-2 and np.median(gaps) < 2e-3
+    assert cov_gap < 1e-2
+    gaps3, _ = _gn_gap(oracle_lib, 0.3)
+    assert gaps3.max() < gaps.max() / 4
+
+
+def _pk(i, j):
+    return [(a, b) for a in range(6) for b in range(a, 6)].index((i, j))
+
+
+def _pulls(val, truth, var):
+    return (val - truth) / np.sqrt(var)
+
+
+@pytest.mark.parametrize("cfg,n", [(1, 10000), (2, 10000), (3, 5000)])
+def test_pulls_are_standard_normal(oracle_lib, cfg, n):
+    ev = synth.make_config(cfg, n, seed=2001)
+    r = oracle_lib.fit(ev)
+    assert np.all(r.status == 0)
+    N = ev.n_tracks
+    p = _pulls(r.tgt_par, ev.truth_par0, r.tgt_cov[DIAG])
+    assert np.all(np.abs(p.mean(axis=1)) < 4 / np.sqrt(N)), p.mean(axis=1)
+    assert np.all(np.abs(p.std(axis=1) - 1) < 4 / np.sqrt(2 * N)), p.std(axis=1)
+    ph = _pulls(r.par, ev.truth_hit, r.cov[DIAG])
+    for s in np.unique(ev.surface_id):
+        sel = ev.surface_id == s
+        q = ph[:, sel]
+        M = sel.sum()
+        assert np.all(np.abs(q.mean(axis=1)) < 4.5 / np.sqrt(M)), (s, q.mean(axis=1))
+        assert np.all(np.abs(q.std(axis=1) - 1) < 4.5 / np.sqrt(2 * M)), (s, q.std(axis=1))
+    # consistent prior: E[chi2] = 2 n (every measured coordinate)
+    nmeas = 2 * np.diff(ev.hit_offsets)
+    z = (r.chi2 - nmeas).sum() / np.sqrt(2 * nmeas.sum())
+    assert abs(z) < 4
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_chi2_follows_ndf_with_diffuse_prior(oracle_lib, cfg):
+    ev = synth.make_config(cfg, 10000, seed=2002, f_inf=1e4)
+    r = oracle_lib.fit(ev)
+    assert np.all(r.status == 0)
+    ndf = r.ndf[0]
+    assert ndf == 15
+    z = (r.chi2.mean() - ndf) / np.sqrt(2 * ndf / ev.n_tracks)
+    assert abs(z) < 4
+    assert stats.kstest(r.chi2, stats.chi2(ndf).cdf).pvalue > 1e-3
+    # no field: q/p is not measured -> one fewer constraint
+    ev0 = synth.telescope_event(4000, 2003, bz=0.0, f_inf=1e4)
+    r0 = oracle_lib.fit(ev0)
+    assert r0.ndf[0] == 16
+    assert abs((r0.chi2.mean() - 16) / np.sqrt(32 / 4000)) < 4
+
+
+def test_failure_statuses_and_isolation(oracle_lib):
+    base = synth.make_config(1, 20, seed=77)
+    ref = oracle_lib.fit(base)
+    assert np.all(ref.status == 0)
+    off = base.hit_offsets
+
+    def check(ev, t, status, **kw):
+        r = oracle_lib.fit(ev, **kw)
+        assert r.status[t] == status
+        assert np.all(np.isnan(r.tgt_par[:, t])) and np.isnan(r.chi2[t])
+        others = np.arange(ev.n_tracks) != t
+        assert np.all(r.status[others] == 0)
+        hit_others = np.ones(ev.n_hits, bool)
+        hit_others[off[t]:off[t + 1]] = False
+        assert np.array_equal(r.par[:, hit_others], ref.par[:, hit_others])
+        assert np.array_equal(r.tgt_par[:, others], ref.tgt_par[:, others])
+
+    ev = synth.make_config(1, 20, seed=77); ev.loc[0, off[3] + 2] = np.nan
+    check(ev, 3, oracle_lib.ST_BAD_INPUT)
+    ev = synth.make_config(1, 20, seed=77); ev.cov[0, off[4] + 1] = 0.0
+    check(ev, 4, oracle_lib.ST_BAD_INPUT)
+    ev = synth.make_config(1, 20, seed=77); ev.seed_cov[0, 5] = -1.0
+    check(ev, 5, oracle_lib.ST_BAD_INPUT)
+    ev = synth.make_config(1, 20, seed=77); ev.surface_id[off[6] + 1] = 99
+    check(ev, 6, oracle_lib.ST_BAD_INPUT)
+    ev = synth.make_config(1, 20, seed=77); ev.seed_par[2, 7] = np.pi / 2   # moving along y: parallel to the planes
+    check(ev, 7, oracle_lib.ST_NO_INTERSECT)
+    # too few hits: a 2-hit track in the middle of the batch
+    ev = synth.make_config(1, 20, seed=77)
+    keep = np.ones(ev.n_hits, bool)
+    keep[off[8] + 2: off[9]] = False
+    ev.loc, ev.cov, ev.surface_id = ev.loc[:, keep], ev.cov[:, keep], ev.surface_id[keep]
+    ev.truth_hit = ev.truth_hit[:, keep]
+    cnt = np.diff(off).copy(); cnt[8] = 2
+    ev.hit_offsets = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+    r = oracle_lib.fit(ev)
+    assert r.status[8] == oracle_lib.ST_TOO_FEW and np.all(r.status[np.arange(20) != 8] == 0)
+    assert np.array_equal(r.tgt_par[:, 9:], ref.tgt_par[:, 9:])
+    # step cap: every track needs at least two trials per gap in a 2 T field
+    r = oracle_lib.fit(base, max_steps=1)
+    assert np.all(r.status == oracle_lib.ST_STEP_CAP)
