@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Throughput of the batched Kalman-filter track fit on one MI355X.
+
+Workload (default): 1e5 muon tracks, 10 planes normal to x at x = 30..300 mm,
+uniform Bz = 2 T, 0.5 % X0 per plane with Highland multiple scattering,
+pT 1-10 GeV, |phi| < 0.1, |eta| < 0.2, 50 um hits; seeded synthetic data.
+One step = one filter + RTS-smoother pass over all tracks (inputs resident
+in HBM).  Prints one JSON line.
+
+The roofline entry uses the oracle's count of non-trivial floating-point
+operations per track (add/sub, mul, div, sqrt) times the tracks in a launch,
+divided by the fit launch's average duration measured with HIP events on the
+launch stream; the peak is MI355X's FP64 vector rate.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tracks fitted/s (filter+smoother; +adjoint) at 1e5 tracks, FP64 vs mixed"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    1: "100 tracks, 10 planes x=30..300 mm, Bz=2 T, pT 1-10 GeV, no material",
+    2: "1e5 tracks, 10 planes x=30..300 mm, Bz=2 T, 0.5% X0/plane Highland MS, pT 1-10 GeV, |phi|<0.1, |eta|<0.2",
+    3: "1e5 tracks, 30 planes x=30..900 mm, Bz=2 T, ragged 5-30 hits (holes p=0.1)",
+    4: "1e5 tracks, 10 planes, Bz=2 T, misaligned truth",
+    5: "solenoid B=2T(1-0.1(z/1m)^2), 30 planes, pT log-uniform 0.5-100 GeV, |eta|<2.5, ragged 8-30 hits",
+}
+
+
+def host_threads() -> int:
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def time_plan(plan, steps, warmup):
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.run(stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for a, b in ev:
+        a.record(stream)
+        plan.run(stream)
+        b.record(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    per = [a.elapsed_time(b) for a, b in ev]
+    return total_ms / steps, sum(per) / len(per), per
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
+    ap.add_argument("--tracks", type=int, default=None)
+    ap.add_argument("--schedule", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--occupancy", type=int, default=0)
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU only (tracks are independent; the multi-GPU "
+              "sharding is described in DESIGN.md and not built). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2105_01796_amd import kfmi, synth
+
+    t_gen = time.time()
+    ev = synth.make_config(args.config, args.tracks)
+    t_gen = time.time() - t_gen
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    batch = kfmi.Batch.from_event(ev, device=dev)
+    N = ev.n_tracks
+    base_opt = dict(schedule=args.schedule, block=args.block, occupancy=args.occupancy,
+                    waves_per_cu=args.waves_per_cu)
+
+    # FP64 leg (the headline value)
+    plan64 = kfmi.Plan(batch, kfmi.Options(precision=kfmi.KF_PREC_FP64, **base_opt))
+    ms64, kms64, per64 = time_plan(plan64, args.steps, args.warmup)
+    st = plan64.out.status.cpu().numpy()
+    n_ok = int((st == 0).sum())
+
+    mixed = None
+    if not args.no_mixed:
+        planm = kfmi.Plan(batch, kfmi.Options(precision=kfmi.KF_PREC_MIXED, **base_opt))
+        msm, kmsm, _ = time_plan(planm, args.steps, args.warmup)
+        mixed = {"value": N / (msm * 1e-3), "ms_per_step": msm, "launch_ms": kmsm,
+                 "speedup_vs_fp64": ms64 / msm}
+
+    # algorithmic work per track (oracle operation count on a sample)
+    import oracle
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(N, min(N, 400), replace=False))
+    cnt = oracle.count_ops(ev.subset(idx))
+    flops_per_track = float(cnt[:, :4].sum(axis=1).mean())
+    hits_per_track = ev.n_hits / N
+    flops = flops_per_track * N
+    achieved = flops / (kms64 * 1e-3) / 1e12
+    io_bytes = ev.n_hits * (2 + 3) * 8 + ev.n_hits * 4 + (N + 1) * 4 + N * 27 * 8 \
+        + ev.n_hits * 27 * 8 + N * 27 * 8 + N * (8 + 4 + 1)
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "flops_per_track": flops_per_track, "hits_per_track": hits_per_track,
+                "io_bytes_per_launch": io_bytes, "io_GBs": io_bytes / (kms64 * 1e-3) / 1e9}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        nth = host_threads()
+        m = min(N, 20000)
+        sub = ev.subset(np.arange(m))
+        oracle.fit(sub, n_threads=nth)        # warm
+        t0 = time.time()
+        done = 0
+        while True:
+            oracle.fit(sub, n_threads=nth)
+            done += m
+            if time.time() - t0 >= args.cpu_seconds:
+                break
+        dt = time.time() - t0
+        cpu = {"value": done / dt, "unit": "tracks/s", "cores": nth, "kind": "oracle",
+               "sample": f"first {m} tracks of the same workload, fitted {done // m}x in {dt:.1f} s "
+                         f"(FP64 filter+smoother, OpenMP over tracks)"}
+
+    out = {
+        "metric": METRIC,
+        "value": N / (ms64 * 1e-3),
+        "unit": "tracks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"C{args.config}: " + WORKLOADS[args.config], "tracks": N,
+                   "hits": ev.n_hits, "precision": "fp64", "launch_ms": kms64,
+                   "launch_ms_min": min(per64), "tracks_ok": n_ok, "options": base_opt,
+                   "gen_seconds": round(t_gen, 2)},
+        "mixed": mixed,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,165 @@
+/*
+ * kf.h -- C ABI of the MI355X batched Kalman-filter track fitter (libkfmi.so).
+ *
+ * The library fits many independent charged-particle tracks at once.  Each
+ * track is a list of 2-D hits on planar surfaces.  The fit is the Kalman-filter
+ * track fit of the paper (Sect. 2, Fig. 1): adaptive Runge-Kutta-Nystrom
+ * propagation from surface to surface with the transport Jacobian and the
+ * local<->global Jacobians (Sect. 4.1), a gain-matrix update on every measured
+ * surface (Sect. 2, step 3), then a Rauch-Tung-Striebel smoother that reuses
+ * the Jacobians stored during the forward pass (Sect. 2, smoother paragraph).
+ * The matrix inverse the smoother needs is always done in FP64 (Sect. 4.2.4).
+ * The per-track data sets follow Sect. 4.3: measurements, starting
+ * parameters, fit configuration (target surface), and results (status,
+ * track states, fitted parameters at the target surface).
+ *
+ * Conventions
+ *   units            mm, GeV, T, ns, rad
+ *   bound parameters (loc0, loc1, phi, theta, q/p, t) -- Sect. 2 parameter list;
+ *                    phi in (-pi, pi], theta in [0, pi]
+ *   covariances      packed upper triangle, row-major: (0,0),(0,1)..(0,5),(1,1)..(5,5)
+ *   surfaces         planes with centre c and rotation R = [u v n] (columns);
+ *                    loc0 = u.(r - c), loc1 = v.(r - c); planes are unbounded
+ *   array layout     component-major ("[3][S]" means 3 rows of S items); every
+ *                    array pointer is a DEVICE pointer owned by the caller
+ *   hits             CSR over tracks: hits of track t are hit_offsets[t] ..
+ *                    hit_offsets[t+1]-1, in the order the track crosses them
+ *   seed surface     the starting parameters live on one surface (kf_seeds);
+ *                    the fitted parameters are returned on that same surface
+ *                    (it is the fit's target surface)
+ *
+ * Execution: every entry point validates its arguments on the host before any
+ * device work, then enqueues kernels on `stream` (a hipStream_t, NULL = the
+ * null stream) and returns without waiting.  Inputs must stay valid until the
+ * stream reaches the work.  The library allocates device memory only for its
+ * own small persistent tables; the caller passes a workspace of at least
+ * kf_workspace_bytes().  Calls that share a workspace must not overlap.
+ *
+ * Errors: a negative return is an argument error found on the host before any
+ * launch (nothing was enqueued), or KF_E_HIP if the HIP runtime refused a
+ * launch.  Per-track problems are reported in status[t] (KF_ST_*); a failed
+ * track's outputs are NaN and never affect other tracks.
+ */
+#ifndef KF_H
+#define KF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define KF_OK 0
+#define KF_E_NULL (-1)      /* a required pointer is NULL */
+#define KF_E_SIZE (-2)      /* a count is negative, too large, or inconsistent */
+#define KF_E_ENUM (-3)      /* an enum field has an unknown value */
+#define KF_E_WS (-4)        /* workspace missing or too small */
+#define KF_E_HIP (-5)       /* the HIP runtime reported an error */
+#define KF_E_VALUE (-6)     /* a configuration value is out of range (tolerance <= 0, ...) */
+
+/* ---- per-track status ---- */
+#define KF_ST_OK 0
+#define KF_ST_NO_INTERSECT 1   /* direction parallel to a target plane (|n.T| < 1e-6) */
+#define KF_ST_STEP_CAP 2       /* more than max_steps RKN trials in one gap */
+#define KF_ST_NOT_SPD 3        /* residual covariance or predicted covariance not positive definite */
+#define KF_ST_BAD_INPUT 4      /* non-finite input, non-SPD hit or seed covariance, bad surface id,
+                                  or more hits than kf_measurements.max_hits */
+#define KF_ST_TOO_FEW 5        /* fewer than 3 hits */
+
+/* ---- enums ---- */
+#define KF_FIELD_UNIFORM 0     /* B = b0 everywhere */
+#define KF_FIELD_SOLENOID 1    /* Bz = b0[2] (1 - a z^2), Bx = a b0[2] x z, By = a b0[2] y z */
+
+#define KF_PREC_FP64 0         /* every step in FP64 */
+#define KF_PREC_MIXED 1        /* RKN stepping and transport Jacobian in FP32 on increments
+                                  from an FP64 anchor; landing, update, smoother in FP64 */
+
+#define KF_SCHED_AUTO 0        /* pick from the autotune table */
+#define KF_SCHED_DIRECT 1      /* one lane per track, tracks in input order */
+#define KF_SCHED_SORTED 2      /* tracks sorted by hit count (longest first), persistent waves
+                                  pull 64-track tiles from a queue */
+
+#define KF_MAX_SURFACES 512     /* the surface table is staged in LDS (13 doubles each) */
+#define KF_MAX_HITS 64         /* per track */
+
+typedef struct {
+    int32_t n;                 /* number of surfaces S (1 .. KF_MAX_SURFACES) */
+    const double *center;      /* [3][S] */
+    const double *rot;         /* [9][S] row-major 3x3, columns u, v, n (orthonormal) */
+    const double *x_over_X0;   /* [S] material thickness in radiation lengths (0 = none) */
+} kf_surfaces;
+
+typedef struct {
+    int32_t kind;              /* KF_FIELD_* */
+    double b0[3];              /* T */
+    double a;                  /* 1/mm^2, KF_FIELD_SOLENOID only */
+} kf_field;
+
+typedef struct {
+    int32_t n_tracks;          /* N >= 0 */
+    int32_t max_hits;          /* upper bound of hits per track (1 .. KF_MAX_HITS); tracks with
+                                  more hits get KF_ST_BAD_INPUT */
+    int64_t n_hits;            /* H = hit_offsets[N] (the host cannot read device memory) */
+    const int32_t *hit_offsets;  /* [N+1] non-decreasing, hit_offsets[0] = 0 */
+    const int32_t *surface_id;   /* [H] */
+    const double *loc;           /* [2][H] measured loc0, loc1 */
+    const double *cov;           /* [3][H] hit covariance v00, v01, v11 */
+} kf_measurements;
+
+typedef struct {
+    const double *par;         /* [6][N] starting parameters on the seed surface */
+    const double *cov;         /* [21][N] their covariance (the prior), packed upper */
+    int32_t surface_id;        /* the seed / target surface */
+} kf_seeds;
+
+typedef struct {
+    int32_t precision;           /* KF_PREC_* */
+    int32_t multiple_scattering; /* 1: thin-scatterer process noise after each update (Highland) */
+    double mass;                 /* GeV */
+    double rk_tol;               /* RKN local error tolerance [mm], e.g. 1e-4 */
+    double land_tol;             /* landing tolerance on the distance to a plane [mm], e.g. 1e-10 */
+    int32_t max_steps;           /* RKN trials per gap, e.g. 1000 */
+    int32_t schedule;            /* KF_SCHED_* */
+    int32_t block;               /* threads per workgroup (64, 128, 256), 0 = autotuned */
+    int32_t waves_per_cu;        /* persistent schedule: resident waves per CU, 0 = autotuned */
+    int32_t occupancy;           /* register budget as waves per SIMD (1, 2, 3), 0 = autotuned */
+} kf_config;
+
+typedef struct {
+    double *par;               /* [6][H] smoothed parameters at every hit */
+    double *cov;               /* [21][H] smoothed covariance at every hit */
+    double *tgt_par;           /* [6][N] fitted parameters on the seed/target surface */
+    double *tgt_cov;           /* [21][N] */
+    double *chi2;              /* [N] sum of predicted-residual chi2 increments */
+    int32_t *ndf;              /* [N] 2 n - 5 with field, 2 n - 4 without */
+    uint8_t *status;           /* [N] KF_ST_* */
+    int32_t *trials;           /* [H] optional (NULL): RKN trials taken to reach each hit */
+    double *filt_par;          /* [6][H] optional (NULL): filtered parameters */
+    double *filt_cov;          /* [21][H] optional (NULL) */
+} kf_outputs;
+
+/* Library version string (static storage). */
+const char *kf_version(void);
+
+/* Text for a return code or (if code >= 0) a per-track status. */
+const char *kf_status_string(int code);
+
+/* Bytes of workspace kf_fit_tracks needs for these sizes (0 on bad arguments).
+ * Grows as n_tracks * max_hits * 79 doubles (filtered state, predicted state,
+ * transport Jacobian per hit) plus small per-track and per-tile tables. */
+size_t kf_workspace_bytes(const kf_config *cfg, const kf_measurements *meas, int32_t n_surfaces);
+
+/* Filter + RTS smoother for every track (Sect. 2; Sect. 4.1; Sect. 4.3).
+ * All pointers inside the structs are device pointers except where stated.
+ * Returns KF_OK or a negative KF_E_* code; per-track results in out->status. */
+int kf_fit_tracks(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
+                  const kf_measurements *meas, const kf_seeds *seeds, const kf_outputs *out,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KF_H */

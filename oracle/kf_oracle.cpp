@@ -365,7 +365,8 @@ double rkn_step(const FieldDef& f, double mass, const S F[8], S h, S Fn[8], S (&
 //   first trial = the signed straight-line distance d = n.(c - r)/(n.T);
 //   every trial is capped by |d| (then h = d exactly);
 //   accept if err <= tol; next trial magnitude |h| * clamp(0.9 (tol/err)^(1/4), 0.25, 4);
-//   stop when |n.(c - r)| < land_tol.
+//   stop when |n.(c - r)| < land_tol, then move the remaining distance d onto
+//   the plane to second order in d.
 // D receives the product of the accepted steps' Jacobians.
 template <class S>
 int propagate(const FieldDef& f, const Cfg& cfg, const Surf<S>& s, S F[8], S (&D)[8][8], int* n_trials) {
@@ -394,6 +395,25 @@ int propagate(const FieldDef& f, const Cfg& cfg, const Surf<S>& s, S F[8], S (&D
             for (int i = 0; i < 8; ++i) for (int j = 0; j < 8; ++j) D[i][j] = Dn[i][j];
         }
         hmag = std::fabs(val(h)) * fac;
+    }
+    // Final move onto the plane, second order in the remaining distance d
+    // (|d| < land_tol): r += d T + d^2/2 T', T += d T', t += d dt/ds.  The
+    // result then lies on the plane to rounding whether or not one more
+    // landing iteration was taken.
+    {
+        S nT = *n3[0] * F[4] + *n3[1] * F[5] + *n3[2] * F[6];
+        S dist = *n3[0] * (s.c[0] - F[0]) + *n3[1] * (s.c[1] - F[1]) + *n3[2] * (s.c[2] - F[2]);
+        S d = dist / nT;
+        S r[3] = {F[0], F[1], F[2]}, T[3] = {F[4], F[5], F[6]};
+        S B[3], dB[3][3], TxB[3];
+        field_at(f, r, B, dB);
+        cross(T, B, TxB);
+        S lam = F[7];
+        for (int i = 0; i < 3; ++i) {
+            F[i] = F[i] + d * T[i] + 0.5 * d * d * lam * kB * TxB[i];
+            F[4 + i] = F[4 + i] + d * lam * kB * TxB[i];
+        }
+        F[3] = F[3] + d * sqrt(1.0 + cfg.mass * cfg.mass * lam * lam) / kC;
     }
     *n_trials = trials;
     return ST_OK;

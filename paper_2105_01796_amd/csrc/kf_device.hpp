@@ -1,0 +1,538 @@
+// kf_device.hpp -- device-side arithmetic of the batched Kalman-filter track fit.
+//
+// One lane fits one track.  Every small matrix lives in registers: loops over
+// matrix indices have compile-time bounds and are fully unrolled, so the
+// structural zeros and ones of the Jacobians fold away and nothing is indexed
+// dynamically (which would push arrays to scratch memory).
+//
+// Paper: Sect. 2 (Kalman step, gain-matrix update, RTS smoother with stored
+// Jacobians, chi2 from residuals, the six bound parameters), Sect. 4.1
+// (adaptive Runge-Kutta-Nystrom transport with transport Jacobian and
+// local<->global Jacobians; 8-component global representation), Sect. 4.2.4
+// (the smoother's inverse in FP64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kfm {
+
+constexpr double kC = 299.792458;         // speed of light, mm/ns
+constexpr double kKappa = 0.299792458e-3; // curvature per (q/p) per tesla, 1/mm per (GeV^-1 T)
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+enum : int { ST_OK = 0, ST_NO_INTERSECT = 1, ST_STEP_CAP = 2, ST_NOT_SPD = 3, ST_BAD_INPUT = 4, ST_TOO_FEW = 5 };
+enum : int { FIELD_UNIFORM = 0, FIELD_SOLENOID = 1 };
+
+// packed index of symmetric 6x6 element (i, j): upper triangle, row-major
+__host__ __device__ constexpr int sy(int i, int j) {
+    return i <= j ? (i * (11 - i)) / 2 + j : (j * (11 - j)) / 2 + i;
+}
+// stored rows of the bound transport Jacobian F: rows l0, l1, phi, theta, t
+// (the q/p row is e4 and the t column is e5, both implied); 5 x 5 = 25 entries
+__host__ __device__ constexpr int frow(int i) { return i < 4 ? i : 4; }
+
+// surface table entry in LDS: c[3], R[9] (row-major, columns u v n), x/X0
+constexpr int SURF_STRIDE = 13;
+
+struct FieldDef {
+    int kind;
+    double b0[3];
+    double a;
+};
+
+struct Cfg {
+    int ms;
+    double mass;
+    double tol;
+    double land_tol;
+    int max_steps;
+};
+
+template <class P> __device__ inline P pabs(P x) { return x < P(0) ? -x : x; }
+
+template <class P>
+__device__ inline void cross(const P a[3], const P b[3], P o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ inline double wrap_phi(double p) {
+    while (p > kPi) p -= 2.0 * kPi;
+    while (p <= -kPi) p += 2.0 * kPi;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// magnetic field in the propagation precision
+// ---------------------------------------------------------------------------
+template <class P, int FK>
+struct Field {
+    P b[3];   // uniform value, or (0, 0, b0z) for the solenoid
+    P g;      // a * b0z
+    P a;
+    __device__ void init(const FieldDef& f) {
+        for (int i = 0; i < 3; ++i) b[i] = P(f.b0[i]);
+        a = P(f.a);
+        g = P(f.a * f.b0[2]);
+    }
+    __device__ inline void eval(const P r[3], P B[3]) const {
+        if (FK == FIELD_UNIFORM) {
+            B[0] = b[0]; B[1] = b[1]; B[2] = b[2];
+        } else {
+            B[0] = g * r[0] * r[2];
+            B[1] = g * r[1] * r[2];
+            B[2] = b[2] - g * r[2] * r[2];
+        }
+    }
+    // dB_a/dr_b applied to v: (grad B) v
+    __device__ inline void grad_apply(const P r[3], const P v[3], P o[3]) const {
+        o[0] = g * (r[2] * v[0] + r[0] * v[2]);
+        o[1] = g * (r[2] * v[1] + r[1] * v[2]);
+        o[2] = P(-2) * g * r[2] * v[2];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// one Runge-Kutta-Nystrom trial step (Sect. 4.1), state on an FP64 anchor:
+//   position r = r0 + dr, direction T = T0 + dT, time t = t0 + dt
+//   r' = T, T' = (q/p) kappa T x B(r), t' = sqrt(1 + m^2 (q/p)^2)/c
+// ---------------------------------------------------------------------------
+template <class P, int FK>
+struct Stages {
+    P T[4][3];    // stage directions
+    P w[4][3];    // kappa * T_i x B(r_i)
+    P B[4][3];    // solenoid: field at the stage points
+    P r[4][3];    // solenoid: absolute stage positions
+};
+
+template <class P, int FK>
+__device__ inline P rkn_trial(const Field<P, FK>& fl, const P rabs[3], const P T[3], P lam, P h,
+                              Stages<P, FK>& S, P k[4][3]) {
+    const P h2 = h * P(0.5), hh = h * h;
+    P B[3];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        P rs[3], Ts[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (st == 0) { rs[i] = rabs[i]; Ts[i] = T[i]; }
+            else if (st == 1) { rs[i] = rabs[i] + h2 * T[i] + hh * P(0.125) * k[0][i]; Ts[i] = T[i] + h2 * k[0][i]; }
+            else if (st == 2) { rs[i] = S.r[1][i]; Ts[i] = T[i] + h2 * k[1][i]; }
+            else { rs[i] = rabs[i] + h * T[i] + hh * P(0.5) * k[2][i]; Ts[i] = T[i] + h * k[2][i]; }
+        }
+        if (FK == FIELD_UNIFORM) {
+            if (st == 0) fl.eval(rs, B);
+        } else {
+            fl.eval(rs, B);
+        }
+        P c[3];
+        cross(Ts, B, c);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            S.w[st][i] = P(kKappa) * c[i];
+            k[st][i] = lam * S.w[st][i];
+            if (FK != FIELD_UNIFORM) { S.T[st][i] = Ts[i]; S.B[st][i] = B[i]; S.r[st][i] = rs[i]; }
+            else if (st == 1) S.r[1][i] = rs[i];
+        }
+    }
+    P e = P(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) e += pabs(k[0][i] - k[1][i] - k[2][i] + k[3][i]);
+    return hh * e;
+}
+
+// Transport-Jacobian update for an accepted step: the columns (l0, l1, phi,
+// theta, q/p) of d(free state)/d(bound start) are pushed through the stage
+// equations at fixed h (forward tangents).
+template <class P, int FK>
+__device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& S, P lam, P h,
+                                   P Mr[3][5], P MT[3][5]) {
+    const P h2 = h * P(0.5), hh = h * h, lk = lam * P(kKappa);
+    P LB[3];
+    if (FK == FIELD_UNIFORM) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) LB[i] = lk * fl.b[i];
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        P dk[4][3], dr2[3], dr4[3];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            P dT[3], dr[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                if (st == 0) { dT[i] = MT[i][j]; dr[i] = Mr[i][j]; }
+                else if (st == 1) { dT[i] = MT[i][j] + h2 * dk[0][i]; dr2[i] = Mr[i][j] + h2 * MT[i][j] + hh * P(0.125) * dk[0][i]; dr[i] = dr2[i]; }
+                else if (st == 2) { dT[i] = MT[i][j] + h2 * dk[1][i]; dr[i] = dr2[i]; }
+                else { dT[i] = MT[i][j] + h * dk[2][i]; dr4[i] = Mr[i][j] + h * MT[i][j] + hh * P(0.5) * dk[2][i]; dr[i] = dr4[i]; }
+            }
+            P c[3];
+            if (FK == FIELD_UNIFORM) {
+                cross(dT, LB, c);
+            } else {
+                P g[3], c2[3];
+                cross(dT, S.B[st], c);
+                fl.grad_apply(S.r[st], dr, g);
+                cross(S.T[st], g, c2);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) c[i] = lk * (c[i] + c2[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) dk[st][i] = (j == 4) ? c[i] + S.w[st][i] : c[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const P dT1 = MT[i][j];
+            Mr[i][j] = Mr[i][j] + h * dT1 + hh * (P(1) / P(6)) * (dk[0][i] + dk[1][i] + dk[2][i]);
+            MT[i][j] = dT1 + h * (P(1) / P(6)) * (dk[0][i] + P(2) * dk[1][i] + P(2) * dk[2][i] + dk[3][i]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// bound -> free at surface a, adaptive propagation to plane b, path
+// correction, free -> bound.  Outputs the predicted bound state and the
+// 6x6 transport Jacobian F (25 stored entries).  Returns a status.
+// Step control (same decisions as the FP64 reference fit):
+//   first trial = signed straight-line distance d = n.(c - r)/(n.T);
+//   every trial is capped by |d| (then h = d);
+//   accept if err <= tol; next trial |h| * clamp(0.9 (tol/err)^(1/4), 1/4, 4);
+//   land when |n.(c - r)| < land_tol, then move the remaining distance onto
+//   the plane in FP64, to second order in that distance.
+// MIXED (P = float): stepping and tangents in FP32 on increments from the
+// FP64 anchor; the landing loop stops at an FP32-resolvable distance and the
+// same FP64 second-order move finishes it.
+// ---------------------------------------------------------------------------
+template <class P, int FK>
+__device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, const Cfg& cfg,
+                                const double* __restrict__ sa, const double* __restrict__ sb,
+                                const double x[6], double xp[6], double F[25], int* trials_out) {
+    // bound -> free on surface a
+    double sp, cp, st, ct;
+    sincos(x[2], &sp, &cp);
+    sincos(x[3], &st, &ct);
+    double r0[3], T0[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r0[i] = sa[i] + x[0] * sa[3 + 3 * i + 0] + x[1] * sa[3 + 3 * i + 1];
+    T0[0] = cp * st; T0[1] = sp * st; T0[2] = ct;
+    const double lam_d = x[4];
+    const P lam = P(lam_d);
+    const double gd = sqrt(1.0 + cfg.mass * cfg.mass * lam_d * lam_d) / kC;     // dt/ds
+    const double gpd = cfg.mass * cfg.mass * lam_d / (kC * kC * gd);            // d(dt/ds)/d(q/p)
+    P Mr[3][5], MT[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) { Mr[i][j] = P(0); MT[i][j] = P(0); }
+        Mr[i][0] = P(sa[3 + 3 * i + 0]);
+        Mr[i][1] = P(sa[3 + 3 * i + 1]);
+    }
+    MT[0][2] = P(-sp * st); MT[1][2] = P(cp * st); MT[2][2] = P(0);
+    MT[0][3] = P(cp * ct);  MT[1][3] = P(sp * ct); MT[2][3] = P(-st);
+    double Mtl = 0.0;     // d t / d(q/p) accumulated over accepted steps
+
+    const double nb[3] = {sb[3 + 2], sb[3 + 5], sb[3 + 8]};
+    const double d0 = nb[0] * (sb[0] - r0[0]) + nb[1] * (sb[1] - r0[1]) + nb[2] * (sb[2] - r0[2]);
+    const P n[3] = {P(nb[0]), P(nb[1]), P(nb[2])};
+    const P tol = P(cfg.tol);
+    const bool mixed = sizeof(P) < sizeof(double);
+    P dr[3] = {P(0), P(0), P(0)}, dT[3] = {P(0), P(0), P(0)};
+    double dt = 0.0;
+    P spath = P(0);       // accumulated path length in this gap
+    P hmag = P(-1);
+    int trials = 0;
+    int status = ST_OK;
+    Stages<P, FK> S;
+    for (;;) {
+        P T[3], rabs[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { T[i] = P(T0[i]) + dT[i]; rabs[i] = P(r0[i]) + dr[i]; }
+        const P nT = n[0] * T[0] + n[1] * T[1] + n[2] * T[2];
+        const P dist = P(d0) - (n[0] * dr[0] + n[1] * dr[1] + n[2] * dr[2]);
+        if (pabs(nT) < P(1e-6)) { status = ST_NO_INTERSECT; break; }
+        const P ltol = mixed ? P(1e-6) * (pabs(spath) + P(10)) : P(cfg.land_tol);
+        if (pabs(dist) < ltol) break;
+        if (trials >= cfg.max_steps) { status = ST_STEP_CAP; break; }
+        const P d = dist / nT;
+        if (hmag < P(0)) hmag = pabs(d);
+        const P h = (pabs(d) <= hmag) ? d : (d < P(0) ? -hmag : hmag);
+        P k[4][3];
+        const P err = rkn_trial<P, FK>(fl, rabs, T, lam, h, S, k);
+        ++trials;
+        const P tiny = P(sizeof(P) < sizeof(double) ? 1e-30 : 1e-300);
+        P fac = P(0.9) * sqrt(sqrt(tol / (err > tiny ? err : tiny)));
+        fac = fac < P(0.25) ? P(0.25) : (fac > P(4) ? P(4) : fac);
+        if (err <= tol) {
+            rkn_tangent<P, FK>(fl, S, lam, h, Mr, MT);
+            Mtl += double(h) * gpd;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                dr[i] = dr[i] + h * T[i] + h * h * (P(1) / P(6)) * (k[0][i] + k[1][i] + k[2][i]);
+                dT[i] = dT[i] + h * (P(1) / P(6)) * (k[0][i] + P(2) * k[1][i] + P(2) * k[2][i] + k[3][i]);
+            }
+            dt += double(h) * gd;
+            spath += h;
+        }
+        hmag = pabs(h) * fac;
+    }
+    *trials_out = trials;
+    if (status != ST_OK) return status;
+
+    // final free state in FP64, then the remaining distance d onto the plane,
+    // second order in d: r += d T + d^2/2 T', T += d T', t += d dt/ds
+    double r[3], T[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { r[i] = r0[i] + double(dr[i]); T[i] = T0[i] + double(dT[i]); }
+    double t = x[5] + dt;
+    Field<double, FK> f64;
+    f64.init(fd);
+    {
+        const double nT0 = nb[0] * T[0] + nb[1] * T[1] + nb[2] * T[2];
+        const double rem = (nb[0] * (sb[0] - r[0]) + nb[1] * (sb[1] - r[1]) + nb[2] * (sb[2] - r[2])) / nT0;
+        double B0[3], TB0[3];
+        f64.eval(r, B0);
+        cross(T, B0, TB0);
+        const double lk = lam_d * kKappa;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            r[i] += rem * T[i] + 0.5 * rem * rem * lk * TB0[i];
+            T[i] += rem * lk * TB0[i];
+        }
+        t += rem * gd;
+    }
+    const double nTd = nb[0] * T[0] + nb[1] * T[1] + nb[2] * T[2];
+    // path correction: move the variations back onto the plane along dF/ds
+    double B[3];
+    f64.eval(r, B);
+    double TxB[3];
+    cross(T, B, TxB);
+    double Mrd[3][5], MTd[3][5], Mt[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const double s = (nb[0] * double(Mr[0][j]) + nb[1] * double(Mr[1][j]) + nb[2] * double(Mr[2][j])) / nTd;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            Mrd[i][j] = double(Mr[i][j]) - T[i] * s;
+            MTd[i][j] = double(MT[i][j]) - lam_d * kKappa * TxB[i] * s;
+        }
+        Mt[j] = (j == 4 ? Mtl : 0.0) - gd * s;
+    }
+    // free -> bound on surface b, and F = J_fb * (corrected D J_bf)
+    const double u[3] = {sb[3 + 0], sb[3 + 3], sb[3 + 6]};
+    const double v[3] = {sb[3 + 1], sb[3 + 4], sb[3 + 7]};
+    const double dd[3] = {r[0] - sb[0], r[1] - sb[1], r[2] - sb[2]};
+    xp[0] = u[0] * dd[0] + u[1] * dd[1] + u[2] * dd[2];
+    xp[1] = v[0] * dd[0] + v[1] * dd[1] + v[2] * dd[2];
+    const double rho2 = T[0] * T[0] + T[1] * T[1];
+    const double rho = sqrt(rho2);
+    const double n2 = rho2 + T[2] * T[2];
+    xp[2] = atan2(T[1], T[0]);
+    xp[3] = atan2(rho, T[2]);
+    xp[4] = lam_d;
+    xp[5] = t;
+    const double ip = 1.0 / rho2, ith = 1.0 / (rho * n2), in2 = 1.0 / n2;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        F[0 * 5 + j] = u[0] * Mrd[0][j] + u[1] * Mrd[1][j] + u[2] * Mrd[2][j];
+        F[1 * 5 + j] = v[0] * Mrd[0][j] + v[1] * Mrd[1][j] + v[2] * Mrd[2][j];
+        F[2 * 5 + j] = (T[0] * MTd[1][j] - T[1] * MTd[0][j]) * ip;
+        F[3 * 5 + j] = T[2] * (T[0] * MTd[0][j] + T[1] * MTd[1][j]) * ith - rho * MTd[2][j] * in2;
+        F[4 * 5 + j] = Mt[j];
+    }
+    return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// thin-scatterer noise on surface s for the filtered state x (PDG Highland)
+// Q = diag(0, 0, theta0^2 / sin^2(theta), theta0^2, 0, 0)
+// ---------------------------------------------------------------------------
+__device__ inline void highland(const double* __restrict__ s, const double x[6], double mass, double* q22, double* q33) {
+    const double x0 = s[12];
+    if (!(x0 > 0.0)) { *q22 = 0.0; *q33 = 0.0; return; }
+    double sp, cp, st, ct;
+    sincos(x[2], &sp, &cp);
+    sincos(x[3], &st, &ct);
+    const double nT = s[3 + 2] * cp * st + s[3 + 5] * sp * st + s[3 + 8] * ct;
+    const double path = x0 / fabs(nT);
+    const double p = 1.0 / fabs(x[4]);
+    const double beta = p / sqrt(p * p + mass * mass);
+    const double th0 = 0.0136 / (beta * p) * sqrt(path) * (1.0 + 0.038 * log(path / (beta * beta)));
+    *q33 = th0 * th0;
+    *q22 = th0 * th0 / (st * st);
+}
+
+// ---------------------------------------------------------------------------
+// covariance transport Cp = F C F^T (C symmetric packed, F with implied
+// q/p row e4 and t column e5)
+// ---------------------------------------------------------------------------
+__device__ inline double fget(const double F[25], int i, int j) {
+    // valid for compile-time i, j after unrolling
+    return (i == 4) ? (j == 4 ? 1.0 : 0.0) : (j == 5 ? (i == 5 ? 1.0 : 0.0) : F[frow(i) * 5 + j]);
+}
+
+__device__ inline void transport_cov(const double F[25], const double C[21], double Cp[21]) {
+    double G[6][6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            if (i == 4) { G[i][m] = C[sy(4, m)]; continue; }
+            double acc = (i == 5) ? C[sy(5, m)] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) acc += F[frow(i) * 5 + j] * C[sy(j, m)];
+            G[i][m] = acc;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+        for (int l = i; l < 6; ++l) {
+            double acc;
+            if (l == 4) acc = G[i][4];
+            else {
+                acc = (l == 5) ? G[i][5] : 0.0;
+#pragma unroll
+                for (int m = 0; m < 5; ++m) acc += G[i][m] * F[frow(l) * 5 + m];
+            }
+            Cp[sy(i, l)] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gain-matrix update with H = [I2 0] (Sect. 2), Joseph covariance form:
+//   Cf = (I - K H) Cp (I - K H)^T + K V K^T
+//      = Cp - K P - P^T K^T + K S K^T,  P = H Cp, S = V + H Cp H^T
+// ---------------------------------------------------------------------------
+__device__ inline int kalman_update(const double xp[6], const double Cp[21], const double m[2],
+                                    const double V[3], double xf[6], double Cf[21], double* chi2) {
+    const double r0 = m[0] - xp[0], r1 = m[1] - xp[1];
+    const double S00 = V[0] + Cp[sy(0, 0)], S01 = V[1] + Cp[sy(0, 1)], S11 = V[2] + Cp[sy(1, 1)];
+    const double det = S00 * S11 - S01 * S01;
+    if (!(S00 > 0.0 && det > 0.0)) return ST_NOT_SPD;
+    const double idet = 1.0 / det;
+    const double I00 = S11 * idet, I01 = -S01 * idet, I11 = S00 * idet;
+    double K[6][2];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const double p0 = Cp[sy(0, i)], p1 = Cp[sy(1, i)];
+        K[i][0] = p0 * I00 + p1 * I01;
+        K[i][1] = p0 * I01 + p1 * I11;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) xf[i] = xp[i] + K[i][0] * r0 + K[i][1] * r1;
+    xf[2] = wrap_phi(xf[2]);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        // (K S)_i
+        const double ks0 = K[i][0] * S00 + K[i][1] * S01;
+        const double ks1 = K[i][0] * S01 + K[i][1] * S11;
+#pragma unroll
+        for (int j = i; j < 6; ++j) {
+            const double kp = K[i][0] * Cp[sy(0, j)] + K[i][1] * Cp[sy(1, j)];
+            const double pk = Cp[sy(0, i)] * K[j][0] + Cp[sy(1, i)] * K[j][1];
+            const double ksk = ks0 * K[j][0] + ks1 * K[j][1];
+            Cf[sy(i, j)] = Cp[sy(i, j)] - kp - pk + ksk;
+        }
+    }
+    *chi2 = r0 * (I00 * r0 + I01 * r1) + r1 * (I01 * r0 + I11 * r1);
+    return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// RTS smoother step (Sect. 2) with the stored Jacobian F of the step k -> k+1:
+//   A = Cf F^T Cp1^{-1}          (FP64 Cholesky solve, Sect. 4.2.4)
+//   xs = xf + A (xs1 - xp1),  Cs = Cf + A (Cs1 - Cp1) A^T
+// xs1/Cs1 are overwritten with the result (smoothed state k).
+// ---------------------------------------------------------------------------
+__device__ inline int rts_step(const double xf[6], const double Cf[21], const double F[25],
+                               const double xp1[6], const double Cp1[21], double xs[6], double Cs[21]) {
+    // D = Cs1 - Cp1 (symmetric), dx = xs1 - xp1
+    double D[21], dx[6];
+#pragma unroll
+    for (int q = 0; q < 21; ++q) D[q] = Cs[q] - Cp1[q];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) dx[i] = xs[i] - xp1[i];
+    dx[2] = wrap_phi(dx[2]);
+    // Cholesky Cp1 = L L^T (lower, packed by rows of L^T = upper of L^T)
+    double L[6][6], id[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        double s = Cp1[sy(j, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+        if (!(s > 0.0)) return ST_NOT_SPD;
+        const double l = sqrt(s);
+        L[j][j] = l;
+        id[j] = 1.0 / l;
+#pragma unroll
+        for (int i = j + 1; i < 6; ++i) {
+            double t = Cp1[sy(i, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t * id[j];
+        }
+    }
+    // B = F Cf (6x6); solve Cp1 X = B -> X = A^T
+    double X[6][6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            if (i == 4) { X[i][c] = Cf[sy(4, c)]; continue; }
+            double acc = (i == 5) ? Cf[sy(5, c)] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) acc += F[frow(i) * 5 + j] * Cf[sy(j, c)];
+            X[i][c] = acc;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            double s = X[i][c];
+#pragma unroll
+            for (int k = 0; k < i; ++k) s -= L[i][k] * X[k][c];
+            X[i][c] = s * id[i];
+        }
+#pragma unroll
+        for (int i = 5; i >= 0; --i) {
+            double s = X[i][c];
+#pragma unroll
+            for (int k = i + 1; k < 6; ++k) s -= L[k][i] * X[k][c];
+            X[i][c] = s * id[i];
+        }
+    }
+    // A[i][k] = X[k][i]
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double acc = xf[i];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc += X[k][i] * dx[k];
+        xs[i] = acc;
+    }
+    xs[2] = wrap_phi(xs[2]);
+    // Cs = Cf + A D A^T, one row of A D at a time
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double e[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc += X[k][i] * D[sy(k, m)];
+            e[m] = acc;
+        }
+#pragma unroll
+        for (int j = i; j < 6; ++j) {
+            double acc = Cf[sy(i, j)];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) acc += e[m] * X[m][j];
+            Cs[sy(i, j)] = acc;
+        }
+    }
+    return ST_OK;
+}
+
+}  // namespace kfm

@@ -1,0 +1,133 @@
+"""The C ABI of libkfmi.so on the CPU: the library loads, exports every symbol
+include/kf.h declares, and rejects bad arguments on the host before any device
+work (no GPU needed: validation precedes every HIP call)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def kf():
+    from paper_2105_01796_amd import kfmi
+    kfmi.lib()
+    return kfmi
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "kf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(kf_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol(kf):
+    decl = _declared()
+    assert set(decl) == set(kf.EXPORTS), decl
+    L = kf.lib()
+    for name in decl:
+        assert hasattr(L, name), name
+    assert "gfx950" in kf.kf_version()
+
+
+def test_status_strings(kf):
+    for code in [0, -1, -2, -3, -4, -5, -6, 1, 2, 3, 4, 5]:
+        assert kf.kf_status_string(code) != "unknown code"
+    assert kf.kf_status_string(99) == "unknown code"
+
+
+def _args(kf, N=10, H=100, max_hits=10, S=11):
+    fake = C.c_void_p(0x1000)     # never dereferenced on the host
+    cfg = kf.kf_config(0, 0, 0.1056583755, 1e-4, 1e-10, 1000, 0, 0, 0, 0)
+    surf = kf.kf_surfaces(S, fake, fake, fake)
+    fld = kf.kf_field(0, (C.c_double * 3)(0, 0, 2), 0.0)
+    meas = kf.kf_measurements(N, max_hits, H, fake, fake, fake, fake)
+    seeds = kf.kf_seeds(fake, fake, 0)
+    out = kf.kf_outputs(fake, fake, fake, fake, fake, fake, fake, None, None, None)
+    return cfg, surf, fld, meas, seeds, out
+
+
+def _call(kf, cfg, surf, fld, meas, seeds, out, ws=C.c_void_p(0x2000), nbytes=None):
+    L = kf.lib()
+    if nbytes is None:
+        nbytes = L.kf_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n)
+    return L.kf_fit_tracks(C.byref(cfg), C.byref(surf), C.byref(fld), C.byref(meas), C.byref(seeds),
+                           C.byref(out), ws, nbytes, None)
+
+
+def test_null_struct_pointers(kf):
+    L = kf.lib()
+    assert L.kf_fit_tracks(None, None, None, None, None, None, None, 0, None) == kf.KF_E_NULL
+
+
+def test_argument_validation(kf):
+    a = _args(kf)
+    cfg, surf, fld, meas, seeds, out = a
+    # bad enums
+    cfg.precision = 7
+    assert _call(kf, *a) == kf.KF_E_ENUM
+    cfg.precision = 0
+    cfg.schedule = 9
+    assert _call(kf, *a) == kf.KF_E_ENUM
+    cfg.schedule = 0
+    fld.kind = 5
+    assert _call(kf, *a) == kf.KF_E_ENUM
+    fld.kind = 0
+    # bad values
+    cfg.rk_tol = 0.0
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.rk_tol = 1e-4
+    cfg.block = 100
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.block = 0
+    cfg.occupancy = 9
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.occupancy = 0
+    fld.b0[2] = float("nan")
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    fld.b0[2] = 2.0
+    # bad sizes
+    meas.max_hits = kf.KF_MAX_HITS + 1
+    assert _call(kf, *a, nbytes=1 << 30) == kf.KF_E_SIZE
+    meas.max_hits = 10
+    meas.n_tracks = -1
+    assert _call(kf, *a, nbytes=1 << 30) == kf.KF_E_SIZE
+    meas.n_tracks = 10
+    surf.n = 0
+    assert _call(kf, *a, nbytes=1 << 30) == kf.KF_E_SIZE
+    surf.n = 11
+    seeds.surface_id = 11
+    assert _call(kf, *a) == kf.KF_E_SIZE
+    seeds.surface_id = 0
+    # null inner pointers
+    surf.center = None
+    assert _call(kf, *a) == kf.KF_E_NULL
+    surf.center = C.c_void_p(0x1000)
+    out.chi2 = None
+    assert _call(kf, *a) == kf.KF_E_NULL
+    out.chi2 = C.c_void_p(0x1000)
+    out.filt_par = C.c_void_p(0x1000)      # filt_par without filt_cov
+    assert _call(kf, *a) == kf.KF_E_NULL
+    out.filt_par = None
+    # workspace
+    assert _call(kf, *a, ws=None) == kf.KF_E_WS
+    need = kf.lib().kf_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n)
+    assert need >= 10 * 10 * 79 * 8
+    assert _call(kf, *a, nbytes=need - 1) == kf.KF_E_WS
+    # nothing to do: no tracks is OK without touching the device
+    meas.n_tracks = 0
+    assert _call(kf, *a) == kf.KF_OK
+
+
+def test_workspace_size_grows_with_tracks_and_hits(kf):
+    L = kf.lib()
+    cfg = kf.kf_config(0, 0, 0.1, 1e-4, 1e-10, 1000, 0, 0, 0, 0)
+    sizes = []
+    for N, mh in [(1, 10), (64, 10), (65, 10), (1000, 30)]:
+        m = kf.kf_measurements(N, mh, N * mh, None, None, None, None)
+        sizes.append(L.kf_workspace_bytes(C.byref(cfg), C.byref(m), 31))
+    assert sizes[0] == sizes[1] < sizes[2] < sizes[3]
+    m = kf.kf_measurements(10, 0, 0, None, None, None, None)
+    assert L.kf_workspace_bytes(C.byref(cfg), C.byref(m), 31) == 0

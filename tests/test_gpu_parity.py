@@ -1,0 +1,187 @@
+"""HIP fit vs the CPU oracle, element by element, through the C ABI.
+
+FP64 path: relative 1e-9 per element (1e-8 for the solenoid workload; see
+parity.py), identical status and ndf, RKN trial counts identical on >= 99.9 %
+of hits.  Mixed path: parameters within 1e-3 sigma.
+Full-size runs (1e5 tracks, the benchmark's launch configuration) are checked
+on a sample of tracks that the oracle fits one by one (tracks are independent,
+so a sub-batch has the same exact answer).
+"""
+import sys
+import os
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from parity import DIAG, attach_offsets, compare, par_err  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_2105_01796_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+# FP64 relative bar per workload (see parity.py for the solenoid floor)
+TOL = {1: 1e-9, 2: 1e-9, 3: 1e-9, 4: 1e-9, 5: 1e-8}
+
+
+@pytest.fixture(scope="module")
+def kf():
+    import torch
+    from paper_2105_01796_amd import kfmi
+    assert torch.cuda.is_available()
+    kfmi.lib()
+    return kfmi
+
+
+def _fit(kf, ev, extras=True, detector=None, **opt):
+    import torch
+    b = kf.Batch.from_event(ev, detector=detector)
+    out = kf.Plan(b, kf.Options(**opt), extras=extras).run()
+    torch.cuda.synchronize()
+    return out
+
+
+def _ref(ev, **kw):
+    return attach_offsets(oracle.fit(ev, extras=True, **kw), ev)
+
+
+def _announce(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("schedule,block,occ", [(1, 64, 1), (2, 64, 1), (1, 256, 1), (2, 128, 2), (1, 64, 3)])
+def test_c1_fp64_all_launch_shapes(kf, schedule, block, occ):
+    _announce(f"C1 fp64 schedule={schedule} block={block} occ={occ}")
+    ev = synth.make_config(1)
+    out = _fit(kf, ev, schedule=schedule, block=block, occupancy=occ)
+    compare(out, _ref(ev), label="C1")
+
+
+@pytest.mark.parametrize("cfg,n", [(2, 3000), (3, 3000), (4, 2000), (5, 2000)])
+def test_configs_fp64_small(kf, cfg, n):
+    _announce(f"C{cfg} fp64 n={n}")
+    ev = synth.make_config(cfg, n)
+    for sched in (1, 2):
+        out = _fit(kf, ev, schedule=sched)
+        compare(out, _ref(ev), tol=TOL[cfg], label=f"C{cfg} sched {sched}")
+
+
+def test_field_free_and_misaligned_geometry(kf):
+    _announce("B=0 and misaligned planes, fp64")
+    ev = synth.telescope_event(1000, 31, bz=0.0)
+    compare(_fit(kf, ev), _ref(ev), label="B=0")
+    ev = synth.make_config(4, 1000)
+    # give the fitter the tilted/shifted planes the hits were simulated on
+    out = _fit(kf, ev, detector=ev.detector_true)
+    compare(out, _ref(ev, detector=ev.detector_true), label="misaligned")
+
+
+def _sampled(out, ev, idx):
+    """GPU outputs restricted to tracks idx (with their hits), as numpy."""
+    off = ev.hit_offsets.astype(np.int64)
+    hit_idx = np.concatenate([np.arange(off[i], off[i + 1]) for i in idx])
+    g = lambda t: t.detach().cpu().numpy()
+    return SimpleNamespace(par=g(out.par)[:, hit_idx], cov=g(out.cov)[:, hit_idx], tgt_par=g(out.tgt_par)[:, idx],
+                           tgt_cov=g(out.tgt_cov)[:, idx], chi2=g(out.chi2)[idx], ndf=g(out.ndf)[idx],
+                           status=g(out.status)[idx], trials=g(out.trials)[hit_idx])
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_full_size_sampled_fp64(kf, cfg):
+    _announce(f"C{cfg} fp64 full size (1e5 tracks), sampled parity")
+    ev = synth.make_config(cfg)
+    out = _fit(kf, ev)                      # default launch configuration (as benchmarked)
+    rng = np.random.default_rng(cfg)
+    idx = np.sort(np.concatenate([[0, ev.n_tracks - 1], rng.choice(ev.n_tracks, 600, replace=False)]))
+    idx = np.unique(idx)
+    sub = ev.subset(idx)
+    compare(_sampled(out, ev, idx), _ref(sub), label=f"C{cfg} full/sampled")
+    st = out.status.cpu().numpy()
+    assert np.all(st == 0)
+
+
+def test_full_size_solenoid_sampled_fp64(kf):
+    _announce("C5 fp64 200k tracks, sampled parity")
+    ev = synth.make_config(5, 200_000)
+    out = _fit(kf, ev)
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([[0, ev.n_tracks - 1], rng.choice(ev.n_tracks, 400, replace=False)]))
+    compare(_sampled(out, ev, idx), _ref(ev.subset(idx)), tol=TOL[5], label="C5 sampled")
+
+
+@pytest.mark.parametrize("cfg,n", [(1, 100), (2, 3000), (3, 3000), (5, 2000)])
+def test_mixed_precision_within_1e3_sigma(kf, cfg, n):
+    _announce(f"C{cfg} mixed n={n}")
+    ev = synth.make_config(cfg, n)
+    out = _fit(kf, ev, precision=kf.KF_PREC_MIXED)
+    ref = _ref(ev)
+    assert np.array_equal(out.status.cpu().numpy(), ref.status)
+    _, sp = par_err(out.par, ref.par, ref.cov)
+    _, st = par_err(out.tgt_par, ref.tgt_par, ref.tgt_cov)
+    worst_hit = sp.max(axis=1)
+    worst_tgt = st.max(axis=1)
+    print(f"  mixed C{cfg}: max |d|/sigma per param, hits {np.array2string(worst_hit, precision=2)}"
+          f" target {np.array2string(worst_tgt, precision=2)}", flush=True)
+    assert worst_hit.max() < 1e-3 and worst_tgt.max() < 1e-3
+    chi = np.abs(out.chi2.cpu().numpy() - ref.chi2)
+    assert chi.max() < 1e-3 * np.sqrt(2 * ref.ndf.max())
+
+
+def test_edge_cases(kf):
+    _announce("edge cases")
+    import torch
+    # no tracks at all
+    ev = synth.make_config(1, 5)
+    e0 = ev.subset(np.array([], dtype=np.int64))
+    b = kf.Batch.from_event(e0)
+    out = kf.kf_fit_tracks(b)
+    torch.cuda.synchronize()
+    assert out.chi2.numel() == 0
+    # one batch with every failure mode next to good tracks
+    ev = synth.make_config(3, 300)
+    off = ev.hit_offsets
+    ev.loc[0, off[3] + 1] = np.nan                     # non-finite hit
+    ev.cov[2, off[5]] = -1.0                           # non-SPD hit covariance
+    ev.surface_id[off[7] + 2] = 500                    # surface id out of range
+    ev.seed_cov[0, 9] = 0.0                            # seed covariance not SPD
+    ev.seed_par[2, 11] = np.pi / 2                     # moving parallel to the planes
+    # a 2-hit track, a 1-hit track and a 0-hit track (too few)
+    cnt = np.diff(off).astype(np.int64)
+    keep = np.ones(ev.n_hits, bool)
+    for t, k in [(13, 2), (14, 1), (15, 0)]:
+        keep[off[t] + k: off[t + 1]] = False
+        cnt[t] = k
+    ev.loc, ev.cov, ev.surface_id, ev.truth_hit = ev.loc[:, keep], ev.cov[:, keep], ev.surface_id[keep], ev.truth_hit[:, keep]
+    ev.hit_offsets = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+    for sched in (1, 2):
+        out = _fit(kf, ev, schedule=sched)
+        ref = _ref(ev)
+        compare(out, ref, label=f"edge sched {sched}")
+        st = out.status.cpu().numpy()
+        assert st[3] == kf.KF_ST_BAD_INPUT and st[5] == kf.KF_ST_BAD_INPUT and st[7] == kf.KF_ST_BAD_INPUT
+        assert st[9] == kf.KF_ST_BAD_INPUT and st[11] == kf.KF_ST_NO_INTERSECT
+        assert st[13] == st[14] == st[15] == kf.KF_ST_TOO_FEW
+        assert (st == 0).sum() == ev.n_tracks - 8
+    # tracks longer than the declared max_hits are rejected, others fitted
+    ev = synth.make_config(3, 500)
+    b = kf.Batch.from_event(ev)
+    b.max_hits = 12
+    out = kf.Plan(b, kf.Options(), extras=True).run()
+    torch.cuda.synchronize()
+    n = np.diff(ev.hit_offsets)
+    st = out.status.cpu().numpy()
+    assert np.all(st[n > 12] == kf.KF_ST_BAD_INPUT) and np.all(st[n <= 12] == 0)
+    # step cap: one trial per gap is never enough in a field
+    out = _fit(kf, synth.make_config(1, 64), max_steps=1)
+    assert np.all(out.status.cpu().numpy() == kf.KF_ST_STEP_CAP)
+
+
+def test_run_to_run_bitwise_determinism(kf):
+    _announce("determinism")
+    ev = synth.make_config(3, 20000)
+    a = _fit(kf, ev)
+    b = _fit(kf, ev)
+    for name in ("par", "cov", "tgt_par", "tgt_cov", "chi2"):
+        assert np.array_equal(getattr(a, name).cpu().numpy(), getattr(b, name).cpu().numpy(), equal_nan=True), name
