@@ -119,7 +119,8 @@ typedef struct {
     int32_t multiple_scattering; /* 1: thin-scatterer process noise after each update (Highland) */
     double mass;                 /* GeV */
     double rk_tol;               /* RKN local error tolerance [mm], e.g. 1e-4 */
-    double land_tol;             /* landing tolerance on the distance to a plane [mm], e.g. 1e-10 */
+    double land_tol;             /* landing tolerance on the distance to a plane [mm], e.g. 1e-6; the
+                                    remaining distance is covered by a second-order move */
     int32_t max_steps;           /* RKN trials per gap, e.g. 1000 */
     int32_t schedule;            /* KF_SCHED_* */
     int32_t block;               /* threads per workgroup (64, 128, 256), 0 = autotuned */

@@ -25,7 +25,7 @@ LIB = os.path.join(HERE, "libkf_oracle.so")
 ST_OK, ST_NO_INTERSECT, ST_STEP_CAP, ST_NOT_SPD, ST_BAD_INPUT, ST_TOO_FEW = range(6)
 
 DEFAULT_TOL = 1e-4
-DEFAULT_LAND_TOL = 1e-10
+DEFAULT_LAND_TOL = 1e-6
 DEFAULT_MAX_STEPS = 1000
 
 

@@ -50,6 +50,12 @@ struct Cfg {
 
 template <class P> __device__ inline P pabs(P x) { return x < P(0) ? -x : x; }
 
+// Phase boundary for the instruction scheduler: nothing is moved across it.
+// The fit is a chain of register-heavy phases (propagation, covariance
+// transport, gain solve, update, smoother); letting the scheduler interleave
+// neighbouring phases for ILP would add their live sets together.
+__device__ inline void phase_boundary() { __builtin_amdgcn_sched_barrier(0); }
+
 template <class P>
 __device__ inline void cross(const P a[3], const P b[3], P o[3]) {
     o[0] = a[1] * b[2] - a[2] * b[1];
@@ -100,16 +106,18 @@ struct Field {
 // ---------------------------------------------------------------------------
 template <class P, int FK>
 struct Stages {
-    P T[4][3];    // stage directions
-    P w[4][3];    // kappa * T_i x B(r_i)
+    P T[4][3];    // solenoid: stage directions
     P B[4][3];    // solenoid: field at the stage points
     P r[4][3];    // solenoid: absolute stage positions
+    P r2[3];      // uniform: midpoint position (unused by the field)
 };
 
+// Returns the error estimate h^2 |k1 - k2 - k3 + k4|_1; k receives the stage
+// accelerations k_i = (q/p) kappa T_i x B(r_i).
 template <class P, int FK>
 __device__ inline P rkn_trial(const Field<P, FK>& fl, const P rabs[3], const P T[3], P lam, P h,
                               Stages<P, FK>& S, P k[4][3]) {
-    const P h2 = h * P(0.5), hh = h * h;
+    const P h2 = h * P(0.5), hh = h * h, lk = lam * P(kKappa);
     P B[3];
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
@@ -118,7 +126,7 @@ __device__ inline P rkn_trial(const Field<P, FK>& fl, const P rabs[3], const P T
         for (int i = 0; i < 3; ++i) {
             if (st == 0) { rs[i] = rabs[i]; Ts[i] = T[i]; }
             else if (st == 1) { rs[i] = rabs[i] + h2 * T[i] + hh * P(0.125) * k[0][i]; Ts[i] = T[i] + h2 * k[0][i]; }
-            else if (st == 2) { rs[i] = S.r[1][i]; Ts[i] = T[i] + h2 * k[1][i]; }
+            else if (st == 2) { rs[i] = (FK == FIELD_UNIFORM) ? S.r2[i] : S.r[1][i]; Ts[i] = T[i] + h2 * k[1][i]; }
             else { rs[i] = rabs[i] + h * T[i] + hh * P(0.5) * k[2][i]; Ts[i] = T[i] + h * k[2][i]; }
         }
         if (FK == FIELD_UNIFORM) {
@@ -130,10 +138,9 @@ __device__ inline P rkn_trial(const Field<P, FK>& fl, const P rabs[3], const P T
         cross(Ts, B, c);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            S.w[st][i] = P(kKappa) * c[i];
-            k[st][i] = lam * S.w[st][i];
+            k[st][i] = lk * c[i];
             if (FK != FIELD_UNIFORM) { S.T[st][i] = Ts[i]; S.B[st][i] = B[i]; S.r[st][i] = rs[i]; }
-            else if (st == 1) S.r[1][i] = rs[i];
+            else if (st == 1) S.r2[i] = rs[i];
         }
     }
     P e = P(0);
@@ -144,28 +151,31 @@ __device__ inline P rkn_trial(const Field<P, FK>& fl, const P rabs[3], const P T
 
 // Transport-Jacobian update for an accepted step: the columns (l0, l1, phi,
 // theta, q/p) of d(free state)/d(bound start) are pushed through the stage
-// equations at fixed h (forward tangents).
+// equations at fixed h (forward tangents).  d k_i/d(q/p) = k_i / (q/p).
+// In a uniform field dk/dr = 0, so the l0 and l1 columns stay (u, v; 0, 0)
+// exactly and are neither stored nor propagated: columns start at JT0.
+template <int FK> struct TangentCols { static constexpr int J0 = (FK == FIELD_UNIFORM) ? 2 : 0; };
 template <class P, int FK>
-__device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& S, P lam, P h,
+__device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& S, const P k[4][3], P lam, P h,
                                    P Mr[3][5], P MT[3][5]) {
-    const P h2 = h * P(0.5), hh = h * h, lk = lam * P(kKappa);
+    const P h2 = h * P(0.5), hh = h * h, lk = lam * P(kKappa), ilam = P(1) / lam;
     P LB[3];
     if (FK == FIELD_UNIFORM) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) LB[i] = lk * fl.b[i];
     }
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        P dk[4][3], dr2[3], dr4[3];
+    for (int j = TangentCols<FK>::J0; j < 5; ++j) {
+        P dk[3], sR[3], sT[3], dr2[3];
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
             P dT[3], dr[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 if (st == 0) { dT[i] = MT[i][j]; dr[i] = Mr[i][j]; }
-                else if (st == 1) { dT[i] = MT[i][j] + h2 * dk[0][i]; dr2[i] = Mr[i][j] + h2 * MT[i][j] + hh * P(0.125) * dk[0][i]; dr[i] = dr2[i]; }
-                else if (st == 2) { dT[i] = MT[i][j] + h2 * dk[1][i]; dr[i] = dr2[i]; }
-                else { dT[i] = MT[i][j] + h * dk[2][i]; dr4[i] = Mr[i][j] + h * MT[i][j] + hh * P(0.5) * dk[2][i]; dr[i] = dr4[i]; }
+                else if (st == 1) { dT[i] = MT[i][j] + h2 * dk[i]; dr2[i] = Mr[i][j] + h2 * MT[i][j] + hh * P(0.125) * dk[i]; dr[i] = dr2[i]; }
+                else if (st == 2) { dT[i] = MT[i][j] + h2 * dk[i]; dr[i] = dr2[i]; }
+                else { dT[i] = MT[i][j] + h * dk[i]; dr[i] = Mr[i][j] + h * MT[i][j] + hh * P(0.5) * dk[i]; }
             }
             P c[3];
             if (FK == FIELD_UNIFORM) {
@@ -179,13 +189,18 @@ __device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& 
                 for (int i = 0; i < 3; ++i) c[i] = lk * (c[i] + c2[i]);
             }
 #pragma unroll
-            for (int i = 0; i < 3; ++i) dk[st][i] = (j == 4) ? c[i] + S.w[st][i] : c[i];
+            for (int i = 0; i < 3; ++i) {
+                dk[i] = (j == 4) ? c[i] + k[st][i] * ilam : c[i];
+                if (st == 0) { sR[i] = dk[i]; sT[i] = dk[i]; }
+                else if (st < 3) { sR[i] += dk[i]; sT[i] += P(2) * dk[i]; }
+                else sT[i] += dk[i];
+            }
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const P dT1 = MT[i][j];
-            Mr[i][j] = Mr[i][j] + h * dT1 + hh * (P(1) / P(6)) * (dk[0][i] + dk[1][i] + dk[2][i]);
-            MT[i][j] = dT1 + h * (P(1) / P(6)) * (dk[0][i] + P(2) * dk[1][i] + P(2) * dk[2][i] + dk[3][i]);
+            Mr[i][j] = Mr[i][j] + h * dT1 + hh * (P(1) / P(6)) * sR[i];
+            MT[i][j] = dT1 + h * (P(1) / P(6)) * sT[i];
         }
     }
 }
@@ -225,8 +240,10 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
     for (int i = 0; i < 3; ++i) {
 #pragma unroll
         for (int j = 0; j < 5; ++j) { Mr[i][j] = P(0); MT[i][j] = P(0); }
-        Mr[i][0] = P(sa[3 + 3 * i + 0]);
-        Mr[i][1] = P(sa[3 + 3 * i + 1]);
+        if (TangentCols<FK>::J0 == 0) {
+            Mr[i][0] = P(sa[3 + 3 * i + 0]);
+            Mr[i][1] = P(sa[3 + 3 * i + 1]);
+        }
     }
     MT[0][2] = P(-sp * st); MT[1][2] = P(cp * st); MT[2][2] = P(0);
     MT[0][3] = P(cp * ct);  MT[1][3] = P(sp * ct); MT[2][3] = P(-st);
@@ -237,24 +254,35 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
     const P n[3] = {P(nb[0]), P(nb[1]), P(nb[2])};
     const P tol = P(cfg.tol);
     const bool mixed = sizeof(P) < sizeof(double);
+    // position = r0 + rl + dr: rl (FP64) collects the straight-line part h T of
+    // every step, dr the curvature part h^2/6 (k1 + k2 + k3) in precision P;
+    // direction = T0 + dT.  In FP32 the big h T term would cost ~1e-7 relative
+    // over a long step, so only the small curvature increments are FP32.
+    double rl[3] = {0.0, 0.0, 0.0};
     P dr[3] = {P(0), P(0), P(0)}, dT[3] = {P(0), P(0), P(0)};
     double dt = 0.0;
-    P spath = P(0);       // accumulated path length in this gap
     P hmag = P(-1);
     int trials = 0;
     int status = ST_OK;
     Stages<P, FK> S;
     for (;;) {
         P T[3], rabs[3];
+        double Td[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) { T[i] = P(T0[i]) + dT[i]; rabs[i] = P(r0[i]) + dr[i]; }
-        const P nT = n[0] * T[0] + n[1] * T[1] + n[2] * T[2];
-        const P dist = P(d0) - (n[0] * dr[0] + n[1] * dr[1] + n[2] * dr[2]);
-        if (pabs(nT) < P(1e-6)) { status = ST_NO_INTERSECT; break; }
-        const P ltol = mixed ? P(1e-6) * (pabs(spath) + P(10)) : P(cfg.land_tol);
-        if (pabs(dist) < ltol) break;
+        for (int i = 0; i < 3; ++i) {
+            Td[i] = T0[i] + double(dT[i]);
+            T[i] = P(Td[i]);
+            rabs[i] = P(r0[i] + rl[i]) + dr[i];
+        }
+        const double nTd = nb[0] * Td[0] + nb[1] * Td[1] + nb[2] * Td[2];
+        const double distd = d0 - (nb[0] * rl[0] + nb[1] * rl[1] + nb[2] * rl[2])
+                                 - (nb[0] * double(dr[0]) + nb[1] * double(dr[1]) + nb[2] * double(dr[2]));
+        if (fabs(nTd) < 1e-6) { status = ST_NO_INTERSECT; break; }
+        // FP32 curvature increments resolve ~1e-7 mm; the FP64 move below finishes the landing
+        const double ltol = mixed ? 1e-5 : cfg.land_tol;
+        if (fabs(distd) < ltol) break;
         if (trials >= cfg.max_steps) { status = ST_STEP_CAP; break; }
-        const P d = dist / nT;
+        const P d = P(distd / nTd);
         if (hmag < P(0)) hmag = pabs(d);
         const P h = (pabs(d) <= hmag) ? d : (d < P(0) ? -hmag : hmag);
         P k[4][3];
@@ -264,15 +292,16 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
         P fac = P(0.9) * sqrt(sqrt(tol / (err > tiny ? err : tiny)));
         fac = fac < P(0.25) ? P(0.25) : (fac > P(4) ? P(4) : fac);
         if (err <= tol) {
-            rkn_tangent<P, FK>(fl, S, lam, h, Mr, MT);
+            rkn_tangent<P, FK>(fl, S, k, lam, h, Mr, MT);
             Mtl += double(h) * gpd;
+            const double hd = double(h);
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                dr[i] = dr[i] + h * T[i] + h * h * (P(1) / P(6)) * (k[0][i] + k[1][i] + k[2][i]);
+                rl[i] += hd * Td[i];
+                dr[i] = dr[i] + h * h * (P(1) / P(6)) * (k[0][i] + k[1][i] + k[2][i]);
                 dT[i] = dT[i] + h * (P(1) / P(6)) * (k[0][i] + P(2) * k[1][i] + P(2) * k[2][i] + k[3][i]);
             }
-            dt += double(h) * gd;
-            spath += h;
+            dt += hd * gd;
         }
         hmag = pabs(h) * fac;
     }
@@ -283,7 +312,7 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
     // second order in d: r += d T + d^2/2 T', T += d T', t += d dt/ds
     double r[3], T[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { r[i] = r0[i] + double(dr[i]); T[i] = T0[i] + double(dT[i]); }
+    for (int i = 0; i < 3; ++i) { r[i] = r0[i] + rl[i] + double(dr[i]); T[i] = T0[i] + double(dT[i]); }
     double t = x[5] + dt;
     Field<double, FK> f64;
     f64.init(fd);
@@ -302,23 +331,7 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
         t += rem * gd;
     }
     const double nTd = nb[0] * T[0] + nb[1] * T[1] + nb[2] * T[2];
-    // path correction: move the variations back onto the plane along dF/ds
-    double B[3];
-    f64.eval(r, B);
-    double TxB[3];
-    cross(T, B, TxB);
-    double Mrd[3][5], MTd[3][5], Mt[5];
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        const double s = (nb[0] * double(Mr[0][j]) + nb[1] * double(Mr[1][j]) + nb[2] * double(Mr[2][j])) / nTd;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            Mrd[i][j] = double(Mr[i][j]) - T[i] * s;
-            MTd[i][j] = double(MT[i][j]) - lam_d * kKappa * TxB[i] * s;
-        }
-        Mt[j] = (j == 4 ? Mtl : 0.0) - gd * s;
-    }
-    // free -> bound on surface b, and F = J_fb * (corrected D J_bf)
+    // free -> bound on surface b
     const double u[3] = {sb[3 + 0], sb[3 + 3], sb[3 + 6]};
     const double v[3] = {sb[3 + 1], sb[3 + 4], sb[3 + 7]};
     const double dd[3] = {r[0] - sb[0], r[1] - sb[1], r[2] - sb[2]};
@@ -331,14 +344,35 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
     xp[3] = atan2(rho, T[2]);
     xp[4] = lam_d;
     xp[5] = t;
-    const double ip = 1.0 / rho2, ith = 1.0 / (rho * n2), in2 = 1.0 / n2;
+    // F = J_fb * P_corr * (D J_bf), one column at a time: the path correction
+    // moves each variation back onto the plane along dF/ds, then J_fb maps it
+    // to the bound parameters of surface b
+    double B[3], TxB[3];
+    f64.eval(r, B);
+    cross(T, B, TxB);
+    const double lk = lam_d * kKappa;
+    const double inT = 1.0 / nTd, ip = 1.0 / rho2, ith = 1.0 / (rho * n2), in2 = 1.0 / n2;
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
-        F[0 * 5 + j] = u[0] * Mrd[0][j] + u[1] * Mrd[1][j] + u[2] * Mrd[2][j];
-        F[1 * 5 + j] = v[0] * Mrd[0][j] + v[1] * Mrd[1][j] + v[2] * Mrd[2][j];
-        F[2 * 5 + j] = (T[0] * MTd[1][j] - T[1] * MTd[0][j]) * ip;
-        F[3 * 5 + j] = T[2] * (T[0] * MTd[0][j] + T[1] * MTd[1][j]) * ith - rho * MTd[2][j] * in2;
-        F[4 * 5 + j] = Mt[j];
+        // columns below J0 were never propagated: (u, v) of surface a, no direction part
+        const bool fixed = j < TangentCols<FK>::J0;
+        double mr[3], mt[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            mr[i] = fixed ? sa[3 + 3 * i + j] : double(Mr[i][j]);
+            mt[i] = fixed ? 0.0 : double(MT[i][j]);
+        }
+        const double sc = (nb[0] * mr[0] + nb[1] * mr[1] + nb[2] * mr[2]) * inT;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            mr[i] -= T[i] * sc;
+            mt[i] -= lk * TxB[i] * sc;
+        }
+        F[0 * 5 + j] = u[0] * mr[0] + u[1] * mr[1] + u[2] * mr[2];
+        F[1 * 5 + j] = v[0] * mr[0] + v[1] * mr[1] + v[2] * mr[2];
+        F[2 * 5 + j] = (T[0] * mt[1] - T[1] * mt[0]) * ip;
+        F[3 * 5 + j] = T[2] * (T[0] * mt[0] + T[1] * mt[1]) * ith - rho * mt[2] * in2;
+        F[4 * 5 + j] = (j == 4 ? Mtl : 0.0) - gd * sc;
     }
     return ST_OK;
 }
@@ -372,28 +406,26 @@ __device__ inline double fget(const double F[25], int i, int j) {
 }
 
 __device__ inline void transport_cov(const double F[25], const double C[21], double Cp[21]) {
-    double G[6][6];
+    // one row g = (F C)[i, :] at a time, then Cp[i][l] = g . F[l, :] for l >= i
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
+        double g[6];
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
-            if (i == 4) { G[i][m] = C[sy(4, m)]; continue; }
+            if (i == 4) { g[m] = C[sy(4, m)]; continue; }
             double acc = (i == 5) ? C[sy(5, m)] : 0.0;
 #pragma unroll
             for (int j = 0; j < 5; ++j) acc += F[frow(i) * 5 + j] * C[sy(j, m)];
-            G[i][m] = acc;
+            g[m] = acc;
         }
-    }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
 #pragma unroll
         for (int l = i; l < 6; ++l) {
             double acc;
-            if (l == 4) acc = G[i][4];
+            if (l == 4) acc = g[4];
             else {
-                acc = (l == 5) ? G[i][5] : 0.0;
+                acc = (l == 5) ? g[5] : 0.0;
 #pragma unroll
-                for (int m = 0; m < 5; ++m) acc += G[i][m] * F[frow(l) * 5 + m];
+                for (int m = 0; m < 5; ++m) acc += g[m] * F[frow(l) * 5 + m];
             }
             Cp[sy(i, l)] = acc;
         }
@@ -441,79 +473,90 @@ __device__ inline int kalman_update(const double xp[6], const double Cp[21], con
 }
 
 // ---------------------------------------------------------------------------
-// RTS smoother step (Sect. 2) with the stored Jacobian F of the step k -> k+1:
-//   A = Cf F^T Cp1^{-1}          (FP64 Cholesky solve, Sect. 4.2.4)
-//   xs = xf + A (xs1 - xp1),  Cs = Cf + A (Cs1 - Cp1) A^T
-// xs1/Cs1 are overwritten with the result (smoothed state k).
+// FP64 Cholesky factor of an SPD 6x6 (Sect. 4.2.4: the smoother's inverse is
+// done in FP64): L packed with sy(i, j), i >= j; id[j] = 1 / L[j][j].
 // ---------------------------------------------------------------------------
-__device__ inline int rts_step(const double xf[6], const double Cf[21], const double F[25],
-                               const double xp1[6], const double Cp1[21], double xs[6], double Cs[21]) {
-    // D = Cs1 - Cp1 (symmetric), dx = xs1 - xp1
-    double D[21], dx[6];
-#pragma unroll
-    for (int q = 0; q < 21; ++q) D[q] = Cs[q] - Cp1[q];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) dx[i] = xs[i] - xp1[i];
-    dx[2] = wrap_phi(dx[2]);
-    // Cholesky Cp1 = L L^T (lower, packed by rows of L^T = upper of L^T)
-    double L[6][6], id[6];
+__device__ inline bool chol6(const double A[21], double L[21], double id[6]) {
+    bool ok = true;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        double s = Cp1[sy(j, j)];
+        double s = A[sy(j, j)];
 #pragma unroll
-        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
-        if (!(s > 0.0)) return ST_NOT_SPD;
-        const double l = sqrt(s);
-        L[j][j] = l;
+        for (int k = 0; k < j; ++k) s -= L[sy(j, k)] * L[sy(j, k)];
+        ok = ok && (s > 0.0);
+        const double l = sqrt(s > 0.0 ? s : 1.0);
+        L[sy(j, j)] = l;
         id[j] = 1.0 / l;
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {
-            double t = Cp1[sy(i, j)];
+            double t = A[sy(i, j)];
 #pragma unroll
-            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
-            L[i][j] = t * id[j];
+            for (int k = 0; k < j; ++k) t -= L[sy(i, k)] * L[sy(j, k)];
+            L[sy(i, j)] = t * id[j];
         }
     }
-    // B = F Cf (6x6); solve Cp1 X = B -> X = A^T
-    double X[6][6];
+    return ok;
+}
+
+// solve (L L^T) v = b in place
+__device__ inline void chol_solve6(const double L[21], const double id[6], double v[6]) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
+        double s = v[i];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            if (i == 4) { X[i][c] = Cf[sy(4, c)]; continue; }
-            double acc = (i == 5) ? Cf[sy(5, c)] : 0.0;
-#pragma unroll
-            for (int j = 0; j < 5; ++j) acc += F[frow(i) * 5 + j] * Cf[sy(j, c)];
-            X[i][c] = acc;
-        }
+        for (int k = 0; k < i; ++k) s -= L[sy(i, k)] * v[k];
+        v[i] = s * id[i];
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
+    for (int i = 5; i >= 0; --i) {
+        double s = v[i];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            double s = X[i][c];
-#pragma unroll
-            for (int k = 0; k < i; ++k) s -= L[i][k] * X[k][c];
-            X[i][c] = s * id[i];
-        }
-#pragma unroll
-        for (int i = 5; i >= 0; --i) {
-            double s = X[i][c];
-#pragma unroll
-            for (int k = i + 1; k < 6; ++k) s -= L[k][i] * X[k][c];
-            X[i][c] = s * id[i];
-        }
+        for (int k = i + 1; k < 6; ++k) s -= L[sy(k, i)] * v[k];
+        v[i] = s * id[i];
     }
-    // A[i][k] = X[k][i]
+}
+
+// Row c of the RTS smoother gain A = C F^T Cp^{-1} (Sect. 2): with
+// Cp = L L^T, column c of A^T = Cp^{-1} (F C)[:, c].
+__device__ inline void smoother_gain_row(const double F[25], const double C[21], const double L[21],
+                                         const double id[6], int c, double g[6]) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        if (i == 4) { g[i] = C[sy(4, c)]; continue; }
+        double acc = (i == 5) ? C[sy(5, c)] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) acc += F[frow(i) * 5 + j] * C[sy(j, c)];
+        g[i] = acc;
+    }
+    chol_solve6(L, id, g);
+}
+
+// ---------------------------------------------------------------------------
+// RTS smoother step (Sect. 2) with the stored gain A of the step k -> k+1:
+//   xs = xf + A (xs1 - xp1),  Cs = Cf + A (Cs1 - Cp1) A^T
+// xs/Cs hold (xs1, Cs1) on entry and the smoothed state k on exit.
+// ---------------------------------------------------------------------------
+__device__ inline void rts_apply(const double xf[6], const double Cf[21], const double A[36],
+                                 const double xp1[6], const double Cp1[21], double xs[6], double Cs[21]) {
+    double dx[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) dx[i] = xs[i] - xp1[i];
+    dx[2] = wrap_phi(dx[2]);
+#pragma unroll
+    for (int q = 0; q < 21; ++q) Cs[q] -= Cp1[q];        // D = Cs1 - Cp1
+    phase_boundary();
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double acc = xf[i];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) acc += X[k][i] * dx[k];
+        for (int k = 0; k < 6; ++k) acc += A[6 * i + k] * dx[k];
         xs[i] = acc;
     }
     xs[2] = wrap_phi(xs[2]);
-    // Cs = Cf + A D A^T, one row of A D at a time
+    phase_boundary();
+    // Cs = Cf + A D A^T one row of A D at a time; Cs (holding D) is written
+    // into a separate result so D stays intact until every row is done
+    double R[21];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double e[6];
@@ -521,18 +564,19 @@ __device__ inline int rts_step(const double xf[6], const double Cf[21], const do
         for (int m = 0; m < 6; ++m) {
             double acc = 0.0;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) acc += X[k][i] * D[sy(k, m)];
+            for (int k = 0; k < 6; ++k) acc += A[6 * i + k] * Cs[sy(k, m)];
             e[m] = acc;
         }
 #pragma unroll
         for (int j = i; j < 6; ++j) {
             double acc = Cf[sy(i, j)];
 #pragma unroll
-            for (int m = 0; m < 6; ++m) acc += e[m] * X[m][j];
-            Cs[sy(i, j)] = acc;
+            for (int m = 0; m < 6; ++m) acc += e[m] * A[6 * j + m];
+            R[sy(i, j)] = acc;
         }
     }
-    return ST_OK;
+#pragma unroll
+    for (int q = 0; q < 21; ++q) Cs[q] = R[q];
 }
 
 }  // namespace kfm

@@ -2,12 +2,16 @@
 //
 // Forward filter + RTS smoother (Sect. 2; Sect. 4.1), one lane per track:
 //   * the surface table is staged once per workgroup in LDS;
-//   * the forward pass writes, per hit, the filtered state, the transport
-//     Jacobian and the predicted state to a workspace laid out
-//     [hit][component][slot] so a wave's 64 lanes store/load 64 consecutive
-//     doubles (coalesced);
-//   * the backward pass reads them back and writes the smoothed states to the
-//     caller's CSR outputs, and the seed-surface result to tgt_*.
+//   * the forward pass writes, per hit, the predicted state, the filtered
+//     state and the RTS gain of the previous state (computed as soon as the
+//     predicted covariance exists, with the FP64 Cholesky solve) to a
+//     tile-major workspace [tile][hit][component][64 lanes]: a wave's 64
+//     lanes store/load 64 consecutive doubles (coalesced), and every
+//     component sits at a compile-time offset from one per-lane base, so the
+//     addressing costs neither scalar nor vector registers per component;
+//   * the backward pass is then a light streaming pass: it reads them back,
+//     applies the smoother and writes the smoothed states to the caller's CSR
+//     outputs, and the seed-surface result to tgt_*.
 // Schedules: DIRECT (track i on lane i) and SORTED (tracks ordered by hit
 // count, longest first; persistent waves pull 64-track tiles from a queue so
 // that waves carry tracks of equal length).
@@ -23,8 +27,10 @@ using namespace kfm;
 
 namespace {
 
-constexpr int NC = 79;          // workspace doubles per hit: xf 6, Cf 21, F 25, xp 6, Cp 21
-constexpr int OFF_XF = 0, OFF_CF = 6, OFF_F = 27, OFF_XP = 52, OFF_CP = 58;
+// workspace doubles per hit: filtered state xf 6, Cf 21; smoother gain of the
+// previous state A 36 (row-major); predicted state xp 6, Cp 21
+constexpr int NC = 90;
+constexpr int OFF_XF = 0, OFF_CF = 6, OFF_A = 27, OFF_XP = 63, OFF_CP = 69;
 constexpr int TILE = 64;
 
 struct FitArgs {
@@ -33,7 +39,7 @@ struct FitArgs {
     int seed_sid;
     int max_hits;
     int64_t n_hits;
-    int64_t stride;             // workspace slot stride (padded track count)
+    int64_t tile_doubles;       // workspace doubles per 64-track tile = max_hits * NC * 64
     const int32_t* off;
     const int32_t* sid;
     const double* loc;
@@ -64,6 +70,18 @@ struct FitArgs {
 
 __device__ inline bool finite(double v) { return isfinite(v); }
 
+// Store v[0..N) at p, p + H, p + 2H, ...: the running pointer is kept opaque
+// so the compiler adds H per row instead of materialising N scalar offsets.
+template <int N>
+__device__ inline void store_rows(double* p, int64_t H, const double (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        *p = v[i];
+        p += H;
+        __asm__ volatile("" : "+v"(p));
+    }
+}
+
 // Fit the track held by workspace slot `slot` (track index t).
 template <class P, int FK>
 __device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
@@ -74,12 +92,13 @@ __device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t
     if (o < 0 || n < 0 || (int64_t)o + n > H) { status = ST_BAD_INPUT; n = 0; }   // corrupt CSR: touch no hit
     else if (n < 3) status = ST_TOO_FEW;
     else if (n > a.max_hits) status = ST_BAD_INPUT;
-    double x[6], C[21];
+    double x[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) x[i] = a.seed[i * a.n_tracks + t];
-#pragma unroll
-    for (int q = 0; q < 21; ++q) C[q] = a.seed_cov[q * a.n_tracks + t];
     if (status == ST_OK) {
+        double C[21];
+#pragma unroll
+        for (int q = 0; q < 21; ++q) C[q] = a.seed_cov[q * a.n_tracks + t];
         bool ok = true;
 #pragma unroll
         for (int i = 0; i < 6; ++i) ok = ok && finite(x[i]);
@@ -116,8 +135,8 @@ __device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t
     }
     Field<P, FK> fl;
     fl.init(a.field);
-    double* ws = a.ws;
-    const int64_t st = a.stride;
+    // this lane's column of its tile: component c of hit k at wl[(k * NC + c) * TILE]
+    double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
     double chi2 = 0.0;
     // ---- forward filter ----
     int prev = a.seed_sid;
@@ -132,6 +151,7 @@ __device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t
         status = transport<P, FK>(fl, a.field, a.cfg, sa, sb, x, xp, F, &tr);
         if (a.trials) a.trials[o + k] = tr;
         if (status != ST_OK) break;
+        phase_boundary();
         // the previous filtered covariance is not kept live across the
         // propagation: it is re-read from the slot written one step earlier
         double CQ[21];
@@ -139,51 +159,85 @@ __device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t
 #pragma unroll
             for (int q = 0; q < 21; ++q) CQ[q] = a.seed_cov[q * a.n_tracks + t];
         } else {
-            const double* wprev = ws + (int64_t)(k - 1) * NC * st + slot;
+            const double* wprev = wl + (k - 1) * (NC * TILE);
 #pragma unroll
-            for (int q = 0; q < 21; ++q) CQ[q] = wprev[(OFF_CF + q) * st];
+            for (int q = 0; q < 21; ++q) CQ[q] = wprev[(OFF_CF + q) * TILE];
         }
         CQ[sy(2, 2)] += q22;
         CQ[sy(3, 3)] += q33;
+        phase_boundary();
+        double* w = wl + k * (NC * TILE);
+        {
+            double Cp[21];
+            transport_cov(F, CQ, Cp);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) w[(OFF_XP + i) * TILE] = xp[i];
+#pragma unroll
+            for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = Cp[q];
+            phase_boundary();
+            // RTS gain of the previous state, A = C F^T Cp^-1 (C without the noise)
+            double L[21], id[6];
+            const bool spd = chol6(Cp, L, id);
+            CQ[sy(2, 2)] -= q22;
+            CQ[sy(3, 3)] -= q33;
+            phase_boundary();
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                double g[6];
+                smoother_gain_row(F, CQ, L, id, c, g);
+                // g is column c of A^T = row c of A
+#pragma unroll
+                for (int i = 0; i < 6; ++i) w[(OFF_A + 6 * c + i) * TILE] = g[i];
+                phase_boundary();
+            }
+            if (!spd) { status = ST_NOT_SPD; break; }
+        }
+        // the update reads the predicted covariance back (L1/L2 hit) rather
+        // than holding it across the gain solve
         double Cp[21];
-        transport_cov(F, CQ, Cp);
+#pragma unroll
+        for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
         const double m[2] = {a.loc[o + k], a.loc[H + o + k]};
         const double V[3] = {a.cov[o + k], a.cov[H + o + k], a.cov[2 * H + o + k]};
-        double ck;
+        double ck, C[21];
+        phase_boundary();
         status = kalman_update(xp, Cp, m, V, x, C, &ck);
         if (status != ST_OK) break;
+        phase_boundary();
         chi2 += ck;
-        double* w = ws + (int64_t)k * NC * st + slot;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) { w[(OFF_XF + i) * st] = x[i]; w[(OFF_XP + i) * st] = xp[i]; }
+        for (int i = 0; i < 6; ++i) w[(OFF_XF + i) * TILE] = x[i];
 #pragma unroll
-        for (int q = 0; q < 21; ++q) { w[(OFF_CF + q) * st] = C[q]; w[(OFF_CP + q) * st] = Cp[q]; }
-#pragma unroll
-        for (int q = 0; q < 25; ++q) w[(OFF_F + q) * st] = F[q];
+        for (int q = 0; q < 21; ++q) w[(OFF_CF + q) * TILE] = C[q];
         if (a.filt_par) {
-#pragma unroll
-            for (int i = 0; i < 6; ++i) a.filt_par[i * H + o + k] = x[i];
-#pragma unroll
-            for (int q = 0; q < 21; ++q) a.filt_cov[q * H + o + k] = C[q];
+            store_rows(a.filt_par + o + k, H, x);
+            store_rows(a.filt_cov + o + k, H, C);
         }
         prev = s;
     }
     // ---- RTS smoother ----
+    double C[21];
     if (status == ST_OK) {
-        // last hit: smoothed = filtered (x, C in registers)
+        // last hit: smoothed = filtered (re-read, so the covariance is not kept
+        // live in registers across the forward loop)
+        {
+            const double* w = wl + (n - 1) * (NC * TILE);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) a.par[i * H + o + n - 1] = x[i];
+            for (int i = 0; i < 6; ++i) x[i] = w[(OFF_XF + i) * TILE];
 #pragma unroll
-        for (int q = 0; q < 21; ++q) a.pcov[q * H + o + n - 1] = C[q];
+            for (int q = 0; q < 21; ++q) C[q] = w[(OFF_CF + q) * TILE];
+        }
+        store_rows(a.par + o + n - 1, H, x);
+        store_rows(a.pcov + o + n - 1, H, C);
         for (int k = n - 2; k >= -1; --k) {
-            const double* w1 = ws + (int64_t)(k + 1) * NC * st + slot;
-            double xf[6], Cf[21], F[25], xp1[6], Cp1[21];
+            const double* w1 = wl + (k + 1) * (NC * TILE);
+            double xf[6], Cf[21], A[36], xp1[6], Cp1[21];
             if (k >= 0) {
-                const double* w = ws + (int64_t)k * NC * st + slot;
+                const double* w = wl + k * (NC * TILE);
 #pragma unroll
-                for (int i = 0; i < 6; ++i) xf[i] = w[(OFF_XF + i) * st];
+                for (int i = 0; i < 6; ++i) xf[i] = w[(OFF_XF + i) * TILE];
 #pragma unroll
-                for (int q = 0; q < 21; ++q) Cf[q] = w[(OFF_CF + q) * st];
+                for (int q = 0; q < 21; ++q) Cf[q] = w[(OFF_CF + q) * TILE];
             } else {
 #pragma unroll
                 for (int i = 0; i < 6; ++i) xf[i] = a.seed[i * a.n_tracks + t];
@@ -191,18 +245,15 @@ __device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t
                 for (int q = 0; q < 21; ++q) Cf[q] = a.seed_cov[q * a.n_tracks + t];
             }
 #pragma unroll
-            for (int q = 0; q < 25; ++q) F[q] = w1[(OFF_F + q) * st];
+            for (int q = 0; q < 36; ++q) A[q] = w1[(OFF_A + q) * TILE];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) xp1[i] = w1[(OFF_XP + i) * st];
+            for (int i = 0; i < 6; ++i) xp1[i] = w1[(OFF_XP + i) * TILE];
 #pragma unroll
-            for (int q = 0; q < 21; ++q) Cp1[q] = w1[(OFF_CP + q) * st];
-            status = rts_step(xf, Cf, F, xp1, Cp1, x, C);
-            if (status != ST_OK) break;
+            for (int q = 0; q < 21; ++q) Cp1[q] = w1[(OFF_CP + q) * TILE];
+            rts_apply(xf, Cf, A, xp1, Cp1, x, C);
             if (k >= 0) {
-#pragma unroll
-                for (int i = 0; i < 6; ++i) a.par[i * H + o + k] = x[i];
-#pragma unroll
-                for (int q = 0; q < 21; ++q) a.pcov[q * H + o + k] = C[q];
+                store_rows(a.par + o + k, H, x);
+                store_rows(a.pcov + o + k, H, C);
             }
         }
     }
@@ -249,14 +300,15 @@ __device__ inline void stage_surfaces(const FitArgs& a, double* sm) {
     __syncthreads();
 }
 
-// One kernel for both schedules (a launch-uniform flag); OCC is the
-// occupancy target in waves per SIMD, which caps the registers per lane.
-template <class P, int FK, int OCC>
+// SORTED selects the schedule at compile time (one inlined copy of the fit
+// per kernel); OCC is the occupancy target in waves per SIMD, which caps the
+// registers per lane.
+template <class P, int FK, int OCC, bool SORTED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
-k_fit(FitArgs a, int sorted) {
+k_fit(FitArgs a) {
     extern __shared__ double sm[];
     stage_surfaces(a, sm);
-    if (!sorted) {
+    if (!SORTED) {
         const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
         if (i < a.n_tracks) fit_one<P, FK>(a, sm, i, (int)i);
         return;
@@ -286,42 +338,65 @@ __device__ inline int len_bin(const int32_t* off, int t, int max_hits) {
     return (max_hits + 1) - n;      // longest first
 }
 
-__global__ void k_hist(const int32_t* off, int N, int max_hits, int32_t* counts) {
+// Each workgroup builds its histogram in LDS and adds it to the global one
+// with one atomic per non-empty bin (equal lengths would otherwise serialise
+// every track on one address).
+constexpr int NBINS = KF_MAX_HITS + 2;
+
+__global__ void __launch_bounds__(256) k_hist(const int32_t* off, int N, int max_hits, int32_t* counts) {
+    __shared__ int32_t h[NBINS];
+    for (int i = threadIdx.x; i < NBINS; i += blockDim.x) h[i] = 0;
+    __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < N) atomicAdd(&counts[len_bin(off, t, max_hits)], 1);
+    if (t < N) atomicAdd(&h[len_bin(off, t, max_hits)], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < NBINS; i += blockDim.x)
+        if (h[i]) atomicAdd(&counts[i], h[i]);
 }
 
-// exclusive scan of nb <= 1024 bins by one workgroup of 1024 threads
-__global__ void __launch_bounds__(1024) k_scan(int32_t* counts, int nb) {
-    __shared__ int32_t s[1024];
+// exclusive scan of the NBINS (<= 256) bins by one workgroup of 256 threads
+__global__ void __launch_bounds__(256) k_scan(int32_t* counts) {
+    __shared__ int32_t s[256];
     const int i = threadIdx.x;
-    s[i] = i < nb ? counts[i] : 0;
+    const int own = i < NBINS ? counts[i] : 0;
+    s[i] = own;
     __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
+    for (int d = 1; d < 256; d <<= 1) {
         const int v = i >= d ? s[i - d] : 0;
         __syncthreads();
         s[i] += v;
         __syncthreads();
     }
-    if (i < nb) counts[i] = s[i] - (i < nb ? counts[i] : 0);
+    if (i < NBINS) counts[i] = s[i] - own;
 }
 
-__global__ void k_scatter(const int32_t* off, int N, int max_hits, int32_t* pos, int32_t* order) {
+// each workgroup reserves one range per bin, then places its tracks
+__global__ void __launch_bounds__(256) k_scatter(const int32_t* off, int N, int max_hits, int32_t* pos,
+                                                 int32_t* order) {
+    __shared__ int32_t h[NBINS], base[NBINS];
+    for (int i = threadIdx.x; i < NBINS; i += blockDim.x) h[i] = 0;
+    __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = 0, local = 0;
     if (t < N) {
-        const int p = atomicAdd(&pos[len_bin(off, t, max_hits)], 1);
-        order[p] = t;
+        b = len_bin(off, t, max_hits);
+        local = atomicAdd(&h[b], 1);
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NBINS; i += blockDim.x)
+        if (h[i]) base[i] = atomicAdd(&pos[i], h[i]);
+    __syncthreads();
+    if (t < N) order[base[b] + local] = t;
 }
 
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 struct WsLayout {
-    int64_t stride;
-    size_t fit_bytes;     // [max_hits][NC][stride] doubles
-    size_t order_off;     // int32 [stride]
-    size_t counts_off;    // int32 [KF_MAX_HITS + 2] histogram / positions
+    int64_t tile_doubles;
+    size_t fit_bytes;     // [tiles][max_hits][NC][64] doubles
+    size_t order_off;     // int32 [tiles * 64]
+    size_t counts_off;    // int32 [NBINS] histogram / positions
     size_t counter_off;   // int32 tile counter
     size_t total;
 };
@@ -330,12 +405,12 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 WsLayout ws_layout(int64_t n_tracks, int max_hits) {
     WsLayout L;
-    L.stride = (n_tracks + TILE - 1) / TILE * TILE;
-    if (L.stride == 0) L.stride = TILE;
-    L.fit_bytes = (size_t)max_hits * NC * (size_t)L.stride * sizeof(double);
+    const int64_t tiles = n_tracks > 0 ? (n_tracks + TILE - 1) / TILE : 1;
+    L.tile_doubles = (int64_t)max_hits * NC * TILE;
+    L.fit_bytes = (size_t)tiles * L.tile_doubles * sizeof(double);
     L.order_off = align_up(L.fit_bytes, 256);
-    L.counts_off = align_up(L.order_off + (size_t)L.stride * 4, 256);
-    L.counter_off = align_up(L.counts_off + (KF_MAX_HITS + 2) * 4, 256);
+    L.counts_off = align_up(L.order_off + (size_t)tiles * TILE * 4, 256);
+    L.counter_off = align_up(L.counts_off + NBINS * 4, 256);
     L.total = align_up(L.counter_off + 256, 256);
     return L;
 }
@@ -395,8 +470,10 @@ hipError_t launch_fit_occ(const FitArgs& a, int sched, int block, int waves_per_
     } else {
         grid = (int)((a.n_tracks + block - 1) / block);
     }
-    hipLaunchKernelGGL((k_fit<P, FK, OCC>), dim3(grid), dim3(block), shm, stream, a,
-                       sched == KF_SCHED_SORTED ? 1 : 0);
+    if (sched == KF_SCHED_SORTED)
+        hipLaunchKernelGGL((k_fit<P, FK, OCC, true>), dim3(grid), dim3(block), shm, stream, a);
+    else
+        hipLaunchKernelGGL((k_fit<P, FK, OCC, false>), dim3(grid), dim3(block), shm, stream, a);
     return hipGetLastError();
 }
 
@@ -459,7 +536,7 @@ int kf_fit_tracks(const kf_config* cfg, const kf_surfaces* surf, const kf_field*
     a.seed_sid = seeds->surface_id;
     a.max_hits = meas->max_hits;
     a.n_hits = meas->n_hits;
-    a.stride = L.stride;
+    a.tile_doubles = L.tile_doubles;
     a.off = meas->hit_offsets;
     a.sid = meas->surface_id;
     a.loc = meas->loc;
@@ -500,14 +577,14 @@ int kf_fit_tracks(const kf_config* cfg, const kf_surfaces* surf, const kf_field*
 
     hipError_t e = hipSuccess;
     if (sched == KF_SCHED_SORTED) {
-        const int nb = KF_MAX_HITS + 2;
+        const int nb = NBINS;
         int32_t* counts = (int32_t*)(wsb + L.counts_off);
         const int N = a.n_tracks;
         const int tb = 256, tg = (N + tb - 1) / tb;
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(128), 0, stream, counts, nb);
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, a.tile_counter, 1);
         hipLaunchKernelGGL(k_hist, dim3(tg), dim3(tb), 0, stream, a.off, N, a.max_hits, counts);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, counts, nb);
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, stream, counts);
         hipLaunchKernelGGL(k_scatter, dim3(tg), dim3(tb), 0, stream, a.off, N, a.max_hits, counts,
                            (int32_t*)a.order);
         e = hipGetLastError();

@@ -169,7 +169,7 @@ class Fit:
 class Options:
     precision: int = KF_PREC_FP64
     rk_tol: float = 1e-4
-    land_tol: float = 1e-10
+    land_tol: float = 1e-6
     max_steps: int = 1000
     schedule: int = KF_SCHED_AUTO
     block: int = 0
