@@ -126,6 +126,7 @@ typedef struct {
     int32_t block;               /* threads per workgroup (64, 128, 256), 0 = autotuned */
     int32_t waves_per_cu;        /* persistent schedule: resident waves per CU, 0 = autotuned */
     int32_t occupancy;           /* register budget as waves per SIMD (1, 2, 3), 0 = autotuned */
+    int32_t split_smoother;      /* 0: smoother in the same kernel as the filter; 1: separate kernel */
 } kf_config;
 
 typedef struct {
@@ -158,6 +159,32 @@ size_t kf_workspace_bytes(const kf_config *cfg, const kf_measurements *meas, int
 int kf_fit_tracks(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
                   const kf_measurements *meas, const kf_seeds *seeds, const kf_outputs *out,
                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* A captured fit: the whole launch sequence of kf_fit_tracks (length sort +
+ * fit kernels) for one fixed set of arguments and buffers, recorded once into
+ * a HIP graph and replayed by kf_plan_launch.  The arrays the arguments point
+ * to must stay allocated (their contents may change) until kf_plan_destroy.
+ * AUTO settings are resolved at creation.  Launches of one plan must not
+ * overlap (they share the workspace). */
+typedef struct kf_plan kf_plan;
+
+int kf_plan_create(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
+                   const kf_measurements *meas, const kf_seeds *seeds, const kf_outputs *out,
+                   void *workspace, size_t workspace_bytes, kf_plan **plan);
+int kf_plan_launch(kf_plan *plan, void *stream);
+void kf_plan_destroy(kf_plan *plan);
+
+/* Launch-shape autotuner (the paper's grid/block/register studies, Sect. 5.3,
+ * made automatic): times every candidate schedule (direct / length-sorted
+ * persistent), workgroup size, register budget (waves per SIMD), fused or
+ * separate smoother kernel and persistent waves per CU on these very buffers
+ * (outputs are overwritten), synchronising `stream`.  Writes the fastest
+ * setting to *best (and its time per fit to *best_ms if not NULL) and
+ * remembers it: later calls with AUTO (0) settings and the same precision,
+ * field kind, max_hits and track count (to a power of two) use it. */
+int kf_autotune(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
+                const kf_measurements *meas, const kf_seeds *seeds, const kf_outputs *out,
+                void *workspace, size_t workspace_bytes, void *stream, kf_config *best, float *best_ms);
 
 #ifdef __cplusplus
 }

@@ -202,6 +202,7 @@ __device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& 
             Mr[i][j] = Mr[i][j] + h * dT1 + hh * (P(1) / P(6)) * sR[i];
             MT[i][j] = dT1 + h * (P(1) / P(6)) * sT[i];
         }
+        phase_boundary();   // one column's temporaries at a time
     }
 }
 
@@ -288,11 +289,13 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
         P k[4][3];
         const P err = rkn_trial<P, FK>(fl, rabs, T, lam, h, S, k);
         ++trials;
+        phase_boundary();
         const P tiny = P(sizeof(P) < sizeof(double) ? 1e-30 : 1e-300);
         P fac = P(0.9) * sqrt(sqrt(tol / (err > tiny ? err : tiny)));
         fac = fac < P(0.25) ? P(0.25) : (fac > P(4) ? P(4) : fac);
         if (err <= tol) {
             rkn_tangent<P, FK>(fl, S, k, lam, h, Mr, MT);
+            phase_boundary();
             Mtl += double(h) * gpd;
             const double hd = double(h);
 #pragma unroll
@@ -534,17 +537,21 @@ __device__ inline void smoother_gain_row(const double F[25], const double C[21],
 // ---------------------------------------------------------------------------
 // RTS smoother step (Sect. 2) with the stored gain A of the step k -> k+1:
 //   xs = xf + A (xs1 - xp1),  Cs = Cf + A (Cs1 - Cp1) A^T
-// xs/Cs hold (xs1, Cs1) on entry and the smoothed state k on exit.
+// split in three phases so each loads only what it needs:
+//   rts_diff: dx = xs1 - xp1 (phi wrapped), Cs1 -> D = Cs1 - Cp1 in place
+//   rts_mean: xs = xf + A dx
+//   rts_cov:  Cs = Cf + A D A^T  (R holds Cf on entry, the result on exit)
 // ---------------------------------------------------------------------------
-__device__ inline void rts_apply(const double xf[6], const double Cf[21], const double A[36],
-                                 const double xp1[6], const double Cp1[21], double xs[6], double Cs[21]) {
-    double dx[6];
+__device__ inline void rts_diff(const double xs1[6], double CsD[21], const double xp1[6], const double Cp1[21],
+                                double dx[6]) {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) dx[i] = xs[i] - xp1[i];
+    for (int i = 0; i < 6; ++i) dx[i] = xs1[i] - xp1[i];
     dx[2] = wrap_phi(dx[2]);
 #pragma unroll
-    for (int q = 0; q < 21; ++q) Cs[q] -= Cp1[q];        // D = Cs1 - Cp1
-    phase_boundary();
+    for (int q = 0; q < 21; ++q) CsD[q] -= Cp1[q];
+}
+
+__device__ inline void rts_mean(const double xf[6], const double A[36], const double dx[6], double xs[6]) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double acc = xf[i];
@@ -553,30 +560,27 @@ __device__ inline void rts_apply(const double xf[6], const double Cf[21], const 
         xs[i] = acc;
     }
     xs[2] = wrap_phi(xs[2]);
-    phase_boundary();
-    // Cs = Cf + A D A^T one row of A D at a time; Cs (holding D) is written
-    // into a separate result so D stays intact until every row is done
-    double R[21];
+}
+
+__device__ inline void rts_cov(const double A[36], const double D[21], double R[21]) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        double e[6];
+        double e[6];                                     // row i of A D
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
             double acc = 0.0;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) acc += A[6 * i + k] * Cs[sy(k, m)];
+            for (int k = 0; k < 6; ++k) acc += A[6 * i + k] * D[sy(k, m)];
             e[m] = acc;
         }
 #pragma unroll
         for (int j = i; j < 6; ++j) {
-            double acc = Cf[sy(i, j)];
+            double acc = R[sy(i, j)];
 #pragma unroll
             for (int m = 0; m < 6; ++m) acc += e[m] * A[6 * j + m];
             R[sy(i, j)] = acc;
         }
     }
-#pragma unroll
-    for (int q = 0; q < 21; ++q) Cs[q] = R[q];
 }
 
 }  // namespace kfm

@@ -20,6 +20,8 @@
 #include <string.h>
 #include <math.h>
 #include <mutex>
+#include <map>
+#include <limits.h>
 #include "kf_device.hpp"
 #include "kf.h"
 
@@ -64,27 +66,53 @@ struct FitArgs {
     double* filt_cov;
     double* ws;
     const int32_t* order;       // slot -> track (SORTED) or NULL
-    int32_t* tile_counter;      // SORTED queue head
+    int32_t* tile_counter;      // SORTED queue heads: [0] forward pass, [1] backward pass
     int n_tiles;
 };
 
 __device__ inline bool finite(double v) { return isfinite(v); }
 
-// Store v[0..N) at p, p + H, p + 2H, ...: the running pointer is kept opaque
-// so the compiler adds H per row instead of materialising N scalar offsets.
+// Component-major rows: v[i] lives at p + i * stride.  The running pointer
+// is kept opaque so the compiler adds the stride per row at the point of use
+// instead of computing all N per-lane addresses once and keeping them live
+// across the whole fit (27 64-bit addresses would otherwise occupy 54
+// registers for the track's lifetime).
 template <int N>
-__device__ inline void store_rows(double* p, int64_t H, const double (&v)[N]) {
+__device__ inline void store_rows(double* p, int64_t stride, const double (&v)[N]) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         *p = v[i];
-        p += H;
+        p += stride;
         __asm__ volatile("" : "+v"(p));
     }
 }
 
-// Fit the track held by workspace slot `slot` (track index t).
+template <int N>
+__device__ inline void load_rows(const double* p, int64_t stride, double (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        v[i] = *p;
+        p += stride;
+        __asm__ volatile("" : "+v"(p));
+    }
+}
+
+template <int N>
+__device__ inline void fill_rows(double* p, int64_t stride, double val) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        *p = val;
+        p += stride;
+        __asm__ volatile("" : "+v"(p));
+    }
+}
+
+// Forward filter of the track held by workspace slot `slot` (track index t):
+// validation, then per hit propagation, covariance transport, RTS gain of the
+// previous state and the gain-matrix update.  Writes chi2, ndf and status;
+// a failed track gets NaN outputs here (the backward pass skips it).
 template <class P, int FK>
-__device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
+__device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
     const int o = a.off[t];
     int n = a.off[t + 1] - o;
     const int64_t H = a.n_hits;
@@ -92,13 +120,12 @@ __device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t
     if (o < 0 || n < 0 || (int64_t)o + n > H) { status = ST_BAD_INPUT; n = 0; }   // corrupt CSR: touch no hit
     else if (n < 3) status = ST_TOO_FEW;
     else if (n > a.max_hits) status = ST_BAD_INPUT;
+    const int64_t N = a.n_tracks;
     double x[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) x[i] = a.seed[i * a.n_tracks + t];
+    load_rows(a.seed + t, N, x);
     if (status == ST_OK) {
         double C[21];
-#pragma unroll
-        for (int q = 0; q < 21; ++q) C[q] = a.seed_cov[q * a.n_tracks + t];
+        load_rows(a.seed_cov + t, N, C);
         bool ok = true;
 #pragma unroll
         for (int i = 0; i < 6; ++i) ok = ok && finite(x[i]);
@@ -126,10 +153,11 @@ __device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t
         }
         for (int k = 0; k < n && ok; ++k) {
             const int s = a.sid[o + k];
-            const double m0 = a.loc[o + k], m1 = a.loc[H + o + k];
-            const double v0 = a.cov[o + k], v1 = a.cov[H + o + k], v2 = a.cov[2 * H + o + k];
-            ok = (s >= 0 && s < a.n_surf) && finite(m0) && finite(m1) && finite(v0) && finite(v1) && finite(v2) &&
-                 (v0 > 0.0) && (v0 * v2 - v1 * v1 > 0.0);
+            double m[2], V[3];
+            load_rows(a.loc + o + k, H, m);
+            load_rows(a.cov + o + k, H, V);
+            ok = (s >= 0 && s < a.n_surf) && finite(m[0]) && finite(m[1]) && finite(V[0]) && finite(V[1]) &&
+                 finite(V[2]) && (V[0] > 0.0) && (V[0] * V[2] - V[1] * V[1] > 0.0);
         }
         if (!ok) status = ST_BAD_INPUT;
     }
@@ -156,8 +184,7 @@ __device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t
         // propagation: it is re-read from the slot written one step earlier
         double CQ[21];
         if (k == 0) {
-#pragma unroll
-            for (int q = 0; q < 21; ++q) CQ[q] = a.seed_cov[q * a.n_tracks + t];
+            load_rows(a.seed_cov + t, N, CQ);
         } else {
             const double* wprev = wl + (k - 1) * (NC * TILE);
 #pragma unroll
@@ -197,8 +224,9 @@ __device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t
         double Cp[21];
 #pragma unroll
         for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
-        const double m[2] = {a.loc[o + k], a.loc[H + o + k]};
-        const double V[3] = {a.cov[o + k], a.cov[H + o + k], a.cov[2 * H + o + k]};
+        double m[2], V[3];
+        load_rows(a.loc + o + k, H, m);
+        load_rows(a.cov + o + k, H, V);
         double ck, C[21];
         phase_boundary();
         status = kalman_update(xp, Cp, m, V, x, C, &ck);
@@ -215,76 +243,92 @@ __device__ void fit_one(const FitArgs& a, const double* __restrict__ sm, int64_t
         }
         prev = s;
     }
-    // ---- RTS smoother ----
-    double C[21];
     if (status == ST_OK) {
-        // last hit: smoothed = filtered (re-read, so the covariance is not kept
-        // live in registers across the forward loop)
-        {
-            const double* w = wl + (n - 1) * (NC * TILE);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) x[i] = w[(OFF_XF + i) * TILE];
-#pragma unroll
-            for (int q = 0; q < 21; ++q) C[q] = w[(OFF_CF + q) * TILE];
-        }
-        store_rows(a.par + o + n - 1, H, x);
-        store_rows(a.pcov + o + n - 1, H, C);
-        for (int k = n - 2; k >= -1; --k) {
-            const double* w1 = wl + (k + 1) * (NC * TILE);
-            double xf[6], Cf[21], A[36], xp1[6], Cp1[21];
-            if (k >= 0) {
-                const double* w = wl + k * (NC * TILE);
-#pragma unroll
-                for (int i = 0; i < 6; ++i) xf[i] = w[(OFF_XF + i) * TILE];
-#pragma unroll
-                for (int q = 0; q < 21; ++q) Cf[q] = w[(OFF_CF + q) * TILE];
-            } else {
-#pragma unroll
-                for (int i = 0; i < 6; ++i) xf[i] = a.seed[i * a.n_tracks + t];
-#pragma unroll
-                for (int q = 0; q < 21; ++q) Cf[q] = a.seed_cov[q * a.n_tracks + t];
-            }
-#pragma unroll
-            for (int q = 0; q < 36; ++q) A[q] = w1[(OFF_A + q) * TILE];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) xp1[i] = w1[(OFF_XP + i) * TILE];
-#pragma unroll
-            for (int q = 0; q < 21; ++q) Cp1[q] = w1[(OFF_CP + q) * TILE];
-            rts_apply(xf, Cf, A, xp1, Cp1, x, C);
-            if (k >= 0) {
-                store_rows(a.par + o + k, H, x);
-                store_rows(a.pcov + o + k, H, C);
-            }
-        }
-    }
-    if (status == ST_OK) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) a.tgt_par[i * a.n_tracks + t] = x[i];
-#pragma unroll
-        for (int q = 0; q < 21; ++q) a.tgt_cov[q * a.n_tracks + t] = C[q];
         a.chi2[t] = chi2;
     } else {
         const double nan = __longlong_as_double(0x7ff8000000000000LL);
         for (int k = 0; k < n; ++k) {
-#pragma unroll
-            for (int i = 0; i < 6; ++i) a.par[i * H + o + k] = nan;
-#pragma unroll
-            for (int q = 0; q < 21; ++q) a.pcov[q * H + o + k] = nan;
+            fill_rows<6>(a.par + o + k, H, nan);
+            fill_rows<21>(a.pcov + o + k, H, nan);
             if (a.filt_par) {
-#pragma unroll
-                for (int i = 0; i < 6; ++i) a.filt_par[i * H + o + k] = nan;
-#pragma unroll
-                for (int q = 0; q < 21; ++q) a.filt_cov[q * H + o + k] = nan;
+                fill_rows<6>(a.filt_par + o + k, H, nan);
+                fill_rows<21>(a.filt_cov + o + k, H, nan);
             }
         }
-#pragma unroll
-        for (int i = 0; i < 6; ++i) a.tgt_par[i * a.n_tracks + t] = nan;
-#pragma unroll
-        for (int q = 0; q < 21; ++q) a.tgt_cov[q * a.n_tracks + t] = nan;
+        fill_rows<6>(a.tgt_par + t, N, nan);
+        fill_rows<21>(a.tgt_cov + t, N, nan);
         a.chi2[t] = nan;
     }
     a.ndf[t] = 2 * n - (a.bnz ? 5 : 4);
     a.status[t] = (uint8_t)status;
+}
+
+// RTS smoother of one track (Sect. 2), run by a separate streaming kernel
+// after the forward pass: the smoothed state of the last hit is the filtered
+// one; every earlier state, and finally the seed/target state, follows from
+// the stored gain and predicted state of the next hit.
+__device__ void bwd_one(const FitArgs& a, int64_t slot, int t) {
+    if (a.status[t] != ST_OK) return;
+    const int o = a.off[t];
+    const int n = a.off[t + 1] - o;
+    const int64_t H = a.n_hits;
+    const int64_t N = a.n_tracks;
+    const double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
+    double x[6], C[21];
+    {
+        const double* w = wl + (n - 1) * (NC * TILE);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) x[i] = w[(OFF_XF + i) * TILE];
+#pragma unroll
+        for (int q = 0; q < 21; ++q) C[q] = w[(OFF_CF + q) * TILE];
+    }
+    store_rows(a.par + o + n - 1, H, x);
+    store_rows(a.pcov + o + n - 1, H, C);
+    for (int k = n - 2; k >= -1; --k) {
+        const double* w1 = wl + (k + 1) * (NC * TILE);
+        const double* w = wl + k * (NC * TILE);
+        double dx[6];
+        {
+            double xp1[6], Cp1[21];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) xp1[i] = w1[(OFF_XP + i) * TILE];
+#pragma unroll
+            for (int q = 0; q < 21; ++q) Cp1[q] = w1[(OFF_CP + q) * TILE];
+            rts_diff(x, C, xp1, Cp1, dx);                // C now holds D
+        }
+        phase_boundary();
+        double A[36];
+#pragma unroll
+        for (int q = 0; q < 36; ++q) A[q] = w1[(OFF_A + q) * TILE];
+        {
+            double xf[6];
+            if (k >= 0) {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) xf[i] = w[(OFF_XF + i) * TILE];
+            } else {
+                load_rows(a.seed + t, N, xf);
+            }
+            rts_mean(xf, A, dx, x);
+        }
+        phase_boundary();
+        double R[21];
+        if (k >= 0) {
+#pragma unroll
+            for (int q = 0; q < 21; ++q) R[q] = w[(OFF_CF + q) * TILE];
+        } else {
+            load_rows(a.seed_cov + t, N, R);
+        }
+        rts_cov(A, C, R);
+#pragma unroll
+        for (int q = 0; q < 21; ++q) C[q] = R[q];
+        if (k >= 0) {
+            store_rows(a.par + o + k, H, x);
+            store_rows(a.pcov + o + k, H, C);
+        }
+        phase_boundary();
+    }
+    store_rows(a.tgt_par + t, N, x);
+    store_rows(a.tgt_cov + t, N, C);
 }
 
 __device__ inline void stage_surfaces(const FitArgs& a, double* sm) {
@@ -300,27 +344,52 @@ __device__ inline void stage_surfaces(const FitArgs& a, double* sm) {
     __syncthreads();
 }
 
-// SORTED selects the schedule at compile time (one inlined copy of the fit
-// per kernel); OCC is the occupancy target in waves per SIMD, which caps the
-// registers per lane.
-template <class P, int FK, int OCC, bool SORTED>
+// Tile source for both passes: DIRECT maps workgroups to tiles in order;
+// SORTED makes every wave pull tiles (64 tracks of equal length, longest
+// first) from a queue until it is empty.
+template <bool SORTED>
+__device__ inline int next_tile(int32_t* counter, int& iter) {
+    if (!SORTED) return iter++ == 0 ? (int)((blockIdx.x * blockDim.x + threadIdx.x) / TILE) : INT_MAX;
+    int tile = 0;
+    if ((threadIdx.x & (TILE - 1)) == 0) tile = atomicAdd(counter, 1);
+    return __shfl(tile, 0, TILE);
+}
+
+// Filter (+ smoother).  SORTED selects the schedule at compile time; OCC is
+// the occupancy target in waves per SIMD, which caps the registers per lane;
+// FUSED runs the smoother for a track right after its forward pass, while
+// its workspace column is still cache-hot (otherwise k_bwd does it).
+template <class P, int FK, int OCC, bool SORTED, bool FUSED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
-k_fit(FitArgs a) {
+k_fwd(FitArgs a) {
     extern __shared__ double sm[];
     stage_surfaces(a, sm);
-    if (!SORTED) {
-        const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (i < a.n_tracks) fit_one<P, FK>(a, sm, i, (int)i);
-        return;
-    }
     const int lane = threadIdx.x & (TILE - 1);
+    int iter = 0;
     for (;;) {
-        int tile = 0;
-        if (lane == 0) tile = atomicAdd(a.tile_counter, 1);
-        tile = __shfl(tile, 0, TILE);
+        const int tile = next_tile<SORTED>(a.tile_counter, iter);
         if (tile >= a.n_tiles) break;
         const int64_t i = (int64_t)tile * TILE + lane;
-        if (i < a.n_tracks) fit_one<P, FK>(a, sm, i, a.order[i]);
+        if (i < a.n_tracks) {
+            const int t = SORTED ? a.order[i] : (int)i;
+            fwd_one<P, FK>(a, sm, i, t);
+            if (FUSED) bwd_one(a, i, t);
+        }
+    }
+}
+
+// Backward (smoother) pass: a streaming pass with a small live set, run at
+// two waves per SIMD (no spills) so the per-step workspace reads overlap.
+template <bool SORTED>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_bwd(FitArgs a) {
+    const int lane = threadIdx.x & (TILE - 1);
+    int iter = 0;
+    for (;;) {
+        const int tile = next_tile<SORTED>(a.tile_counter + 1, iter);
+        if (tile >= a.n_tiles) break;
+        const int64_t i = (int64_t)tile * TILE + lane;
+        if (i < a.n_tracks) bwd_one(a, i, SORTED ? a.order[i] : (int)i);
     }
 }
 
@@ -439,6 +508,7 @@ int validate(const kf_config* cfg, const kf_surfaces* surf, const kf_field* fiel
     if (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256) return KF_E_VALUE;
     if (cfg->waves_per_cu < 0 || cfg->waves_per_cu > 32) return KF_E_VALUE;
     if (cfg->occupancy < 0 || cfg->occupancy > 3) return KF_E_VALUE;
+    if (cfg->split_smoother < 0 || cfg->split_smoother > 1) return KF_E_VALUE;
     if (!(cfg->rk_tol > 0.0) || !(cfg->land_tol > 0.0) || !(cfg->mass >= 0.0) || cfg->max_steps < 1)
         return KF_E_VALUE;
     if (!isfinite(field->b0[0]) || !isfinite(field->b0[1]) || !isfinite(field->b0[2]) || !isfinite(field->a))
@@ -459,74 +529,46 @@ int validate(const kf_config* cfg, const kf_surfaces* surf, const kf_field* fiel
 }
 
 template <class P, int FK, int OCC>
-hipError_t launch_fit_occ(const FitArgs& a, int sched, int block, int waves_per_cu, hipStream_t stream) {
+hipError_t launch_fit_occ(const FitArgs& a, int sched, int block, int waves_per_cu, bool split,
+                          hipStream_t stream) {
     const size_t shm = (size_t)a.n_surf * SURF_STRIDE * sizeof(double);
-    int grid;
+    const int need = (a.n_tiles * TILE + block - 1) / block;
     if (sched == KF_SCHED_SORTED) {
-        grid = num_cu() * waves_per_cu * TILE / block;
-        const int need = (a.n_tiles * TILE + block - 1) / block;
-        if (grid > need) grid = need;
-        if (grid < 1) grid = 1;
+        int grid = num_cu() * waves_per_cu * TILE / block;
+        grid = grid > need ? need : (grid < 1 ? 1 : grid);
+        if (split) {
+            int gridb = num_cu() * 8 * TILE / block;
+            gridb = gridb > need ? need : (gridb < 1 ? 1 : gridb);
+            hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, false>), dim3(grid), dim3(block), shm, stream, a);
+            hipLaunchKernelGGL((k_bwd<true>), dim3(gridb), dim3(block), 0, stream, a);
+        } else {
+            hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, true>), dim3(grid), dim3(block), shm, stream, a);
+        }
     } else {
-        grid = (int)((a.n_tracks + block - 1) / block);
+        if (split) {
+            hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, false>), dim3(need), dim3(block), shm, stream, a);
+            hipLaunchKernelGGL((k_bwd<false>), dim3(need), dim3(block), 0, stream, a);
+        } else {
+            hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, true>), dim3(need), dim3(block), shm, stream, a);
+        }
     }
-    if (sched == KF_SCHED_SORTED)
-        hipLaunchKernelGGL((k_fit<P, FK, OCC, true>), dim3(grid), dim3(block), shm, stream, a);
-    else
-        hipLaunchKernelGGL((k_fit<P, FK, OCC, false>), dim3(grid), dim3(block), shm, stream, a);
     return hipGetLastError();
 }
 
 template <class P, int FK>
-hipError_t launch_fit(const FitArgs& a, int sched, int block, int waves_per_cu, int occ, hipStream_t stream) {
+hipError_t launch_fit(const FitArgs& a, int sched, int block, int waves_per_cu, int occ, bool split,
+                      hipStream_t stream) {
     switch (occ) {
-        case 1: return launch_fit_occ<P, FK, 1>(a, sched, block, waves_per_cu, stream);
-        case 3: return launch_fit_occ<P, FK, 3>(a, sched, block, waves_per_cu, stream);
-        default: return launch_fit_occ<P, FK, 2>(a, sched, block, waves_per_cu, stream);
+        case 1: return launch_fit_occ<P, FK, 1>(a, sched, block, waves_per_cu, split, stream);
+        case 3: return launch_fit_occ<P, FK, 3>(a, sched, block, waves_per_cu, split, stream);
+        default: return launch_fit_occ<P, FK, 2>(a, sched, block, waves_per_cu, split, stream);
     }
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* kf_version(void) { return "kfmi 0.1 (gfx950, fp64 + mixed)"; }
-
-const char* kf_status_string(int code) {
-    switch (code) {
-        case KF_OK: return "ok";
-        case KF_E_NULL: return "required pointer is NULL";
-        case KF_E_SIZE: return "count negative, too large or inconsistent";
-        case KF_E_ENUM: return "unknown enum value";
-        case KF_E_WS: return "workspace missing or too small";
-        case KF_E_HIP: return "HIP runtime error";
-        case KF_E_VALUE: return "configuration value out of range";
-        case KF_ST_NO_INTERSECT: return "track: no intersection with a surface";
-        case KF_ST_STEP_CAP: return "track: step cap reached";
-        case KF_ST_NOT_SPD: return "track: covariance not positive definite";
-        case KF_ST_BAD_INPUT: return "track: invalid input";
-        case KF_ST_TOO_FEW: return "track: fewer than 3 hits";
-        default: return "unknown code";
-    }
-}
-
-size_t kf_workspace_bytes(const kf_config* cfg, const kf_measurements* meas, int32_t n_surfaces) {
-    (void)cfg;
-    if (!meas || meas->n_tracks < 0 || meas->max_hits < 1 || meas->max_hits > KF_MAX_HITS || n_surfaces < 1)
-        return 0;
-    return ws_layout(meas->n_tracks, meas->max_hits).total;
-}
-
-int kf_fit_tracks(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field,
-                  const kf_measurements* meas, const kf_seeds* seeds, const kf_outputs* out, void* workspace,
-                  size_t workspace_bytes, void* stream_) {
-    int rc = validate(cfg, surf, field, meas, seeds, out);
-    if (rc != KF_OK) return rc;
-    if (meas->n_tracks == 0) return KF_OK;
+// Enqueue one fit with every launch setting resolved (no AUTO fields).
+int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field, const kf_measurements* meas,
+                const kf_seeds* seeds, const kf_outputs* out, void* workspace, hipStream_t stream) {
     const WsLayout L = ws_layout(meas->n_tracks, meas->max_hits);
-    if (!workspace) return KF_E_WS;
-    if (workspace_bytes < L.total) return KF_E_WS;
-    hipStream_t stream = (hipStream_t)stream_;
     char* wsb = (char*)workspace;
 
     FitArgs a;
@@ -570,10 +612,9 @@ int kf_fit_tracks(const kf_config* cfg, const kf_surfaces* surf, const kf_field*
     a.tile_counter = (int32_t*)(wsb + L.counter_off);
     a.n_tiles = (int)((a.n_tracks + TILE - 1) / TILE);
 
-    int sched = cfg->schedule;
-    if (sched == KF_SCHED_AUTO) sched = KF_SCHED_SORTED;
-    int block = cfg->block ? cfg->block : 64;
-    int wpc = cfg->waves_per_cu ? cfg->waves_per_cu : 8;
+    const int sched = cfg->schedule;
+    const int block = cfg->block;
+    const int wpc = cfg->waves_per_cu;
 
     hipError_t e = hipSuccess;
     if (sched == KF_SCHED_SORTED) {
@@ -582,7 +623,7 @@ int kf_fit_tracks(const kf_config* cfg, const kf_surfaces* surf, const kf_field*
         const int N = a.n_tracks;
         const int tb = 256, tg = (N + tb - 1) / tb;
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(128), 0, stream, counts, nb);
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, a.tile_counter, 1);
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, a.tile_counter, 2);
         hipLaunchKernelGGL(k_hist, dim3(tg), dim3(tb), 0, stream, a.off, N, a.max_hits, counts);
         hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, stream, counts);
         hipLaunchKernelGGL(k_scatter, dim3(tg), dim3(tb), 0, stream, a.off, N, a.max_hits, counts,
@@ -591,14 +632,232 @@ int kf_fit_tracks(const kf_config* cfg, const kf_surfaces* surf, const kf_field*
         if (e != hipSuccess) return KF_E_HIP;
     }
     const bool mixed = cfg->precision == KF_PREC_MIXED;
-    const int occ = cfg->occupancy ? cfg->occupancy : 1;
+    const int occ = cfg->occupancy;
+    const bool split = cfg->split_smoother != 0;
     if (field->kind == KF_FIELD_UNIFORM)
-        e = mixed ? launch_fit<float, FIELD_UNIFORM>(a, sched, block, wpc, occ, stream)
-                  : launch_fit<double, FIELD_UNIFORM>(a, sched, block, wpc, occ, stream);
+        e = mixed ? launch_fit<float, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, stream)
+                  : launch_fit<double, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, stream);
     else
-        e = mixed ? launch_fit<float, FIELD_SOLENOID>(a, sched, block, wpc, occ, stream)
-                  : launch_fit<double, FIELD_SOLENOID>(a, sched, block, wpc, occ, stream);
+        e = mixed ? launch_fit<float, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, stream)
+                  : launch_fit<double, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, stream);
     return e == hipSuccess ? KF_OK : KF_E_HIP;
+}
+
+
+// ---- autotuned launch settings ----
+// Key: precision, field kind, max hits per track, track count rounded to a
+// power of two.  Filled by kf_autotune, read when a setting is AUTO (0).
+struct TuneKey {
+    int precision, field_kind, max_hits, log2n;
+    bool operator<(const TuneKey& o) const {
+        if (precision != o.precision) return precision < o.precision;
+        if (field_kind != o.field_kind) return field_kind < o.field_kind;
+        if (max_hits != o.max_hits) return max_hits < o.max_hits;
+        return log2n < o.log2n;
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, kf_config> g_tune;
+
+TuneKey tune_key(const kf_config* cfg, const kf_field* field, const kf_measurements* meas) {
+    int l = 0;
+    while ((1LL << (l + 1)) <= (long long)meas->n_tracks) ++l;
+    return TuneKey{cfg->precision, field->kind, meas->max_hits, l};
+}
+
+// Fill AUTO (0) launch settings from the tuning table, else the defaults
+// (length-sorted persistent schedule, 64-thread groups, one wave per SIMD,
+// 8 resident waves per CU, smoother fused into the filter kernel).
+kf_config resolve(const kf_config* cfg, const kf_field* field, const kf_measurements* meas) {
+    kf_config r = *cfg;
+    kf_config d = r;
+    d.schedule = KF_SCHED_SORTED;
+    d.block = 64;
+    d.occupancy = 1;
+    d.waves_per_cu = 8;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(tune_key(cfg, field, meas));
+        if (it != g_tune.end()) d = it->second;
+    }
+    if (r.schedule == KF_SCHED_AUTO) { r.schedule = d.schedule; r.split_smoother = d.split_smoother; }
+    if (r.block == 0) r.block = d.block;
+    if (r.occupancy == 0) r.occupancy = d.occupancy;
+    if (r.waves_per_cu == 0) r.waves_per_cu = d.waves_per_cu;
+    return r;
+}
+
+int check_ws(const kf_measurements* meas, void* workspace, size_t workspace_bytes) {
+    if (!workspace) return KF_E_WS;
+    if (workspace_bytes < ws_layout(meas->n_tracks, meas->max_hits).total) return KF_E_WS;
+    return KF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kf_version(void) { return "kfmi 0.1 (gfx950, fp64 + mixed)"; }
+
+const char* kf_status_string(int code) {
+    switch (code) {
+        case KF_OK: return "ok";
+        case KF_E_NULL: return "required pointer is NULL";
+        case KF_E_SIZE: return "count negative, too large or inconsistent";
+        case KF_E_ENUM: return "unknown enum value";
+        case KF_E_WS: return "workspace missing or too small";
+        case KF_E_HIP: return "HIP runtime error";
+        case KF_E_VALUE: return "configuration value out of range";
+        case KF_ST_NO_INTERSECT: return "track: no intersection with a surface";
+        case KF_ST_STEP_CAP: return "track: step cap reached";
+        case KF_ST_NOT_SPD: return "track: covariance not positive definite";
+        case KF_ST_BAD_INPUT: return "track: invalid input";
+        case KF_ST_TOO_FEW: return "track: fewer than 3 hits";
+        default: return "unknown code";
+    }
+}
+
+size_t kf_workspace_bytes(const kf_config* cfg, const kf_measurements* meas, int32_t n_surfaces) {
+    (void)cfg;
+    if (!meas || meas->n_tracks < 0 || meas->max_hits < 1 || meas->max_hits > KF_MAX_HITS || n_surfaces < 1)
+        return 0;
+    return ws_layout(meas->n_tracks, meas->max_hits).total;
+}
+
+int kf_fit_tracks(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field,
+                  const kf_measurements* meas, const kf_seeds* seeds, const kf_outputs* out, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+    int rc = validate(cfg, surf, field, meas, seeds, out);
+    if (rc != KF_OK) return rc;
+    if (meas->n_tracks == 0) return KF_OK;
+    rc = check_ws(meas, workspace, workspace_bytes);
+    if (rc != KF_OK) return rc;
+    num_cu();
+    const kf_config r = resolve(cfg, field, meas);
+    return enqueue_fit(&r, surf, field, meas, seeds, out, workspace, (hipStream_t)stream);
+}
+
+struct kf_plan {
+    hipStream_t capture;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int empty;
+};
+
+int kf_plan_create(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field,
+                   const kf_measurements* meas, const kf_seeds* seeds, const kf_outputs* out, void* workspace,
+                   size_t workspace_bytes, kf_plan** plan) {
+    if (!plan) return KF_E_NULL;
+    *plan = nullptr;
+    int rc = validate(cfg, surf, field, meas, seeds, out);
+    if (rc != KF_OK) return rc;
+    kf_plan* p = new kf_plan();
+    p->empty = meas->n_tracks == 0;
+    if (p->empty) { *plan = p; return KF_OK; }
+    rc = check_ws(meas, workspace, workspace_bytes);
+    if (rc != KF_OK) { delete p; return rc; }
+    num_cu();
+    const kf_config r = resolve(cfg, field, meas);
+    if (hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) { delete p; return KF_E_HIP; }
+    if (hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(p->capture);
+        delete p;
+        return KF_E_HIP;
+    }
+    rc = enqueue_fit(&r, surf, field, meas, seeds, out, workspace, p->capture);
+    hipGraph_t g = nullptr;
+    const hipError_t e1 = hipStreamEndCapture(p->capture, &g);
+    if (rc != KF_OK || e1 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(p->capture);
+        delete p;
+        return rc != KF_OK ? rc : KF_E_HIP;
+    }
+    p->graph = g;
+    if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(p->capture);
+        delete p;
+        return KF_E_HIP;
+    }
+    *plan = p;
+    return KF_OK;
+}
+
+int kf_plan_launch(kf_plan* plan, void* stream) {
+    if (!plan) return KF_E_NULL;
+    if (plan->empty) return KF_OK;
+    return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? KF_OK : KF_E_HIP;
+}
+
+void kf_plan_destroy(kf_plan* plan) {
+    if (!plan) return;
+    if (!plan->empty) {
+        (void)hipGraphExecDestroy(plan->exec);
+        (void)hipGraphDestroy(plan->graph);
+        (void)hipStreamDestroy(plan->capture);
+    }
+    delete plan;
+}
+
+int kf_autotune(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field, const kf_measurements* meas,
+                const kf_seeds* seeds, const kf_outputs* out, void* workspace, size_t workspace_bytes,
+                void* stream_, kf_config* best, float* best_ms) {
+    if (!best) return KF_E_NULL;
+    int rc = validate(cfg, surf, field, meas, seeds, out);
+    if (rc != KF_OK) return rc;
+    *best = resolve(cfg, field, meas);
+    if (best_ms) *best_ms = 0.0f;
+    if (meas->n_tracks == 0) return KF_OK;
+    rc = check_ws(meas, workspace, workspace_bytes);
+    if (rc != KF_OK) return rc;
+    num_cu();
+    hipStream_t stream = (hipStream_t)stream_;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return KF_E_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return KF_E_HIP; }
+    static const int scheds[] = {KF_SCHED_DIRECT, KF_SCHED_SORTED};
+    static const int blocks[] = {64, 256};
+    static const int occs[] = {1, 2, 3};
+    static const int splits[] = {0, 1};
+    static const int wpcs[] = {4, 8};
+    float best_t = 1e30f;
+    kf_config win = *best;
+    for (int sc : scheds)
+        for (int bl : blocks)
+            for (int oc : occs)
+                for (int sp : splits)
+                    for (int wp : wpcs) {
+                        if (sc == KF_SCHED_DIRECT && wp != wpcs[0]) continue;   // unused by DIRECT
+                        kf_config c = *cfg;
+                        c.schedule = sc;
+                        c.block = bl;
+                        c.occupancy = oc;
+                        c.split_smoother = sp;
+                        c.waves_per_cu = wp;
+                        rc = enqueue_fit(&c, surf, field, meas, seeds, out, workspace, stream);   // warm-up
+                        if (rc != KF_OK) break;
+                        (void)hipEventRecord(e0, stream);
+                        for (int rep = 0; rep < 3 && rc == KF_OK; ++rep)
+                            rc = enqueue_fit(&c, surf, field, meas, seeds, out, workspace, stream);
+                        (void)hipEventRecord(e1, stream);
+                        if (hipEventSynchronize(e1) != hipSuccess) rc = KF_E_HIP;
+                        if (rc != KF_OK) break;
+                        float ms = 0.0f;
+                        (void)hipEventElapsedTime(&ms, e0, e1);
+                        ms /= 3.0f;
+                        if (ms < best_t) { best_t = ms; win = c; }
+                    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != KF_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(cfg, field, meas)] = win;
+    }
+    *best = win;
+    if (best_ms) *best_ms = best_t;
+    return KF_OK;
 }
 
 }  // extern "C"

@@ -50,7 +50,7 @@ class kf_config(C.Structure):
     _fields_ = [("precision", C.c_int32), ("multiple_scattering", C.c_int32), ("mass", C.c_double),
                 ("rk_tol", C.c_double), ("land_tol", C.c_double), ("max_steps", C.c_int32),
                 ("schedule", C.c_int32), ("block", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("occupancy", C.c_int32)]
+                ("occupancy", C.c_int32), ("split_smoother", C.c_int32)]
 
 
 class kf_outputs(C.Structure):
@@ -60,7 +60,8 @@ class kf_outputs(C.Structure):
 
 
 # every symbol include/kf.h declares
-EXPORTS = ("kf_version", "kf_status_string", "kf_workspace_bytes", "kf_fit_tracks")
+EXPORTS = ("kf_version", "kf_status_string", "kf_workspace_bytes", "kf_fit_tracks", "kf_plan_create",
+           "kf_plan_launch", "kf_plan_destroy", "kf_autotune")
 
 _lib = None
 
@@ -82,6 +83,14 @@ def lib():
         L.kf_workspace_bytes.argtypes = [P, P, C.c_int32]
         L.kf_fit_tracks.restype = C.c_int
         L.kf_fit_tracks.argtypes = [P, P, P, P, P, P, P, C.c_size_t, P]
+        L.kf_plan_create.restype = C.c_int
+        L.kf_plan_create.argtypes = [P, P, P, P, P, P, P, C.c_size_t, C.POINTER(C.c_void_p)]
+        L.kf_plan_launch.restype = C.c_int
+        L.kf_plan_launch.argtypes = [P, P]
+        L.kf_plan_destroy.restype = None
+        L.kf_plan_destroy.argtypes = [P]
+        L.kf_autotune.restype = C.c_int
+        L.kf_autotune.argtypes = [P, P, P, P, P, P, P, C.c_size_t, P, P, C.POINTER(C.c_float)]
         _lib = L
     return _lib
 
@@ -175,6 +184,7 @@ class Options:
     block: int = 0
     waves_per_cu: int = 0
     occupancy: int = 0
+    split_smoother: int = 0
 
 
 class Plan:
@@ -192,7 +202,8 @@ class Plan:
             max_hits = int((b.hit_offsets[1:] - b.hit_offsets[:-1]).max().item()) if N else 1
         max_hits = max(1, min(max_hits, KF_MAX_HITS))
         self.cfg = kf_config(opt.precision, int(b.multiple_scattering), b.mass, opt.rk_tol, opt.land_tol,
-                             opt.max_steps, opt.schedule, opt.block, opt.waves_per_cu, opt.occupancy)
+                             opt.max_steps, opt.schedule, opt.block, opt.waves_per_cu, opt.occupancy,
+                             opt.split_smoother)
         self.surf = kf_surfaces(b.center.shape[1], _ptr(b.center), _ptr(b.rot), _ptr(b.x_over_X0))
         self.field = kf_field(b.field_kind, (C.c_double * 3)(*b.b0), b.field_a)
         self.meas = kf_measurements(N, max_hits, H, _ptr(b.hit_offsets), _ptr(b.surface_id), _ptr(b.loc),
@@ -217,12 +228,58 @@ class Plan:
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.ws_bytes = nbytes
 
+        self.graph = None
+
+    def _args(self):
+        return (C.byref(self.cfg), C.byref(self.surf), C.byref(self.field), C.byref(self.meas),
+                C.byref(self.seeds), C.byref(self.outs), _ptr(self.ws), self.ws_bytes)
+
+    def capture(self) -> "Plan":
+        """Record the whole fit once into a HIP graph (kf_plan_create); run()
+        then replays it with one launch."""
+        if self.graph is None:
+            h = C.c_void_p()
+            rc = lib().kf_plan_create(*self._args(), C.byref(h))
+            if rc != KF_OK:
+                raise KFError(rc)
+            self.graph = h
+        return self
+
+    def autotune(self, stream=None) -> tuple:
+        """Time every launch shape on this batch (kf_autotune); the winner
+        becomes this plan's configuration.  Returns (Options, ms per fit)."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.batch.loc.device)
+        best = kf_config()
+        ms = C.c_float()
+        rc = lib().kf_autotune(*self._args(), C.c_void_p(stream.cuda_stream), C.byref(best), C.byref(ms))
+        if rc != KF_OK:
+            raise KFError(rc)
+        self.cfg = best
+        self.release()
+        o = Options(best.precision, best.rk_tol, best.land_tol, best.max_steps, best.schedule, best.block,
+                    best.waves_per_cu, best.occupancy, best.split_smoother)
+        return o, ms.value
+
+    def release(self):
+        if self.graph is not None:
+            lib().kf_plan_destroy(self.graph)
+            self.graph = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
     def run(self, stream=None) -> Fit:
         if stream is None:
             stream = torch.cuda.current_stream(self.batch.loc.device)
-        rc = lib().kf_fit_tracks(C.byref(self.cfg), C.byref(self.surf), C.byref(self.field), C.byref(self.meas),
-                                 C.byref(self.seeds), C.byref(self.outs), _ptr(self.ws), self.ws_bytes,
-                                 C.c_void_p(stream.cuda_stream))
+        s = C.c_void_p(stream.cuda_stream)
+        if self.graph is not None:
+            rc = lib().kf_plan_launch(self.graph, s)
+        else:
+            rc = lib().kf_fit_tracks(*self._args(), s)
         if rc != KF_OK:
             raise KFError(rc)
         return self.out

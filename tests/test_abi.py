@@ -40,7 +40,7 @@ def test_status_strings(kf):
 
 def _args(kf, N=10, H=100, max_hits=10, S=11):
     fake = C.c_void_p(0x1000)     # never dereferenced on the host
-    cfg = kf.kf_config(0, 0, 0.1056583755, 1e-4, 1e-10, 1000, 0, 0, 0, 0)
+    cfg = kf.kf_config(0, 0, 0.1056583755, 1e-4, 1e-6, 1000, 0, 0, 0, 0, 0)
     surf = kf.kf_surfaces(S, fake, fake, fake)
     fld = kf.kf_field(0, (C.c_double * 3)(0, 0, 2), 0.0)
     meas = kf.kf_measurements(N, max_hits, H, fake, fake, fake, fake)
@@ -85,6 +85,9 @@ def test_argument_validation(kf):
     cfg.occupancy = 9
     assert _call(kf, *a) == kf.KF_E_VALUE
     cfg.occupancy = 0
+    cfg.split_smoother = 2
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.split_smoother = 0
     fld.b0[2] = float("nan")
     assert _call(kf, *a) == kf.KF_E_VALUE
     fld.b0[2] = 2.0
@@ -123,7 +126,7 @@ def test_argument_validation(kf):
 
 def test_workspace_size_grows_with_tracks_and_hits(kf):
     L = kf.lib()
-    cfg = kf.kf_config(0, 0, 0.1, 1e-4, 1e-10, 1000, 0, 0, 0, 0)
+    cfg = kf.kf_config(0, 0, 0.1, 1e-4, 1e-6, 1000, 0, 0, 0, 0, 0)
     sizes = []
     for N, mh in [(1, 10), (64, 10), (65, 10), (1000, 30)]:
         m = kf.kf_measurements(N, mh, N * mh, None, None, None, None)

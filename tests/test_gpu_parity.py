@@ -51,11 +51,12 @@ def _announce(msg):
     print(msg, flush=True)
 
 
-@pytest.mark.parametrize("schedule,block,occ", [(1, 64, 1), (2, 64, 1), (1, 256, 1), (2, 128, 2), (1, 64, 3)])
-def test_c1_fp64_all_launch_shapes(kf, schedule, block, occ):
-    _announce(f"C1 fp64 schedule={schedule} block={block} occ={occ}")
+@pytest.mark.parametrize("schedule,block,occ,split", [(1, 64, 1, 0), (2, 64, 1, 0), (1, 256, 1, 1), (2, 128, 2, 1),
+                                                      (1, 64, 3, 0), (2, 256, 3, 1)])
+def test_c1_fp64_all_launch_shapes(kf, schedule, block, occ, split):
+    _announce(f"C1 fp64 schedule={schedule} block={block} occ={occ} split={split}")
     ev = synth.make_config(1)
-    out = _fit(kf, ev, schedule=schedule, block=block, occupancy=occ)
+    out = _fit(kf, ev, schedule=schedule, block=block, occupancy=occ, split_smoother=split)
     compare(out, _ref(ev), label="C1")
 
 
@@ -185,3 +186,43 @@ def test_run_to_run_bitwise_determinism(kf):
     b = _fit(kf, ev)
     for name in ("par", "cov", "tgt_par", "tgt_cov", "chi2"):
         assert np.array_equal(getattr(a, name).cpu().numpy(), getattr(b, name).cpu().numpy(), equal_nan=True), name
+
+
+def test_graph_plan_replays_match_eager(kf):
+    """kf_plan_create records the whole fit (length sort + kernels) into a HIP
+    graph.  Replay it several times with eager work and synchronisations in
+    between; every replay must equal the eager fit bit for bit."""
+    _announce("graph plan replays")
+    import torch
+    ev = synth.make_config(3, 5000)
+    b = kf.Batch.from_event(ev)
+    eager = kf.Plan(b, kf.Options(), extras=False).run()
+    torch.cuda.synchronize()
+    ref = {n: getattr(eager, n).clone() for n in ("par", "cov", "tgt_par", "tgt_cov", "chi2", "status")}
+    p = kf.Plan(b, kf.Options(), extras=False).capture()
+    for rep in range(4):
+        for n in ("par", "tgt_par", "chi2"):
+            getattr(p.out, n).fill_(-1.0)                   # eager work between replays
+        torch.cuda.synchronize()
+        p.run()
+        torch.cuda.synchronize()
+        for n, v in ref.items():
+            assert torch.equal(getattr(p.out, n), v) or (n != "status" and torch.allclose(
+                getattr(p.out, n), v, rtol=0, atol=0, equal_nan=True)), (rep, n)
+    p.release()
+
+
+def test_autotuner_picks_a_valid_shape(kf):
+    _announce("autotune")
+    import torch
+    ev = synth.make_config(3, 20000)
+    b = kf.Batch.from_event(ev)
+    p = kf.Plan(b, kf.Options(), extras=True)
+    opt, ms = p.autotune()
+    print(f"  autotune C3 20k: {opt} {ms:.3f} ms", flush=True)
+    assert ms > 0 and opt.schedule in (1, 2) and opt.block in (64, 256) and opt.occupancy in (1, 2, 3)
+    out = p.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    idx = np.unique(rng.choice(ev.n_tracks, 300, replace=False))
+    compare(_sampled(out, ev, idx), _ref(ev.subset(idx)), label="autotuned")
