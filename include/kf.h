@@ -89,6 +89,10 @@ typedef struct {
     const double *center;      /* [3][S] */
     const double *rot;         /* [9][S] row-major 3x3, columns u, v, n (orthonormal) */
     const double *x_over_X0;   /* [S] material thickness in radiation lengths (0 = none) */
+    const double *align;       /* [6][S] optional (NULL = none): alignment correction per surface,
+                                  (dx, dy, dz, alpha, beta, gamma); the fit uses the surface with
+                                  centre c + (dx, dy, dz) and rotation R Rx(alpha) Ry(beta) Rz(gamma)
+                                  (turned about its own u, v, n axes) */
 } kf_surfaces;
 
 typedef struct {
@@ -149,8 +153,8 @@ const char *kf_version(void);
 const char *kf_status_string(int code);
 
 /* Bytes of workspace kf_fit_tracks needs for these sizes (0 on bad arguments).
- * Grows as n_tracks * max_hits * 79 doubles (filtered state, predicted state,
- * transport Jacobian per hit) plus small per-track and per-tile tables. */
+ * Grows as n_tracks * max_hits * 90 doubles (filtered and predicted state and
+ * covariance, smoother gain per hit) plus small per-track and per-tile tables. */
 size_t kf_workspace_bytes(const kf_config *cfg, const kf_measurements *meas, int32_t n_surfaces);
 
 /* Filter + RTS smoother for every track (Sect. 2; Sect. 4.1; Sect. 4.3).
@@ -185,6 +189,50 @@ void kf_plan_destroy(kf_plan *plan);
 int kf_autotune(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
                 const kf_measurements *meas, const kf_seeds *seeds, const kf_outputs *out,
                 void *workspace, size_t workspace_bytes, void *stream, kf_config *best, float *best_ms);
+
+/* ---- adjoint (vector-Jacobian product) of the fit ----
+ *
+ * For the scalar L = sum_t g_chi2[t] chi2_t + sum_hits g_par . (smoothed
+ * parameters) + sum_t g_tgt . (fitted parameters on the target surface),
+ * kf_fit_tracks_vjp returns dL/d(measured loc0, loc1) of every hit, dL/d(the
+ * alignment correction) of every surface and, optionally, dL/d(starting
+ * parameters) of every track.  It is the reverse of the whole fit: the RTS
+ * smoother (Sect. 2), the gain-matrix update, the covariance transport and the
+ * adaptive RKN propagation with its transport Jacobian (Sect. 4.1), including
+ * the dependence of that Jacobian on the state.  The forward fit is recomputed
+ * per track (nothing from an earlier kf_fit_tracks call is reused); the
+ * propagation of each gap is recomputed again, in forward-mode dual numbers,
+ * for the start state and the alignment of both surfaces, and contracted with
+ * the reverse-mode adjoints of the Kalman and smoother algebra.  Every step of
+ * the adjoint runs in FP64 whatever cfg->precision says.  The alignment
+ * gradient of a surface sums over all tracks in a fixed order: the result is
+ * bitwise reproducible.  A track whose recomputed fit fails contributes
+ * nothing to the alignment gradient and gets NaN in its meas and seed rows. */
+typedef struct {
+    const double *chi2;        /* [N] dL/dchi2 per track, or NULL (zero) */
+    const double *par;         /* [6][H] dL/d(smoothed parameters) per hit, or NULL (zero) */
+    const double *tgt_par;     /* [6][N] dL/d(fitted target parameters), or NULL (zero) */
+} kf_cotangents;
+
+typedef struct {
+    double *meas;              /* [2][H] dL/d(loc0, loc1) per hit (required if H > 0) */
+    double *align;             /* [6][S] dL/d(dx, dy, dz, alpha, beta, gamma) per surface at the
+                                  surfaces' alignment (kf_surfaces.align, zero if NULL), or NULL */
+    double *seed;              /* [6][N] dL/d(starting parameters), or NULL */
+    uint8_t *status;           /* [N] status of the recomputed fit (KF_ST_*), or NULL */
+} kf_gradients;
+
+/* Workspace bytes for kf_fit_tracks_vjp (0 on bad arguments): n_tracks *
+ * max_hits * 87 doubles of per-hit state, 6 doubles per hit and per track of
+ * alignment contributions, and the reduction's partial sums. */
+size_t kf_vjp_workspace_bytes(const kf_config *cfg, const kf_measurements *meas, int32_t n_surfaces);
+
+/* Enqueue the adjoint.  Arguments as kf_fit_tracks; cfg->schedule and
+ * cfg->block select the launch (AUTO: length-sorted persistent schedule).
+ * Returns KF_OK or a negative KF_E_* code. */
+int kf_fit_tracks_vjp(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
+                      const kf_measurements *meas, const kf_seeds *seeds, const kf_cotangents *cot,
+                      const kf_gradients *grad, void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -49,7 +49,7 @@ def lib():
         L = C.CDLL(LIB)
         P = C.c_void_p
         i, d = C.c_int, C.c_double
-        fit_args = [i, P, P, P, P, i, P, P, P, i, P, d, P, P, i, i, d, d, d, i]
+        fit_args = [i, P, P, P, P, i, P, P, P, P, i, P, d, P, P, i, i, d, d, d, i]
         L.kfo_fit.argtypes = fit_args + [P] * 12 + [i]
         L.kfo_fit.restype = i
         L.kfo_fit_vjp.argtypes = fit_args + [P] * 6 + [i]
@@ -101,19 +101,21 @@ class _Args:
     """Common input marshalling for kfo_fit / kfo_fit_vjp / kfo_count_ops."""
 
     def __init__(self, ev, detector=None, ms=None, mass=None, tol=DEFAULT_TOL, land_tol=DEFAULT_LAND_TOL,
-                 max_steps=DEFAULT_MAX_STEPS, loc=None, seed_par=None):
+                 max_steps=DEFAULT_MAX_STEPS, loc=None, seed_par=None, align=None):
         det = detector if detector is not None else ev.detector
         self.keep = dict(
             off=_i32(ev.hit_offsets), sid=_i32(ev.surface_id), loc=_f64(ev.loc if loc is None else loc),
             cov=_f64(ev.cov), center=_f64(det.center), rot=_f64(det.rot), x0=_f64(det.x_over_X0),
             b0=_f64(ev.field.b0), seed=_f64(ev.seed_par if seed_par is None else seed_par),
-            seed_cov=_f64(ev.seed_cov))
+            seed_cov=_f64(ev.seed_cov), align=None if align is None else _f64(align))
         k = self.keep
         self.N = ev.n_tracks
         self.H = ev.n_hits
         self.S = det.center.shape[1]
+        if k["align"] is not None and k["align"].shape != (6, self.S):
+            raise ValueError("align must have shape (6, S)")
         self.args = [self.N, _p(k["off"]), _p(k["sid"]), _p(k["loc"]), _p(k["cov"]), self.S, _p(k["center"]),
-                     _p(k["rot"]), _p(k["x0"]), int(ev.field.kind), _p(k["b0"]), float(ev.field.a),
+                     _p(k["rot"]), _p(k["x0"]), _p(k["align"]), int(ev.field.kind), _p(k["b0"]), float(ev.field.a),
                      _p(k["seed"]), _p(k["seed_cov"]), int(ev.seed_surface),
                      int(ev.multiple_scattering if ms is None else ms), float(ev.mass if mass is None else mass),
                      float(tol), float(land_tol), int(max_steps)]
@@ -136,7 +138,11 @@ def fit(ev, n_threads: int = 0, extras: bool = False, **kw) -> FitResult:
 
 
 def fit_vjp(ev, g_chi2, g_par=None, g_tgt=None, n_threads: int = 0, **kw):
-    """Exact VJP (forward-mode duals) -> (g_meas (2,H), g_align (6,S), g_seed (6,N))."""
+    """Exact VJP (forward-mode duals) -> (g_meas (2,H), g_align (6,S), g_seed (6,N)).
+
+    g_align is the derivative with respect to each surface's alignment
+    correction (dx, dy, dz, alpha, beta, gamma) at its given value (`align`
+    keyword, zero if absent)."""
     a = _Args(ev, **kw)
     g_chi2 = _f64(g_chi2)
     g_par = None if g_par is None else _f64(g_par)

@@ -654,22 +654,58 @@ int fit_track(const FieldDef& f, const Cfg& cfg, const Surf<S>* surf, int n_surf
     return out.status = ST_OK;
 }
 
+// alignment a = (dx, dy, dz, alpha, beta, gamma): c <- c + d, R <- R Rx(alpha) Ry(beta) Rz(gamma)
+template <class S>
+void aligned_surface(const Surf<double>& s0, const S a[6], Surf<S>& o) {
+    for (int i = 0; i < 3; ++i) o.c[i] = s0.c[i] + a[i];
+    S ca = cos(a[3]), sa = sin(a[3]), cb = cos(a[4]), sb = sin(a[4]), cg = cos(a[5]), sg = sin(a[5]);
+    S Rx[3][3] = {{1.0, 0.0, 0.0}, {0.0, ca, -sa}, {0.0, sa, ca}};
+    S Ry[3][3] = {{cb, 0.0, sb}, {0.0, 1.0, 0.0}, {-sb, 0.0, cb}};
+    S Rz[3][3] = {{cg, -sg, 0.0}, {sg, cg, 0.0}, {0.0, 0.0, 1.0}};
+    S R0[3][3], T1[3][3], T2[3][3], R[3][3];
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) R0[i][j] = s0.R[i][j];
+    matmul(R0, Rx, T1);
+    matmul(T1, Ry, T2);
+    matmul(T2, Rz, R);
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) o.R[i][j] = R[i][j];
+    o.x0 = s0.x0;
+}
+
+
 // ---------------------------------------------------------------------------
 // glue: SoA component-major arrays <-> one track
 // ---------------------------------------------------------------------------
 struct Inputs {
     int n_tracks; const int32_t* off; const int32_t* sid; const double* loc; const double* cov; int64_t H;
     int n_surf; const double* center; const double* rot; const double* x0;
+    const double* align;   // [6][S] alignment corrections or NULL
     FieldDef field; const double* seed; const double* seed_cov; int seed_sid;
     Cfg cfg;
 };
 
-inline Surf<double> surf_d(const Inputs& in, int s) {
+// nominal surface s (before any alignment correction)
+inline Surf<double> surf_nominal(const Inputs& in, int s) {
     Surf<double> o;
     for (int i = 0; i < 3; ++i) o.c[i] = in.center[i * in.n_surf + s];
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) o.R[i][j] = in.rot[(3 * i + j) * in.n_surf + s];
     o.x0 = in.x0[s];
     return o;
+}
+
+// alignment correction of surface s (zero without an alignment input)
+inline void align_of(const Inputs& in, int s, double a[6]) {
+    for (int c = 0; c < 6; ++c) a[c] = in.align ? in.align[c * in.n_surf + s] : 0.0;
+}
+
+// surface s as fitted: the nominal one with its alignment correction applied
+inline Surf<double> surf_d(const Inputs& in, int s) {
+    Surf<double> o = surf_nominal(in, s);
+    if (!in.align) return o;
+    double a[6];
+    align_of(in, s, a);
+    Surf<double> r;
+    aligned_surface(o, a, r);
+    return r;
 }
 
 inline bool field_nonzero(const FieldDef& f) {
@@ -682,13 +718,13 @@ using namespace kfo;
 
 static Inputs make_inputs(int n_tracks, const int32_t* off, const int32_t* sid, const double* loc,
                           const double* cov, int n_surf, const double* center, const double* rot,
-                          const double* x0, int field_kind, const double* b0, double field_a,
-                          const double* seed, const double* seed_cov, int seed_sid, int ms, double mass,
-                          double tol, double land_tol, int max_steps) {
+                          const double* x0, const double* align, int field_kind, const double* b0,
+                          double field_a, const double* seed, const double* seed_cov, int seed_sid, int ms,
+                          double mass, double tol, double land_tol, int max_steps) {
     Inputs in;
     in.n_tracks = n_tracks; in.off = off; in.sid = sid; in.loc = loc; in.cov = cov;
     in.H = off ? off[n_tracks] : 0;
-    in.n_surf = n_surf; in.center = center; in.rot = rot; in.x0 = x0;
+    in.n_surf = n_surf; in.center = center; in.rot = rot; in.x0 = x0; in.align = align;
     in.field.kind = field_kind;
     for (int i = 0; i < 3; ++i) in.field.b0[i] = b0[i];
     in.field.a = field_a;
@@ -707,14 +743,14 @@ const char* kfo_version() { return "kf-oracle fp64 1"; }
 // Full fit of every track.  Arrays are component-major ([component][item]).
 // Optional outputs may be NULL.  Returns 0.
 int kfo_fit(int n_tracks, const int32_t* off, const int32_t* sid, const double* loc, const double* cov,
-            int n_surf, const double* center, const double* rot, const double* x0,
+            int n_surf, const double* center, const double* rot, const double* x0, const double* align,
             int field_kind, const double* b0, double field_a,
             const double* seed, const double* seed_cov, int seed_sid,
             int ms, double mass, double tol, double land_tol, int max_steps,
             double* par, double* pcov, double* tgt_par, double* tgt_cov, double* chi2, int32_t* ndf,
             uint8_t* status, double* filt_par, double* filt_cov, double* pred_par, double* pred_cov,
             int32_t* trials, int n_threads) {
-    Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, field_kind, b0, field_a,
+    Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, align, field_kind, b0, field_a,
                             seed, seed_cov, seed_sid, ms, mass, tol, land_tol, max_steps);
     std::vector<Surf<double>> surf(n_surf);
     for (int s = 0; s < n_surf; ++s) surf[s] = surf_d(in, s);
@@ -765,7 +801,7 @@ int kfo_transport(int n_surf, const double* center, const double* rot, const dou
                   double land_tol, int max_steps, int sa, int sb, const double* x, double* xo,
                   double* F, int32_t* trials) {
     double dummy = 0;
-    Inputs in = make_inputs(0, nullptr, nullptr, nullptr, nullptr, n_surf, center, rot, x0, field_kind, b0,
+    Inputs in = make_inputs(0, nullptr, nullptr, nullptr, nullptr, n_surf, center, rot, x0, nullptr, field_kind, b0,
                             field_a, nullptr, nullptr, 0, 0, mass, tol, land_tol, max_steps);
     (void)dummy;
     Surf<double> A = surf_d(in, sa), B = surf_d(in, sb);
@@ -852,44 +888,31 @@ namespace kfo {
 static const int ND = 8;   // directions per dual pass
 using D8 = Dual<ND>;
 
-// alignment a = (dx, dy, dz, alpha, beta, gamma): c <- c + d, R <- R Rx(alpha) Ry(beta) Rz(gamma)
-template <class S>
-void aligned_surface(const Surf<double>& s0, const S a[6], Surf<S>& o) {
-    for (int i = 0; i < 3; ++i) o.c[i] = s0.c[i] + a[i];
-    S ca = cos(a[3]), sa = sin(a[3]), cb = cos(a[4]), sb = sin(a[4]), cg = cos(a[5]), sg = sin(a[5]);
-    S Rx[3][3] = {{1.0, 0.0, 0.0}, {0.0, ca, -sa}, {0.0, sa, ca}};
-    S Ry[3][3] = {{cb, 0.0, sb}, {0.0, 1.0, 0.0}, {-sb, 0.0, cb}};
-    S Rz[3][3] = {{cg, -sg, 0.0}, {sg, cg, 0.0}, {0.0, 0.0, 1.0}};
-    S R0[3][3], T1[3][3], T2[3][3], R[3][3];
-    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) R0[i][j] = s0.R[i][j];
-    matmul(R0, Rx, T1);
-    matmul(T1, Ry, T2);
-    matmul(T2, Rz, R);
-    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) o.R[i][j] = R[i][j];
-    o.x0 = s0.x0;
-}
-
 }  // namespace kfo
 
 extern "C" {
 
 // Vector-Jacobian product of L = sum_t g_chi2[t] chi2_t + sum_hits g_par . smoothed
 //                                + sum_t g_tgt . target
-// with respect to the measurements (g_meas [2][H]), the alignment of every
-// surface at zero offset (g_align [6][S]) and the seed parameters (g_seed [6][N]).
+// with respect to the measurements (g_meas [2][H]), the alignment correction
+// (dx, dy, dz, alpha, beta, gamma) of every surface at its given value (align,
+// zero if NULL) (g_align [6][S]) and the seed parameters (g_seed [6][N]).
 // Each entry is an exact directional derivative (Dual numbers) of the fit.
 // g_par, g_tgt, g_seed may be NULL.  Tracks whose fit fails contribute nothing.
 int kfo_fit_vjp(int n_tracks, const int32_t* off, const int32_t* sid, const double* loc, const double* cov,
-                int n_surf, const double* center, const double* rot, const double* x0,
+                int n_surf, const double* center, const double* rot, const double* x0, const double* align,
                 int field_kind, const double* b0, double field_a,
                 const double* seed, const double* seed_cov, int seed_sid,
                 int ms, double mass, double tol, double land_tol, int max_steps,
                 const double* g_chi2, const double* g_par, const double* g_tgt,
                 double* g_meas, double* g_align, double* g_seed, int n_threads) {
-    Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, field_kind, b0, field_a,
+    Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, align, field_kind, b0, field_a,
                             seed, seed_cov, seed_sid, ms, mass, tol, land_tol, max_steps);
+    // derivatives are taken with respect to the alignment correction itself:
+    // every pass rebuilds each surface from its nominal placement
     std::vector<Surf<double>> surf(n_surf);
-    for (int s = 0; s < n_surf; ++s) surf[s] = surf_d(in, s);
+    std::vector<double> a0(6 * n_surf);
+    for (int s = 0; s < n_surf; ++s) { surf[s] = surf_nominal(in, s); align_of(in, s, &a0[6 * s]); }
     const int64_t H = in.H;
     const int N = n_tracks;
     for (int i = 0; i < 6 * n_surf; ++i) g_align[i] = 0.0;
@@ -922,6 +945,7 @@ int kfo_fit_vjp(int n_tracks, const int32_t* off, const int32_t* sid, const doub
                 D8 sd[6];
                 for (int i = 0; i < 6; ++i) sd[i] = seed[i * N + t];
                 std::vector<D8> al(6 * n_surf);
+                for (int i = 0; i < 6 * n_surf; ++i) al[i] = a0[i];
                 for (size_t q = 0; q < ND && d0 + q < dirs.size(); ++q) {
                     const Dir& d = dirs[d0 + q];
                     if (d.kind == 0) m[2 * d.idx + d.comp].d[q] = 1.0;
@@ -959,11 +983,11 @@ int kfo_fit_vjp(int n_tracks, const int32_t* off, const int32_t* sid, const doub
 // Non-trivial floating-point operations of the fit of each track.
 // counts: [N][5] = add/sub, mul, div, sqrt, transcendental (sin, cos, atan2, log).
 int kfo_count_ops(int n_tracks, const int32_t* off, const int32_t* sid, const double* loc, const double* cov,
-                  int n_surf, const double* center, const double* rot, const double* x0,
+                  int n_surf, const double* center, const double* rot, const double* x0, const double* align,
                   int field_kind, const double* b0, double field_a,
                   const double* seed, const double* seed_cov, int seed_sid,
                   int ms, double mass, double tol, double land_tol, int max_steps, int64_t* counts) {
-    Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, field_kind, b0, field_a,
+    Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, align, field_kind, b0, field_a,
                             seed, seed_cov, seed_sid, ms, mass, tol, land_tol, max_steps);
     std::vector<Surf<Cnt>> surf(n_surf);
     for (int s = 0; s < n_surf; ++s) {
@@ -999,7 +1023,7 @@ extern "C" {
 // Multiple-scattering process noise Q (6x6, row-major) for bound state x on surface s.
 int kfo_ms_noise(int n_surf, const double* center, const double* rot, const double* x0, int s,
                  const double* x, double mass, double* Q) {
-    Inputs in = make_inputs(0, nullptr, nullptr, nullptr, nullptr, n_surf, center, rot, x0, 0, center, 0.0,
+    Inputs in = make_inputs(0, nullptr, nullptr, nullptr, nullptr, n_surf, center, rot, x0, nullptr, 0, center, 0.0,
                             nullptr, nullptr, 0, 1, mass, 0.0, 0.0, 0);
     Surf<double> sf = surf_d(in, s);
     double xi[6], Qm[6][6];

@@ -1,0 +1,332 @@
+// kf_common.hpp -- pieces shared by the fit and the adjoint translation units:
+// per-lane workspace row helpers, track validation, the LDS surface table
+// (with optional alignment corrections), the tile queue of the persistent
+// schedule and the length sort that feeds it.
+//
+// Everything here has internal linkage (anonymous namespace): each .hip file
+// gets its own copy of these kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <limits.h>
+#include <mutex>
+#include "kf_device.hpp"
+#include "kf.h"
+
+namespace {
+
+using namespace kfm;
+
+constexpr int TILE = 64;    // tracks per tile = lanes per wave
+
+__device__ inline bool finite(double v) { return isfinite(v); }
+
+// Component-major rows: v[i] lives at p + i * stride.  The running pointer
+// is kept opaque so the compiler adds the stride per row at the point of use
+// instead of computing all N per-lane addresses once and keeping them live
+// across the whole fit (27 64-bit addresses would otherwise occupy 54
+// registers for the track's lifetime).
+template <int N>
+__device__ inline void store_rows(double* p, int64_t stride, const double (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        *p = v[i];
+        p += stride;
+        __asm__ volatile("" : "+v"(p));
+    }
+}
+
+template <int N>
+__device__ inline void load_rows(const double* p, int64_t stride, double (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        v[i] = *p;
+        p += stride;
+        __asm__ volatile("" : "+v"(p));
+    }
+}
+
+template <int N>
+__device__ inline void fill_rows(double* p, int64_t stride, double val) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        *p = val;
+        p += stride;
+        __asm__ volatile("" : "+v"(p));
+    }
+}
+
+// Input checks of one track, in the order the CPU reference applies them:
+// CSR range, hit count, seed finite with an SPD covariance, every hit on a
+// known surface with finite coordinates and an SPD covariance.  On a corrupt
+// CSR range n is set to 0 so no hit is touched.
+__device__ inline int check_track(const int32_t* off, const int32_t* sid, const double* loc, const double* cov,
+                                  const double* seed, const double* seed_cov, int64_t H, int64_t N, int n_surf,
+                                  int max_hits, int t, int& o, int& n) {
+    o = off[t];
+    n = off[t + 1] - o;
+    if (o < 0 || n < 0 || (int64_t)o + n > H) { n = 0; return ST_BAD_INPUT; }
+    if (n < 3) return ST_TOO_FEW;
+    if (n > max_hits) return ST_BAD_INPUT;
+    double x[6], C[21];
+    load_rows(seed + t, N, x);
+    load_rows(seed_cov + t, N, C);
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ok = ok && finite(x[i]);
+#pragma unroll
+    for (int q = 0; q < 21; ++q) ok = ok && finite(C[q]);
+    // seed covariance must be SPD (Cholesky pivots)
+    if (ok) {
+        double L[6][6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            double s = C[sy(j, j)];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+            ok = ok && (s > 0.0);
+            const double l = sqrt(s > 0.0 ? s : 1.0);
+            L[j][j] = l;
+#pragma unroll
+            for (int i = j + 1; i < 6; ++i) {
+                double tt = C[sy(i, j)];
+#pragma unroll
+                for (int k = 0; k < j; ++k) tt -= L[i][k] * L[j][k];
+                L[i][j] = tt / l;
+            }
+        }
+    }
+    for (int k = 0; k < n && ok; ++k) {
+        const int s = sid[o + k];
+        double m[2], V[3];
+        load_rows(loc + o + k, H, m);
+        load_rows(cov + o + k, H, V);
+        ok = (s >= 0 && s < n_surf) && finite(m[0]) && finite(m[1]) && finite(V[0]) && finite(V[1]) &&
+             finite(V[2]) && (V[0] > 0.0) && (V[0] * V[2] - V[1] * V[1] > 0.0);
+    }
+    return ok ? ST_OK : ST_BAD_INPUT;
+}
+
+// Surface s with an alignment correction a = (dx, dy, dz, alpha, beta, gamma):
+// centre c + (dx, dy, dz), rotation R Rx(alpha) Ry(beta) Rz(gamma), i.e. the
+// plane turned about its own u, v, n axes.
+__device__ inline void apply_alignment(const double al[6], double s[SURF_STRIDE]) {
+    double sa, ca, sb, cb, sg, cg;
+    sincos(al[3], &sa, &ca);
+    sincos(al[4], &sb, &cb);
+    sincos(al[5], &sg, &cg);
+    const double Rx[3][3] = {{1.0, 0.0, 0.0}, {0.0, ca, -sa}, {0.0, sa, ca}};
+    const double Ry[3][3] = {{cb, 0.0, sb}, {0.0, 1.0, 0.0}, {-sb, 0.0, cb}};
+    const double Rz[3][3] = {{cg, -sg, 0.0}, {sg, cg, 0.0}, {0.0, 0.0, 1.0}};
+    double T1[3][3], T2[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc += s[3 + 3 * i + k] * Rx[k][j];
+            T1[i][j] = acc;
+        }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc += T1[i][k] * Ry[k][j];
+            T2[i][j] = acc;
+        }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc += T2[i][k] * Rz[k][j];
+            s[3 + 3 * i + j] = acc;
+        }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s[i] += al[i];
+}
+
+// Surface table in LDS: c[3], R[9] row-major, x/X0 per surface (13 doubles).
+__device__ inline void stage_surfaces(int S, const double* center, const double* rot, const double* x0,
+                                      const double* align, double* sm) {
+    if (!align) {
+        for (int i = threadIdx.x; i < S * SURF_STRIDE; i += blockDim.x) {
+            const int s = i / SURF_STRIDE, f = i - s * SURF_STRIDE;
+            double v;
+            if (f < 3) v = center[f * S + s];
+            else if (f < 12) v = rot[(f - 3) * S + s];
+            else v = x0[s];
+            sm[i] = v;
+        }
+    } else {
+        for (int s = threadIdx.x; s < S; s += blockDim.x) {
+            double v[SURF_STRIDE], al[6];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) v[f] = center[f * S + s];
+#pragma unroll
+            for (int f = 0; f < 9; ++f) v[3 + f] = rot[f * S + s];
+            v[12] = x0[s];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) al[c] = align[c * S + s];
+            apply_alignment(al, v);
+#pragma unroll
+            for (int f = 0; f < SURF_STRIDE; ++f) sm[s * SURF_STRIDE + f] = v[f];
+        }
+    }
+    __syncthreads();
+}
+
+// Tile source: DIRECT maps workgroups to tiles in order; SORTED makes every
+// wave pull tiles (64 tracks of equal length, longest first) from a queue
+// until it is empty.
+template <bool SORTED>
+__device__ inline int next_tile(int32_t* counter, int& iter) {
+    if (!SORTED) return iter++ == 0 ? (int)((blockIdx.x * blockDim.x + threadIdx.x) / TILE) : INT_MAX;
+    int tile = 0;
+    if ((threadIdx.x & (TILE - 1)) == 0) tile = atomicAdd(counter, 1);
+    return __shfl(tile, 0, TILE);
+}
+
+// ---- sorted schedule: order tracks by hit count, longest first ----
+// counts[b] for b = 0..KF_MAX_HITS+1 (bin of n clipped), then positions.
+__global__ void k_zero_i32(int32_t* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__device__ inline int len_bin(const int32_t* off, int t, int max_hits) {
+    int n = off[t + 1] - off[t];
+    n = n < 0 ? 0 : n;
+    n = n > max_hits + 1 ? max_hits + 1 : n;
+    return (max_hits + 1) - n;      // longest first
+}
+
+// Each workgroup builds its histogram in LDS and adds it to the global one
+// with one atomic per non-empty bin (equal lengths would otherwise serialise
+// every track on one address).
+constexpr int NBINS = KF_MAX_HITS + 2;
+
+__global__ void __launch_bounds__(256) k_hist(const int32_t* off, int N, int max_hits, int32_t* counts) {
+    __shared__ int32_t h[NBINS];
+    for (int i = threadIdx.x; i < NBINS; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < N) atomicAdd(&h[len_bin(off, t, max_hits)], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < NBINS; i += blockDim.x)
+        if (h[i]) atomicAdd(&counts[i], h[i]);
+}
+
+// exclusive scan of the NBINS (<= 256) bins by one workgroup of 256 threads
+__global__ void __launch_bounds__(256) k_scan(int32_t* counts) {
+    __shared__ int32_t s[256];
+    const int i = threadIdx.x;
+    const int own = i < NBINS ? counts[i] : 0;
+    s[i] = own;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const int v = i >= d ? s[i - d] : 0;
+        __syncthreads();
+        s[i] += v;
+        __syncthreads();
+    }
+    if (i < NBINS) counts[i] = s[i] - own;
+}
+
+// each workgroup reserves one range per bin, then places its tracks
+__global__ void __launch_bounds__(256) k_scatter(const int32_t* off, int N, int max_hits, int32_t* pos,
+                                                 int32_t* order) {
+    __shared__ int32_t h[NBINS], base[NBINS];
+    for (int i = threadIdx.x; i < NBINS; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = 0, local = 0;
+    if (t < N) {
+        b = len_bin(off, t, max_hits);
+        local = atomicAdd(&h[b], 1);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < NBINS; i += blockDim.x)
+        if (h[i]) base[i] = atomicAdd(&pos[i], h[i]);
+    __syncthreads();
+    if (t < N) order[base[b] + local] = t;
+}
+
+// Enqueue the length sort: order[] receives the track indices, longest
+// first; the two tile-queue heads are cleared.
+inline hipError_t enqueue_length_sort(const int32_t* off, int N, int max_hits, int32_t* counts, int32_t* order,
+                                      int32_t* tile_counter, hipStream_t stream) {
+    const int tb = 256, tg = (N + tb - 1) / tb;
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(128), 0, stream, counts, NBINS);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, tile_counter, 2);
+    hipLaunchKernelGGL(k_hist, dim3(tg), dim3(tb), 0, stream, off, N, max_hits, counts);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, stream, counts);
+    hipLaunchKernelGGL(k_scatter, dim3(tg), dim3(tb), 0, stream, off, N, max_hits, counts, order);
+    return hipGetLastError();
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+inline int num_cu() {
+    static int n = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            n = p.multiProcessorCount;
+        if (n <= 0) n = 256;
+    });
+    return n;
+}
+
+// Host-side checks shared by every entry point (everything but the outputs).
+inline int validate_inputs(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field,
+                           const kf_measurements* meas, const kf_seeds* seeds) {
+    if (!cfg || !surf || !field || !meas || !seeds) return KF_E_NULL;
+    if (cfg->precision != KF_PREC_FP64 && cfg->precision != KF_PREC_MIXED) return KF_E_ENUM;
+    if (cfg->schedule != KF_SCHED_AUTO && cfg->schedule != KF_SCHED_DIRECT && cfg->schedule != KF_SCHED_SORTED)
+        return KF_E_ENUM;
+    if (field->kind != KF_FIELD_UNIFORM && field->kind != KF_FIELD_SOLENOID) return KF_E_ENUM;
+    if (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256) return KF_E_VALUE;
+    if (cfg->waves_per_cu < 0 || cfg->waves_per_cu > 32) return KF_E_VALUE;
+    if (cfg->occupancy < 0 || cfg->occupancy > 3) return KF_E_VALUE;
+    if (cfg->split_smoother < 0 || cfg->split_smoother > 1) return KF_E_VALUE;
+    if (!(cfg->rk_tol > 0.0) || !(cfg->land_tol > 0.0) || !(cfg->mass >= 0.0) || cfg->max_steps < 1)
+        return KF_E_VALUE;
+    if (!isfinite(field->b0[0]) || !isfinite(field->b0[1]) || !isfinite(field->b0[2]) || !isfinite(field->a))
+        return KF_E_VALUE;
+    if (meas->n_tracks < 0 || meas->n_hits < 0 || meas->max_hits < 1 || meas->max_hits > KF_MAX_HITS)
+        return KF_E_SIZE;
+    if (surf->n < 1 || surf->n > KF_MAX_SURFACES) return KF_E_SIZE;
+    if (seeds->surface_id < 0 || seeds->surface_id >= surf->n) return KF_E_SIZE;
+    if (meas->n_tracks == 0) return KF_OK;
+    if (!surf->center || !surf->rot || !surf->x_over_X0) return KF_E_NULL;
+    if (!meas->hit_offsets || !seeds->par || !seeds->cov) return KF_E_NULL;
+    if (meas->n_hits > 0 && (!meas->surface_id || !meas->loc || !meas->cov)) return KF_E_NULL;
+    return KF_OK;
+}
+
+inline FieldDef field_def(const kf_field* field) {
+    FieldDef f;
+    f.kind = field->kind;
+    for (int i = 0; i < 3; ++i) f.b0[i] = field->b0[i];
+    f.a = field->a;
+    return f;
+}
+
+inline Cfg cfg_def(const kf_config* cfg) {
+    Cfg c;
+    c.ms = cfg->multiple_scattering ? 1 : 0;
+    c.mass = cfg->mass;
+    c.tol = cfg->rk_tol;
+    c.land_tol = cfg->land_tol;
+    c.max_steps = cfg->max_steps;
+    return c;
+}
+
+}  // namespace

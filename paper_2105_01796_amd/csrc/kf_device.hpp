@@ -13,6 +13,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include "kf_dual.hpp"
 
 namespace kfm {
 
@@ -220,22 +221,26 @@ __device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& 
 // FP64 anchor; the landing loop stops at an FP32-resolvable distance and the
 // same FP64 second-order move finishes it.
 // ---------------------------------------------------------------------------
-template <class P, int FK>
-__device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, const Cfg& cfg,
-                                const double* __restrict__ sa, const double* __restrict__ sb,
-                                const double x[6], double xp[6], double F[25], int* trials_out) {
+// R is the type of the FP64-precision quantities (double, or a dual number in
+// the adjoint); P the stepping type (double, float for MIXED, or the same
+// dual type).  Surfaces a and b are read as SA / SB values, 13 each
+// (c, R, x/X0): plain doubles, or dual numbers carrying an alignment tangent.
+template <class R, class P, int FK, class SA, class SB>
+__device__ inline int transport_t(const Field<P, FK>& fl, const FieldDef& fd, const Cfg& cfg, const SA* sa,
+                                  const SB* sb, const R x[6], R xp[6], R F[25], int* trials_out) {
+    using V = typename ValueOf<P>::type;    // plain type for step-control bookkeeping
     // bound -> free on surface a
-    double sp, cp, st, ct;
+    R sp, cp, st, ct;
     sincos(x[2], &sp, &cp);
     sincos(x[3], &st, &ct);
-    double r0[3], T0[3];
+    R r0[3], T0[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) r0[i] = sa[i] + x[0] * sa[3 + 3 * i + 0] + x[1] * sa[3 + 3 * i + 1];
     T0[0] = cp * st; T0[1] = sp * st; T0[2] = ct;
-    const double lam_d = x[4];
+    const R lam_d = x[4];
     const P lam = P(lam_d);
-    const double gd = sqrt(1.0 + cfg.mass * cfg.mass * lam_d * lam_d) / kC;     // dt/ds
-    const double gpd = cfg.mass * cfg.mass * lam_d / (kC * kC * gd);            // d(dt/ds)/d(q/p)
+    const R gd = sqrt(1.0 + cfg.mass * cfg.mass * lam_d * lam_d) / kC;     // dt/ds
+    const R gpd = cfg.mass * cfg.mass * lam_d / (kC * kC * gd);            // d(dt/ds)/d(q/p)
     P Mr[3][5], MT[3][5];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -246,103 +251,104 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
             Mr[i][1] = P(sa[3 + 3 * i + 1]);
         }
     }
-    MT[0][2] = P(-sp * st); MT[1][2] = P(cp * st); MT[2][2] = P(0);
-    MT[0][3] = P(cp * ct);  MT[1][3] = P(sp * ct); MT[2][3] = P(-st);
-    double Mtl = 0.0;     // d t / d(q/p) accumulated over accepted steps
+    MT[0][2] = P(-(sp * st)); MT[1][2] = P(cp * st); MT[2][2] = P(0);
+    MT[0][3] = P(cp * ct);    MT[1][3] = P(sp * ct); MT[2][3] = P(-st);
+    R Mtl = 0.0;     // d t / d(q/p) accumulated over accepted steps
 
-    const double nb[3] = {sb[3 + 2], sb[3 + 5], sb[3 + 8]};
-    const double d0 = nb[0] * (sb[0] - r0[0]) + nb[1] * (sb[1] - r0[1]) + nb[2] * (sb[2] - r0[2]);
-    const P n[3] = {P(nb[0]), P(nb[1]), P(nb[2])};
-    const P tol = P(cfg.tol);
-    const bool mixed = sizeof(P) < sizeof(double);
+    const R nb[3] = {sb[3 + 2], sb[3 + 5], sb[3 + 8]};
+    const R d0 = nb[0] * (sb[0] - r0[0]) + nb[1] * (sb[1] - r0[1]) + nb[2] * (sb[2] - r0[2]);
+    const V tol = V(cfg.tol);
+    const bool mixed = sizeof(V) < sizeof(double);
     // position = r0 + rl + dr: rl (FP64) collects the straight-line part h T of
     // every step, dr the curvature part h^2/6 (k1 + k2 + k3) in precision P;
     // direction = T0 + dT.  In FP32 the big h T term would cost ~1e-7 relative
     // over a long step, so only the small curvature increments are FP32.
-    double rl[3] = {0.0, 0.0, 0.0};
+    R rl[3] = {R(0.0), R(0.0), R(0.0)};
     P dr[3] = {P(0), P(0), P(0)}, dT[3] = {P(0), P(0), P(0)};
-    double dt = 0.0;
-    P hmag = P(-1);
+    R dt = 0.0;
+    V hmag = V(-1);
     int trials = 0;
     int status = ST_OK;
     Stages<P, FK> S;
     for (;;) {
         P T[3], rabs[3];
-        double Td[3];
+        R Td[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            Td[i] = T0[i] + double(dT[i]);
+            Td[i] = T0[i] + R(dT[i]);
             T[i] = P(Td[i]);
             rabs[i] = P(r0[i] + rl[i]) + dr[i];
         }
-        const double nTd = nb[0] * Td[0] + nb[1] * Td[1] + nb[2] * Td[2];
-        const double distd = d0 - (nb[0] * rl[0] + nb[1] * rl[1] + nb[2] * rl[2])
-                                 - (nb[0] * double(dr[0]) + nb[1] * double(dr[1]) + nb[2] * double(dr[2]));
-        if (fabs(nTd) < 1e-6) { status = ST_NO_INTERSECT; break; }
+        const R nTd = nb[0] * Td[0] + nb[1] * Td[1] + nb[2] * Td[2];
+        const R distd = d0 - (nb[0] * rl[0] + nb[1] * rl[1] + nb[2] * rl[2])
+                            - (nb[0] * R(dr[0]) + nb[1] * R(dr[1]) + nb[2] * R(dr[2]));
+        if (::fabs(val(nTd)) < 1e-6) { status = ST_NO_INTERSECT; break; }
         // FP32 curvature increments resolve ~1e-7 mm; the FP64 move below finishes the landing
         const double ltol = mixed ? 1e-5 : cfg.land_tol;
-        if (fabs(distd) < ltol) break;
+        if (::fabs(val(distd)) < ltol) break;
         if (trials >= cfg.max_steps) { status = ST_STEP_CAP; break; }
         const P d = P(distd / nTd);
-        if (hmag < P(0)) hmag = pabs(d);
-        const P h = (pabs(d) <= hmag) ? d : (d < P(0) ? -hmag : hmag);
+        const V dv = V(val(d));
+        if (hmag < V(0)) hmag = dv < V(0) ? -dv : dv;
+        const P h = ((dv < V(0) ? -dv : dv) <= hmag) ? d : P(dv < V(0) ? -hmag : hmag);
         P k[4][3];
-        const P err = rkn_trial<P, FK>(fl, rabs, T, lam, h, S, k);
+        const V err = V(val(rkn_trial<P, FK>(fl, rabs, T, lam, h, S, k)));
         ++trials;
         phase_boundary();
-        const P tiny = P(sizeof(P) < sizeof(double) ? 1e-30 : 1e-300);
-        P fac = P(0.9) * sqrt(sqrt(tol / (err > tiny ? err : tiny)));
-        fac = fac < P(0.25) ? P(0.25) : (fac > P(4) ? P(4) : fac);
+        const V tiny = V(mixed ? 1e-30 : 1e-300);
+        V fac = V(0.9) * sqrt(sqrt(tol / (err > tiny ? err : tiny)));
+        fac = fac < V(0.25) ? V(0.25) : (fac > V(4) ? V(4) : fac);
         if (err <= tol) {
             rkn_tangent<P, FK>(fl, S, k, lam, h, Mr, MT);
             phase_boundary();
-            Mtl += double(h) * gpd;
-            const double hd = double(h);
+            const R hd = R(h);
+            Mtl = Mtl + hd * gpd;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                rl[i] += hd * Td[i];
+                rl[i] = rl[i] + hd * Td[i];
                 dr[i] = dr[i] + h * h * (P(1) / P(6)) * (k[0][i] + k[1][i] + k[2][i]);
                 dT[i] = dT[i] + h * (P(1) / P(6)) * (k[0][i] + P(2) * k[1][i] + P(2) * k[2][i] + k[3][i]);
             }
-            dt += hd * gd;
+            dt = dt + hd * gd;
         }
-        hmag = pabs(h) * fac;
+        const V hv = V(val(h));
+        hmag = (hv < V(0) ? -hv : hv) * fac;
     }
     *trials_out = trials;
     if (status != ST_OK) return status;
 
     // final free state in FP64, then the remaining distance d onto the plane,
     // second order in d: r += d T + d^2/2 T', T += d T', t += d dt/ds
-    double r[3], T[3];
+    R r[3], T[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { r[i] = r0[i] + rl[i] + double(dr[i]); T[i] = T0[i] + double(dT[i]); }
-    double t = x[5] + dt;
-    Field<double, FK> f64;
+    for (int i = 0; i < 3; ++i) { r[i] = r0[i] + rl[i] + R(dr[i]); T[i] = T0[i] + R(dT[i]); }
+    R t = x[5] + dt;
+    Field<R, FK> f64;
     f64.init(fd);
     {
-        const double nT0 = nb[0] * T[0] + nb[1] * T[1] + nb[2] * T[2];
-        const double rem = (nb[0] * (sb[0] - r[0]) + nb[1] * (sb[1] - r[1]) + nb[2] * (sb[2] - r[2])) / nT0;
-        double B0[3], TB0[3];
+        const R nT0 = nb[0] * T[0] + nb[1] * T[1] + nb[2] * T[2];
+        const R rem = (nb[0] * (sb[0] - r[0]) + nb[1] * (sb[1] - r[1]) + nb[2] * (sb[2] - r[2])) / nT0;
+        R B0[3], TB0[3];
         f64.eval(r, B0);
         cross(T, B0, TB0);
-        const double lk = lam_d * kKappa;
+        const R lk = lam_d * kKappa;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            r[i] += rem * T[i] + 0.5 * rem * rem * lk * TB0[i];
-            T[i] += rem * lk * TB0[i];
+            r[i] = r[i] + rem * T[i] + 0.5 * rem * rem * lk * TB0[i];
+            T[i] = T[i] + rem * lk * TB0[i];
         }
-        t += rem * gd;
+        t = t + rem * gd;
     }
-    const double nTd = nb[0] * T[0] + nb[1] * T[1] + nb[2] * T[2];
+    const R nTd = nb[0] * T[0] + nb[1] * T[1] + nb[2] * T[2];
     // free -> bound on surface b
-    const double u[3] = {sb[3 + 0], sb[3 + 3], sb[3 + 6]};
-    const double v[3] = {sb[3 + 1], sb[3 + 4], sb[3 + 7]};
-    const double dd[3] = {r[0] - sb[0], r[1] - sb[1], r[2] - sb[2]};
+    const R u[3] = {sb[3 + 0], sb[3 + 3], sb[3 + 6]};
+    const R v[3] = {sb[3 + 1], sb[3 + 4], sb[3 + 7]};
+    const R dd[3] = {r[0] - sb[0], r[1] - sb[1], r[2] - sb[2]};
     xp[0] = u[0] * dd[0] + u[1] * dd[1] + u[2] * dd[2];
     xp[1] = v[0] * dd[0] + v[1] * dd[1] + v[2] * dd[2];
-    const double rho2 = T[0] * T[0] + T[1] * T[1];
-    const double rho = sqrt(rho2);
-    const double n2 = rho2 + T[2] * T[2];
+    const R rho2 = T[0] * T[0] + T[1] * T[1];
+    const R rho = sqrt(rho2);
+    const R n2 = rho2 + T[2] * T[2];
     xp[2] = atan2(T[1], T[0]);
     xp[3] = atan2(rho, T[2]);
     xp[4] = lam_d;
@@ -350,53 +356,65 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
     // F = J_fb * P_corr * (D J_bf), one column at a time: the path correction
     // moves each variation back onto the plane along dF/ds, then J_fb maps it
     // to the bound parameters of surface b
-    double B[3], TxB[3];
+    R B[3], TxB[3];
     f64.eval(r, B);
     cross(T, B, TxB);
-    const double lk = lam_d * kKappa;
-    const double inT = 1.0 / nTd, ip = 1.0 / rho2, ith = 1.0 / (rho * n2), in2 = 1.0 / n2;
+    const R lk = lam_d * kKappa;
+    const R inT = 1.0 / nTd, ip = 1.0 / rho2, ith = 1.0 / (rho * n2), in2 = 1.0 / n2;
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
         // columns below J0 were never propagated: (u, v) of surface a, no direction part
         const bool fixed = j < TangentCols<FK>::J0;
-        double mr[3], mt[3];
+        R mr[3], mt[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            mr[i] = fixed ? sa[3 + 3 * i + j] : double(Mr[i][j]);
-            mt[i] = fixed ? 0.0 : double(MT[i][j]);
+            mr[i] = fixed ? R(sa[3 + 3 * i + j]) : R(Mr[i][j]);
+            mt[i] = fixed ? R(0.0) : R(MT[i][j]);
         }
-        const double sc = (nb[0] * mr[0] + nb[1] * mr[1] + nb[2] * mr[2]) * inT;
+        const R sc = (nb[0] * mr[0] + nb[1] * mr[1] + nb[2] * mr[2]) * inT;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            mr[i] -= T[i] * sc;
-            mt[i] -= lk * TxB[i] * sc;
+            mr[i] = mr[i] - T[i] * sc;
+            mt[i] = mt[i] - lk * TxB[i] * sc;
         }
         F[0 * 5 + j] = u[0] * mr[0] + u[1] * mr[1] + u[2] * mr[2];
         F[1 * 5 + j] = v[0] * mr[0] + v[1] * mr[1] + v[2] * mr[2];
         F[2 * 5 + j] = (T[0] * mt[1] - T[1] * mt[0]) * ip;
         F[3 * 5 + j] = T[2] * (T[0] * mt[0] + T[1] * mt[1]) * ith - rho * mt[2] * in2;
-        F[4 * 5 + j] = (j == 4 ? Mtl : 0.0) - gd * sc;
+        F[4 * 5 + j] = (j == 4 ? Mtl : R(0.0)) - gd * sc;
     }
     return ST_OK;
+}
+
+template <class P, int FK>
+__device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, const Cfg& cfg,
+                                const double* __restrict__ sa, const double* __restrict__ sb,
+                                const double x[6], double xp[6], double F[25], int* trials_out) {
+    return transport_t<double, P, FK, double, double>(fl, fd, cfg, sa, sb, x, xp, F, trials_out);
 }
 
 // ---------------------------------------------------------------------------
 // thin-scatterer noise on surface s for the filtered state x (PDG Highland)
 // Q = diag(0, 0, theta0^2 / sin^2(theta), theta0^2, 0, 0)
 // ---------------------------------------------------------------------------
-__device__ inline void highland(const double* __restrict__ s, const double x[6], double mass, double* q22, double* q33) {
-    const double x0 = s[12];
-    if (!(x0 > 0.0)) { *q22 = 0.0; *q33 = 0.0; return; }
-    double sp, cp, st, ct;
+template <class R, class Surf>
+__device__ inline void highland_t(const Surf* s, const R x[6], double mass, R* q22, R* q33) {
+    const double x0 = val(s[12]);
+    if (!(x0 > 0.0)) { *q22 = R(0.0); *q33 = R(0.0); return; }
+    R sp, cp, st, ct;
     sincos(x[2], &sp, &cp);
     sincos(x[3], &st, &ct);
-    const double nT = s[3 + 2] * cp * st + s[3 + 5] * sp * st + s[3 + 8] * ct;
-    const double path = x0 / fabs(nT);
-    const double p = 1.0 / fabs(x[4]);
-    const double beta = p / sqrt(p * p + mass * mass);
-    const double th0 = 0.0136 / (beta * p) * sqrt(path) * (1.0 + 0.038 * log(path / (beta * beta)));
+    const R nT = s[3 + 2] * cp * st + s[3 + 5] * sp * st + s[3 + 8] * ct;
+    const R path = x0 / fabs(nT);
+    const R p = 1.0 / fabs(x[4]);
+    const R beta = p / sqrt(p * p + mass * mass);
+    const R th0 = 0.0136 / (beta * p) * sqrt(path) * (1.0 + 0.038 * log(path / (beta * beta)));
     *q33 = th0 * th0;
     *q22 = th0 * th0 / (st * st);
+}
+
+__device__ inline void highland(const double* __restrict__ s, const double x[6], double mass, double* q22, double* q33) {
+    highland_t<double, double>(s, x, mass, q22, q33);
 }
 
 // ---------------------------------------------------------------------------

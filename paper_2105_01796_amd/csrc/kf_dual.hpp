@@ -13,6 +13,13 @@
 
 namespace kfm {
 
+// the plain-number versions stay visible next to the dual overloads below
+using ::sqrt;
+using ::log;
+using ::fabs;
+using ::sincos;
+using ::atan2;
+
 template <int K>
 struct Dual {
     double v;

@@ -22,10 +22,7 @@
 #include <mutex>
 #include <map>
 #include <limits.h>
-#include "kf_device.hpp"
-#include "kf.h"
-
-using namespace kfm;
+#include "kf_common.hpp"
 
 namespace {
 
@@ -33,7 +30,6 @@ namespace {
 // previous state A 36 (row-major); predicted state xp 6, Cp 21
 constexpr int NC = 90;
 constexpr int OFF_XF = 0, OFF_CF = 6, OFF_A = 27, OFF_XP = 63, OFF_CP = 69;
-constexpr int TILE = 64;
 
 struct FitArgs {
     int n_tracks;
@@ -49,6 +45,7 @@ struct FitArgs {
     const double* center;
     const double* rot;
     const double* x0;
+    const double* align;        // [6][S] alignment corrections or NULL
     const double* seed;
     const double* seed_cov;
     FieldDef field;
@@ -70,97 +67,18 @@ struct FitArgs {
     int n_tiles;
 };
 
-__device__ inline bool finite(double v) { return isfinite(v); }
-
-// Component-major rows: v[i] lives at p + i * stride.  The running pointer
-// is kept opaque so the compiler adds the stride per row at the point of use
-// instead of computing all N per-lane addresses once and keeping them live
-// across the whole fit (27 64-bit addresses would otherwise occupy 54
-// registers for the track's lifetime).
-template <int N>
-__device__ inline void store_rows(double* p, int64_t stride, const double (&v)[N]) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        *p = v[i];
-        p += stride;
-        __asm__ volatile("" : "+v"(p));
-    }
-}
-
-template <int N>
-__device__ inline void load_rows(const double* p, int64_t stride, double (&v)[N]) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        v[i] = *p;
-        p += stride;
-        __asm__ volatile("" : "+v"(p));
-    }
-}
-
-template <int N>
-__device__ inline void fill_rows(double* p, int64_t stride, double val) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        *p = val;
-        p += stride;
-        __asm__ volatile("" : "+v"(p));
-    }
-}
-
 // Forward filter of the track held by workspace slot `slot` (track index t):
 // validation, then per hit propagation, covariance transport, RTS gain of the
 // previous state and the gain-matrix update.  Writes chi2, ndf and status;
 // a failed track gets NaN outputs here (the backward pass skips it).
 template <class P, int FK>
 __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
-    const int o = a.off[t];
-    int n = a.off[t + 1] - o;
     const int64_t H = a.n_hits;
-    int status = ST_OK;
-    if (o < 0 || n < 0 || (int64_t)o + n > H) { status = ST_BAD_INPUT; n = 0; }   // corrupt CSR: touch no hit
-    else if (n < 3) status = ST_TOO_FEW;
-    else if (n > a.max_hits) status = ST_BAD_INPUT;
     const int64_t N = a.n_tracks;
+    int o, n;
+    int status = check_track(a.off, a.sid, a.loc, a.cov, a.seed, a.seed_cov, H, N, a.n_surf, a.max_hits, t, o, n);
     double x[6];
     load_rows(a.seed + t, N, x);
-    if (status == ST_OK) {
-        double C[21];
-        load_rows(a.seed_cov + t, N, C);
-        bool ok = true;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) ok = ok && finite(x[i]);
-#pragma unroll
-        for (int q = 0; q < 21; ++q) ok = ok && finite(C[q]);
-        // seed covariance must be SPD (Cholesky pivots)
-        if (ok) {
-            double L[6][6];
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-                double s = C[sy(j, j)];
-#pragma unroll
-                for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
-                ok = ok && (s > 0.0);
-                const double l = sqrt(s > 0.0 ? s : 1.0);
-                L[j][j] = l;
-#pragma unroll
-                for (int i = j + 1; i < 6; ++i) {
-                    double tt = C[sy(i, j)];
-#pragma unroll
-                    for (int k = 0; k < j; ++k) tt -= L[i][k] * L[j][k];
-                    L[i][j] = tt / l;
-                }
-            }
-        }
-        for (int k = 0; k < n && ok; ++k) {
-            const int s = a.sid[o + k];
-            double m[2], V[3];
-            load_rows(a.loc + o + k, H, m);
-            load_rows(a.cov + o + k, H, V);
-            ok = (s >= 0 && s < a.n_surf) && finite(m[0]) && finite(m[1]) && finite(V[0]) && finite(V[1]) &&
-                 finite(V[2]) && (V[0] > 0.0) && (V[0] * V[2] - V[1] * V[1] > 0.0);
-        }
-        if (!ok) status = ST_BAD_INPUT;
-    }
     Field<P, FK> fl;
     fl.init(a.field);
     // this lane's column of its tile: component c of hit k at wl[(k * NC + c) * TILE]
@@ -331,30 +249,6 @@ __device__ void bwd_one(const FitArgs& a, int64_t slot, int t) {
     store_rows(a.tgt_cov + t, N, C);
 }
 
-__device__ inline void stage_surfaces(const FitArgs& a, double* sm) {
-    const int S = a.n_surf;
-    for (int i = threadIdx.x; i < S * SURF_STRIDE; i += blockDim.x) {
-        const int s = i / SURF_STRIDE, f = i - s * SURF_STRIDE;
-        double v;
-        if (f < 3) v = a.center[f * S + s];
-        else if (f < 12) v = a.rot[(f - 3) * S + s];
-        else v = a.x0[s];
-        sm[i] = v;
-    }
-    __syncthreads();
-}
-
-// Tile source for both passes: DIRECT maps workgroups to tiles in order;
-// SORTED makes every wave pull tiles (64 tracks of equal length, longest
-// first) from a queue until it is empty.
-template <bool SORTED>
-__device__ inline int next_tile(int32_t* counter, int& iter) {
-    if (!SORTED) return iter++ == 0 ? (int)((blockIdx.x * blockDim.x + threadIdx.x) / TILE) : INT_MAX;
-    int tile = 0;
-    if ((threadIdx.x & (TILE - 1)) == 0) tile = atomicAdd(counter, 1);
-    return __shfl(tile, 0, TILE);
-}
-
 // Filter (+ smoother).  SORTED selects the schedule at compile time; OCC is
 // the occupancy target in waves per SIMD, which caps the registers per lane;
 // FUSED runs the smoother for a track right after its forward pass, while
@@ -363,7 +257,7 @@ template <class P, int FK, int OCC, bool SORTED, bool FUSED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
 k_fwd(FitArgs a) {
     extern __shared__ double sm[];
-    stage_surfaces(a, sm);
+    stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, sm);
     const int lane = threadIdx.x & (TILE - 1);
     int iter = 0;
     for (;;) {
@@ -393,71 +287,6 @@ k_bwd(FitArgs a) {
     }
 }
 
-// ---- sorted schedule: order tracks by hit count, longest first ----
-// counts[b] for b = 0..KF_MAX_HITS+1 (bin of n clipped), then positions.
-__global__ void k_zero_i32(int32_t* p, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
-__device__ inline int len_bin(const int32_t* off, int t, int max_hits) {
-    int n = off[t + 1] - off[t];
-    n = n < 0 ? 0 : n;
-    n = n > max_hits + 1 ? max_hits + 1 : n;
-    return (max_hits + 1) - n;      // longest first
-}
-
-// Each workgroup builds its histogram in LDS and adds it to the global one
-// with one atomic per non-empty bin (equal lengths would otherwise serialise
-// every track on one address).
-constexpr int NBINS = KF_MAX_HITS + 2;
-
-__global__ void __launch_bounds__(256) k_hist(const int32_t* off, int N, int max_hits, int32_t* counts) {
-    __shared__ int32_t h[NBINS];
-    for (int i = threadIdx.x; i < NBINS; i += blockDim.x) h[i] = 0;
-    __syncthreads();
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < N) atomicAdd(&h[len_bin(off, t, max_hits)], 1);
-    __syncthreads();
-    for (int i = threadIdx.x; i < NBINS; i += blockDim.x)
-        if (h[i]) atomicAdd(&counts[i], h[i]);
-}
-
-// exclusive scan of the NBINS (<= 256) bins by one workgroup of 256 threads
-__global__ void __launch_bounds__(256) k_scan(int32_t* counts) {
-    __shared__ int32_t s[256];
-    const int i = threadIdx.x;
-    const int own = i < NBINS ? counts[i] : 0;
-    s[i] = own;
-    __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-        const int v = i >= d ? s[i - d] : 0;
-        __syncthreads();
-        s[i] += v;
-        __syncthreads();
-    }
-    if (i < NBINS) counts[i] = s[i] - own;
-}
-
-// each workgroup reserves one range per bin, then places its tracks
-__global__ void __launch_bounds__(256) k_scatter(const int32_t* off, int N, int max_hits, int32_t* pos,
-                                                 int32_t* order) {
-    __shared__ int32_t h[NBINS], base[NBINS];
-    for (int i = threadIdx.x; i < NBINS; i += blockDim.x) h[i] = 0;
-    __syncthreads();
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int b = 0, local = 0;
-    if (t < N) {
-        b = len_bin(off, t, max_hits);
-        local = atomicAdd(&h[b], 1);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < NBINS; i += blockDim.x)
-        if (h[i]) base[i] = atomicAdd(&pos[i], h[i]);
-    __syncthreads();
-    if (t < N) order[base[b] + local] = t;
-}
-
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -470,7 +299,6 @@ struct WsLayout {
     size_t total;
 };
 
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 WsLayout ws_layout(int64_t n_tracks, int max_hits) {
     WsLayout L;
@@ -484,43 +312,11 @@ WsLayout ws_layout(int64_t n_tracks, int max_hits) {
     return L;
 }
 
-int g_num_cu = 0;
-std::once_flag g_cu_once;
-
-int num_cu() {
-    std::call_once(g_cu_once, [] {
-        int dev = 0;
-        hipDeviceProp_t p;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
-            g_num_cu = p.multiProcessorCount;
-        if (g_num_cu <= 0) g_num_cu = 256;
-    });
-    return g_num_cu;
-}
-
 int validate(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field, const kf_measurements* meas,
              const kf_seeds* seeds, const kf_outputs* out) {
     if (!cfg || !surf || !field || !meas || !seeds || !out) return KF_E_NULL;
-    if (cfg->precision != KF_PREC_FP64 && cfg->precision != KF_PREC_MIXED) return KF_E_ENUM;
-    if (cfg->schedule != KF_SCHED_AUTO && cfg->schedule != KF_SCHED_DIRECT && cfg->schedule != KF_SCHED_SORTED)
-        return KF_E_ENUM;
-    if (field->kind != KF_FIELD_UNIFORM && field->kind != KF_FIELD_SOLENOID) return KF_E_ENUM;
-    if (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256) return KF_E_VALUE;
-    if (cfg->waves_per_cu < 0 || cfg->waves_per_cu > 32) return KF_E_VALUE;
-    if (cfg->occupancy < 0 || cfg->occupancy > 3) return KF_E_VALUE;
-    if (cfg->split_smoother < 0 || cfg->split_smoother > 1) return KF_E_VALUE;
-    if (!(cfg->rk_tol > 0.0) || !(cfg->land_tol > 0.0) || !(cfg->mass >= 0.0) || cfg->max_steps < 1)
-        return KF_E_VALUE;
-    if (!isfinite(field->b0[0]) || !isfinite(field->b0[1]) || !isfinite(field->b0[2]) || !isfinite(field->a))
-        return KF_E_VALUE;
-    if (meas->n_tracks < 0 || meas->n_hits < 0 || meas->max_hits < 1 || meas->max_hits > KF_MAX_HITS)
-        return KF_E_SIZE;
-    if (surf->n < 1 || surf->n > KF_MAX_SURFACES) return KF_E_SIZE;
-    if (seeds->surface_id < 0 || seeds->surface_id >= surf->n) return KF_E_SIZE;
-    if (meas->n_tracks == 0) return KF_OK;
-    if (!surf->center || !surf->rot || !surf->x_over_X0) return KF_E_NULL;
-    if (!meas->hit_offsets || !seeds->par || !seeds->cov) return KF_E_NULL;
-    if (meas->n_hits > 0 && (!meas->surface_id || !meas->loc || !meas->cov)) return KF_E_NULL;
+    const int rc = validate_inputs(cfg, surf, field, meas, seeds);
+    if (rc != KF_OK || meas->n_tracks == 0) return rc;
     if (!out->par && meas->n_hits > 0) return KF_E_NULL;
     if (!out->cov && meas->n_hits > 0) return KF_E_NULL;
     if (!out->tgt_par || !out->tgt_cov || !out->chi2 || !out->ndf || !out->status) return KF_E_NULL;
@@ -586,16 +382,11 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     a.center = surf->center;
     a.rot = surf->rot;
     a.x0 = surf->x_over_X0;
+    a.align = surf->align;
     a.seed = seeds->par;
     a.seed_cov = seeds->cov;
-    a.field.kind = field->kind;
-    for (int i = 0; i < 3; ++i) a.field.b0[i] = field->b0[i];
-    a.field.a = field->a;
-    a.cfg.ms = cfg->multiple_scattering ? 1 : 0;
-    a.cfg.mass = cfg->mass;
-    a.cfg.tol = cfg->rk_tol;
-    a.cfg.land_tol = cfg->land_tol;
-    a.cfg.max_steps = cfg->max_steps;
+    a.field = field_def(field);
+    a.cfg = cfg_def(cfg);
     a.bnz = (field->kind != KF_FIELD_UNIFORM) || field->b0[0] != 0.0 || field->b0[1] != 0.0 || field->b0[2] != 0.0;
     a.par = out->par;
     a.pcov = out->cov;
@@ -618,17 +409,8 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
 
     hipError_t e = hipSuccess;
     if (sched == KF_SCHED_SORTED) {
-        const int nb = NBINS;
-        int32_t* counts = (int32_t*)(wsb + L.counts_off);
-        const int N = a.n_tracks;
-        const int tb = 256, tg = (N + tb - 1) / tb;
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(128), 0, stream, counts, nb);
-        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, a.tile_counter, 2);
-        hipLaunchKernelGGL(k_hist, dim3(tg), dim3(tb), 0, stream, a.off, N, a.max_hits, counts);
-        hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, stream, counts);
-        hipLaunchKernelGGL(k_scatter, dim3(tg), dim3(tb), 0, stream, a.off, N, a.max_hits, counts,
-                           (int32_t*)a.order);
-        e = hipGetLastError();
+        e = enqueue_length_sort(a.off, a.n_tracks, a.max_hits, (int32_t*)(wsb + L.counts_off), (int32_t*)a.order,
+                                a.tile_counter, stream);
         if (e != hipSuccess) return KF_E_HIP;
     }
     const bool mixed = cfg->precision == KF_PREC_MIXED;

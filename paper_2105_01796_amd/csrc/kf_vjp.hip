@@ -1,0 +1,690 @@
+// kf_vjp.hip -- adjoint (vector-Jacobian product) of the batched track fit.
+//
+// For L = sum_t g_chi2 chi2_t + sum_hits g_par . xs + sum_t g_tgt . x_target,
+// one lane per track runs two sweeps over its hits:
+//
+//   forward  (k = 0 .. n-1): the filter of Sect. 2 / Sect. 4.1 again, storing
+//            per hit the predicted state and covariance, the transport
+//            Jacobian F_k, the noise terms and the filtered state and
+//            covariance.  The reverse of the RTS mean recursion only needs the
+//            smoother gains, so it runs here too:
+//              xsb_k = g_par_k + u_k,  u_k = A_{k-1}^T xsb_{k-1}
+//                    = Cp_k^-1 F_k C_{k-1} xsb_{k-1}   (one FP64 Cholesky solve)
+//            with xsb_{-1} = g_tgt.
+//   backward (k = n-1 .. 0): the RTS mean recursion xs_{k-1} = xf_{k-1} + A
+//            (xs_k - xp_k) (with A dx = C_{k-1} F_k^T Cp_k^-1 dx), and the
+//            reverse of the update, the rank-one smoother-gain adjoint, the
+//            covariance transport and the propagation.  The propagation is
+//            recomputed in dual numbers, one pass per input direction (five
+//            start-state directions, six alignment directions of each of the
+//            two surfaces), and each pass is contracted with the adjoints of
+//            its outputs (predicted state, F, noise).
+//
+// Per-hit alignment contributions go to a [6][H + N] buffer; a deterministic
+// two-level reduction (fixed chunks, then a fixed-order tree per surface)
+// sums them per surface and converts the rotation part from the surface's own
+// frame to the (alpha, beta, gamma) of its alignment correction.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+#include <math.h>
+#include "kf_common.hpp"
+#include "kf_adjoint.hpp"
+
+namespace {
+
+// per-hit adjoint workspace [tile][hit][NCV][64 lanes]
+constexpr int NCV = 87;
+constexpr int V_XF = 0, V_CF = 6, V_XP = 27, V_CP = 33, V_F = 54, V_Q = 79, V_U = 81;
+// The backward sweep reuses a hit's slot once its own algebra is done:
+//   V_XF <- xs_{k-1}, V_XP <- adjoint of xp_k, V_CP <- adjoint of C_{k-1},
+//   V_F <- adjoint of F_k, V_Q <- adjoints of the two noise terms,
+//   V_U <- xsb_{k-1}.
+
+struct VjpArgs {
+    int n_tracks;
+    int n_surf;
+    int seed_sid;
+    int max_hits;
+    int64_t n_hits;
+    int64_t tile_doubles;       // max_hits * NCV * 64
+    const int32_t* off;
+    const int32_t* sid;
+    const double* loc;
+    const double* cov;
+    const double* center;
+    const double* rot;
+    const double* x0;
+    const double* align;
+    const double* seed;
+    const double* seed_cov;
+    FieldDef field;
+    Cfg cfg;
+    const double* g_chi2;
+    const double* g_par;
+    const double* g_tgt;
+    double* g_meas;
+    double* g_seed;
+    uint8_t* status;
+    double* contrib;            // [6][n_items]: items < H are hits, the rest tracks (seed surface)
+    int64_t n_items;
+    double* ws;
+    const int32_t* order;
+    int32_t* tile_counter;
+    int n_tiles;
+};
+
+template <int N>
+__device__ inline void ld(const double* w, int off, double (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = w[(off + i) * TILE];
+}
+
+template <int N>
+__device__ inline void st(double* w, int off, const double (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) w[(off + i) * TILE] = v[i];
+}
+
+// ---------------------------------------------------------------------------
+// forward sweep: filter recompute + reverse RTS mean recursion
+// ---------------------------------------------------------------------------
+template <int FK>
+__device__ int vjp_fwd(const VjpArgs& a, const double* __restrict__ sm, double* wl, int t, int o, int n) {
+    const int64_t H = a.n_hits, N = a.n_tracks;
+    Field<double, FK> fl;
+    fl.init(a.field);
+    double x[6];
+    load_rows(a.seed + t, N, x);
+    double as[6];                                   // xsb_{k-1}
+    if (a.g_tgt) load_rows(a.g_tgt + t, N, as);
+    else {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) as[i] = 0.0;
+    }
+    int prev = a.seed_sid;
+    int status = ST_OK;
+    for (int k = 0; k < n; ++k) {
+        const int s = a.sid[o + k];
+        const double* sa = sm + prev * SURF_STRIDE;
+        const double* sb = sm + s * SURF_STRIDE;
+        double q[2] = {0.0, 0.0};
+        if (a.cfg.ms) highland(sa, x, a.cfg.mass, &q[0], &q[1]);
+        double xp[6], F[25];
+        int tr = 0;
+        status = transport<double, FK>(fl, a.field, a.cfg, sa, sb, x, xp, F, &tr);
+        if (status != ST_OK) break;
+        phase_boundary();
+        double* w = wl + k * (NCV * TILE);
+        st(w, V_XP, xp);
+        st(w, V_F, F);
+        st(w, V_Q, q);
+        double C[21];
+        if (k == 0) load_rows(a.seed_cov + t, N, C);
+        else ld(w - NCV * TILE, V_CF, C);
+        phase_boundary();
+        {
+            double CQ[21];
+#pragma unroll
+            for (int i = 0; i < 21; ++i) CQ[i] = C[i];
+            CQ[sy(2, 2)] += q[0];
+            CQ[sy(3, 3)] += q[1];
+            double Cp[21];
+            transport_cov(F, CQ, Cp);
+            st(w, V_CP, Cp);
+        }
+        phase_boundary();
+        {
+            // u = A^T as = Cp^-1 F C as
+            double y[6], v[6], Cp[21], L[21], id[6];
+            symv(C, as, y);
+            fy(F, y, v);
+            ld(w, V_CP, Cp);
+            const bool spd = chol6(Cp, L, id);
+            chol_solve6(L, id, v);
+            st(w, V_U, v);
+            if (!spd) { status = ST_NOT_SPD; break; }
+            if (a.g_par) {
+                double gp[6];
+                load_rows(a.g_par + o + k, H, gp);
+#pragma unroll
+                for (int i = 0; i < 6; ++i) as[i] = v[i] + gp[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) as[i] = v[i];
+            }
+        }
+        phase_boundary();
+        {
+            double Cp[21], m[2], V[3], ck;
+            ld(w, V_CP, Cp);
+            load_rows(a.loc + o + k, H, m);
+            load_rows(a.cov + o + k, H, V);
+            status = kalman_update(xp, Cp, m, V, x, C, &ck);
+            if (status != ST_OK) break;
+            st(w, V_XF, x);
+            st(w, V_CF, C);
+        }
+        phase_boundary();
+        prev = s;
+    }
+    return status;
+}
+
+// sum of (adjoint . tangent) over the outputs of one gap: xp, F and the two
+// noise terms of the start surface
+__device__ inline double contract(const double* w, const Dual<1> xp[6], const Dual<1> F[25]) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc += w[(V_XP + i) * TILE] * xp[i].d[0];
+#pragma unroll
+    for (int q = 0; q < 25; ++q) acc += w[(V_F + q) * TILE] * F[q].d[0];
+    return acc;
+}
+
+// Reverse of one gap (start state x on surface sa -> predicted state on sb):
+// adds d(contracted outputs)/d(x) to xb and the derivatives with respect to
+// the alignment of sa and sb to ga and gb.  w holds the adjoints (V_XP, V_F,
+// V_Q); the start state is read from xsrc (stride xs).
+template <int FK>
+__device__ void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const double* __restrict__ sb,
+                        const double* xsrc, int64_t xs, const double* w, double xb[6], double ga[6],
+                        double gb[6]) {
+    using D = Dual<1>;
+    Field<D, FK> fl;
+    fl.init(a.field);
+    const bool noise = a.cfg.ms && sa[12] > 0.0;
+    // start-state directions loc0, loc1, phi, theta, q/p (t only shifts t)
+#pragma unroll 1
+    for (int dir = 0; dir < 5; ++dir) {
+        D x[6];
+        {
+            double xv[6];
+            load_rows(xsrc, xs, xv);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                x[i] = D(xv[i]);
+                x[i].d[0] = (i == dir) ? 1.0 : 0.0;
+            }
+        }
+        double acc = 0.0;
+        if (noise) {
+            D q22, q33;
+            highland_t<D, double>(sa, x, a.cfg.mass, &q22, &q33);
+            acc += w[(V_Q + 0) * TILE] * q22.d[0] + w[(V_Q + 1) * TILE] * q33.d[0];
+        }
+        D xp[6], F[25];
+        int tr;
+        transport_t<D, D, FK, double, double>(fl, a.field, a.cfg, sa, sb, x, xp, F, &tr);
+        acc += contract(w, xp, F);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) xb[i] += (i == dir) ? acc : 0.0;
+        phase_boundary();
+    }
+    xb[5] += w[(V_XP + 5) * TILE];
+    // alignment of the start surface
+#pragma unroll 1
+    for (int p = 0; p < 6; ++p) {
+        D x[6];
+        {
+            double xv[6];
+            load_rows(xsrc, xs, xv);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) x[i] = D(xv[i]);
+        }
+        D sad[SURF_STRIDE];
+        surface_tangent<1>(sa, p, sad, 0);
+        double acc = 0.0;
+        if (noise) {
+            D q22, q33;
+            highland_t<D, D>(sad, x, a.cfg.mass, &q22, &q33);
+            acc += w[(V_Q + 0) * TILE] * q22.d[0] + w[(V_Q + 1) * TILE] * q33.d[0];
+        }
+        D xp[6], F[25];
+        int tr;
+        transport_t<D, D, FK, D, double>(fl, a.field, a.cfg, sad, sb, x, xp, F, &tr);
+        acc += contract(w, xp, F);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) ga[i] += (i == p) ? acc : 0.0;
+        phase_boundary();
+    }
+    // alignment of the target surface
+#pragma unroll 1
+    for (int p = 0; p < 6; ++p) {
+        D x[6];
+        {
+            double xv[6];
+            load_rows(xsrc, xs, xv);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) x[i] = D(xv[i]);
+        }
+        D sbd[SURF_STRIDE];
+        surface_tangent<1>(sb, p, sbd, 0);
+        D xp[6], F[25];
+        int tr;
+        transport_t<D, D, FK, double, D>(fl, a.field, a.cfg, sa, sbd, x, xp, F, &tr);
+        const double acc = contract(w, xp, F);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) gb[i] += (i == p) ? acc : 0.0;
+        phase_boundary();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward sweep
+// ---------------------------------------------------------------------------
+template <int FK>
+__device__ void vjp_bwd(const VjpArgs& a, const double* __restrict__ sm, double* wl, int t, int o, int n) {
+    const int64_t H = a.n_hits, N = a.n_tracks;
+    const double chi2b = a.g_chi2 ? a.g_chi2[t] : 0.0;
+    double xs[6], xsb[6], xfb[6], Cfb[21], aab[6];
+    {
+        const double* w = wl + (n - 1) * (NCV * TILE);
+        ld(w, V_XF, xs);
+        ld(w, V_U, xsb);
+        if (a.g_par) {
+            double gp[6];
+            load_rows(a.g_par + o + n - 1, H, gp);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) xsb[i] += gp[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) { xfb[i] = 0.0; aab[i] = 0.0; }
+#pragma unroll
+    for (int q = 0; q < 21; ++q) Cfb[q] = 0.0;
+
+    for (int k = n - 1; k >= 0; --k) {
+        double* w = wl + k * (NCV * TILE);
+        const double* wp = w - NCV * TILE;           // slot k-1 (used only for k > 0)
+        const int s = a.sid[o + k];
+        const int prev = k > 0 ? a.sid[o + k - 1] : a.seed_sid;
+        double xpb[6], Cpb[21], wv[6];
+        // ---- update adjoint, and w = Cp^-1 (xs_k - xp_k) ----
+        {
+            double xp[6], Cp[21], m[2], V[3], mb[2];
+            ld(w, V_XP, xp);
+            ld(w, V_CP, Cp);
+            ld(w, V_U, xpb);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                xpb[i] = -xpb[i];                     // from the smoother: -A^T xsb_{k-1}
+                xfb[i] += xsb[i];
+                wv[i] = xs[i] - xp[i];
+            }
+            wv[2] = wrap_phi(wv[2]);
+#pragma unroll
+            for (int q = 0; q < 21; ++q) Cpb[q] = 0.0;
+            load_rows(a.loc + o + k, H, m);
+            load_rows(a.cov + o + k, H, V);
+            update_vjp(xp, Cp, m, V, xfb, Cfb, chi2b, xpb, Cpb, mb);
+            store_rows(a.g_meas + o + k, H, mb);
+            double L[21], id[6];
+            chol6(Cp, L, id);
+            chol_solve6(L, id, wv);
+        }
+        phase_boundary();
+        // ---- xsb_{k-1} ----
+        double av[6];
+        if (k > 0) {
+            ld(wp, V_U, av);
+            if (a.g_par) {
+                double gp[6];
+                load_rows(a.g_par + o + k - 1, H, gp);
+#pragma unroll
+                for (int i = 0; i < 6; ++i) av[i] += gp[i];
+            }
+        } else if (a.g_tgt) {
+            load_rows(a.g_tgt + t, N, av);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) av[i] = 0.0;
+        }
+        // ---- smoother-gain adjoint and xs_{k-1} ----
+        double C[21], F[25], Cb[21], Fb[25];
+        if (k > 0) ld(wp, V_CF, C);
+        else load_rows(a.seed_cov + t, N, C);
+        ld(w, V_F, F);
+#pragma unroll
+        for (int q = 0; q < 21; ++q) Cb[q] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 25; ++q) Fb[q] = 0.0;
+        {
+            double y[6], z[6], u[6], xn[6], xprev[6];
+            symv(C, av, y);
+            ftw(F, wv, z);
+            ld(w, V_U, u);
+            gain_vjp_rank1(av, wv, z, y, u, Cb, Fb, Cpb);
+            if (k > 0) ld(wp, V_XF, xprev);
+            else load_rows(a.seed + t, N, xprev);
+            symv(C, z, xn);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) xn[i] += xprev[i];
+            xn[2] = wrap_phi(xn[2]);
+            st(w, V_XF, xn);                          // xs_{k-1}
+        }
+        phase_boundary();
+        // ---- covariance-transport adjoint ----
+        {
+            double q[2], CQb[21];
+            ld(w, V_Q, q);
+            C[sy(2, 2)] += q[0];
+            C[sy(3, 3)] += q[1];
+            covtransport_vjp(F, C, Cpb, Fb, CQb);
+#pragma unroll
+            for (int i = 0; i < 21; ++i) Cb[i] += CQb[i];
+            const double qb[2] = {CQb[sy(2, 2)], CQb[sy(3, 3)]};
+            st(w, V_Q, qb);
+        }
+        st(w, V_XP, xpb);
+        st(w, V_F, Fb);
+        st(w, V_CP, Cb);
+        st(w, V_U, av);
+        // hit k's surface receives aab (from gap k+1, where it was the start)
+        // now and gb (gap k, where it is the target) below
+        store_rows(a.contrib + o + k, a.n_items, aab);
+        phase_boundary();
+        // ---- propagation adjoint (dual-number recompute) ----
+        double xb[6], ga[6], gb[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) { xb[i] = 0.0; ga[i] = 0.0; gb[i] = 0.0; }
+        if (k > 0) gap_vjp<FK>(a, sm + prev * SURF_STRIDE, sm + s * SURF_STRIDE, wp + V_XF * TILE, TILE, w, xb, ga, gb);
+        else gap_vjp<FK>(a, sm + prev * SURF_STRIDE, sm + s * SURF_STRIDE, a.seed + t, N, w, xb, ga, gb);
+        {
+            double c[6];
+            load_rows(a.contrib + o + k, a.n_items, c);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) c[i] += gb[i];
+            store_rows(a.contrib + o + k, a.n_items, c);
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            aab[i] = ga[i];
+            xfb[i] = xb[i];
+        }
+        ld(w, V_CP, Cfb);
+        ld(w, V_XF, xs);
+        ld(w, V_U, xsb);
+        phase_boundary();
+    }
+    if (a.g_seed) {
+        double g[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) g[i] = xsb[i] + xfb[i];
+        store_rows(a.g_seed + t, N, g);
+    }
+    store_rows(a.contrib + H + t, a.n_items, aab);
+}
+
+template <int FK>
+__device__ void vjp_one(const VjpArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
+    const int64_t H = a.n_hits, N = a.n_tracks;
+    int o, n;
+    int status = check_track(a.off, a.sid, a.loc, a.cov, a.seed, a.seed_cov, H, N, a.n_surf, a.max_hits, t, o, n);
+    double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
+    if (status == ST_OK) status = vjp_fwd<FK>(a, sm, wl, t, o, n);
+    if (status == ST_OK) {
+        vjp_bwd<FK>(a, sm, wl, t, o, n);
+    } else {
+        const double nan = __longlong_as_double(0x7ff8000000000000LL);
+        for (int k = 0; k < n; ++k) fill_rows<2>(a.g_meas + o + k, H, nan);
+        if (a.g_seed) fill_rows<6>(a.g_seed + t, N, nan);
+    }
+    a.status[t] = (uint8_t)status;
+}
+
+template <int FK, bool SORTED>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) k_vjp(VjpArgs a) {
+    extern __shared__ double sm[];
+    stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, sm);
+    const int lane = threadIdx.x & (TILE - 1);
+    int iter = 0;
+    for (;;) {
+        const int tile = next_tile<SORTED>(a.tile_counter, iter);
+        if (tile >= a.n_tiles) break;
+        const int64_t i = (int64_t)tile * TILE + lane;
+        if (i < a.n_tracks) vjp_one<FK>(a, sm, i, SORTED ? a.order[i] : (int)i);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic alignment reduction
+// ---------------------------------------------------------------------------
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__device__ inline double readlane_f64(double v, int j) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), j);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), j);
+    return __hiloint2double(hi, lo);
+}
+
+// One wave per chunk of items: lanes load 64 items at a time (coalesced),
+// then the items are added one after another, in item order, into an LDS
+// table [S][6] (lane c < 6 adds component c).  The table is the chunk's
+// partial sum.
+__global__ void __launch_bounds__(64) k_align_partial(const double* contrib, int64_t n_items, int64_t H,
+                                                      const int32_t* sid, int seed_sid, int S, int64_t chunk,
+                                                      double* partial) {
+    extern __shared__ double tab[];
+    const int lane = threadIdx.x;
+    for (int i = lane; i < S * 6; i += 64) tab[i] = 0.0;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t b1 = b0 + chunk < n_items ? b0 + chunk : n_items;
+    for (int64_t base = b0; base < b1; base += 64) {
+        const int64_t i = base + lane;
+        double v[6];
+        int s = -1;
+        if (i < b1) {
+            s = i < H ? sid[i] : seed_sid;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) v[c] = contrib[c * n_items + i];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) v[c] = 0.0;
+        }
+        const int cnt = (int)(b1 - base < 64 ? b1 - base : 64);
+        for (int j = 0; j < cnt; ++j) {
+            const int sj = __builtin_amdgcn_readlane(s, j);
+            double vj = 0.0;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const double t = readlane_f64(v[c], j);
+                vj = lane == c ? t : vj;
+            }
+            if (lane < 6 && sj >= 0 && sj < S) tab[sj * 6 + lane] += vj;
+        }
+    }
+    __syncthreads();
+    for (int i = lane; i < S * 6; i += 64) partial[(int64_t)blockIdx.x * S * 6 + i] = tab[i];
+}
+
+// One workgroup per surface: each thread sums a fixed stride of chunks, then
+// a fixed tree in LDS.  The rotation part is converted from rotations about
+// the aligned surface's own axes (e1, e2, e3) to (alpha, beta, gamma):
+//   R(a) = R0 Rx(alpha) Ry(beta) Rz(gamma), R^T dR/dalpha = [Rz^T Ry^T e_x]x,
+//   R^T dR/dbeta = [Rz^T e_y]x, R^T dR/dgamma = [e_z]x.
+__global__ void __launch_bounds__(256) k_align_final(const double* partial, int n_chunks, int S,
+                                                     const double* align, double* g_align) {
+    __shared__ double red[6][256];
+    const int s = blockIdx.x;
+    const int tid = threadIdx.x;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c = tid; c < n_chunks; c += 256)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) acc[q] += partial[(int64_t)c * S * 6 + s * 6 + q];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) red[q][tid] = acc[q];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) red[q][tid] += red[q][tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double g[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) g[q] = red[q][0];
+        if (align) {
+            double sb, cb, sg, cg;
+            sincos(align[4 * S + s], &sb, &cb);
+            sincos(align[5 * S + s], &sg, &cg);
+            const double e1 = g[3], e2 = g[4], e3 = g[5];
+            g[3] = cg * cb * e1 - sg * cb * e2 + sb * e3;
+            g[4] = sg * e1 + cg * e2;
+            g[5] = e3;
+        }
+#pragma unroll
+        for (int q = 0; q < 6; ++q) g_align[q * S + s] = g[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct VjpLayout {
+    int64_t tile_doubles;
+    int64_t n_items;
+    int n_chunks;
+    int64_t chunk;
+    size_t contrib_off, partial_off, status_off, order_off, counts_off, counter_off, total;
+};
+
+VjpLayout vjp_layout(int64_t n_tracks, int64_t n_hits, int max_hits, int n_surf) {
+    VjpLayout L;
+    const int64_t tiles = n_tracks > 0 ? (n_tracks + TILE - 1) / TILE : 1;
+    L.tile_doubles = (int64_t)max_hits * NCV * TILE;
+    L.n_items = n_hits + n_tracks;
+    int64_t nc = (L.n_items + 511) / 512;
+    nc = nc < 1 ? 1 : (nc > 2048 ? 2048 : nc);
+    L.n_chunks = (int)nc;
+    L.chunk = (L.n_items + nc - 1) / nc;
+    if (L.chunk < 1) L.chunk = 1;
+    size_t p = (size_t)tiles * L.tile_doubles * sizeof(double);
+    L.contrib_off = align_up(p, 256);
+    p = L.contrib_off + (size_t)6 * L.n_items * sizeof(double);
+    L.partial_off = align_up(p, 256);
+    p = L.partial_off + (size_t)L.n_chunks * n_surf * 6 * sizeof(double);
+    L.status_off = align_up(p, 256);
+    p = L.status_off + (size_t)(n_tracks > 0 ? n_tracks : 1);
+    L.order_off = align_up(p, 256);
+    L.counts_off = align_up(L.order_off + (size_t)tiles * TILE * 4, 256);
+    L.counter_off = align_up(L.counts_off + NBINS * 4, 256);
+    L.total = align_up(L.counter_off + 256, 256);
+    return L;
+}
+
+template <int FK, bool SORTED>
+hipError_t launch_vjp(const VjpArgs& a, hipStream_t stream) {
+    const size_t shm = (size_t)a.n_surf * SURF_STRIDE * sizeof(double);
+    int grid = a.n_tiles;
+    if (SORTED) {
+        const int persistent = num_cu() * 4;          // one wave per SIMD
+        grid = grid < persistent ? grid : persistent;
+    }
+    hipLaunchKernelGGL((k_vjp<FK, SORTED>), dim3(grid), dim3(TILE), shm, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t kf_vjp_workspace_bytes(const kf_config* cfg, const kf_measurements* meas, int32_t n_surfaces) {
+    (void)cfg;
+    if (!meas || meas->n_tracks < 0 || meas->n_hits < 0 || meas->max_hits < 1 || meas->max_hits > KF_MAX_HITS ||
+        n_surfaces < 1 || n_surfaces > KF_MAX_SURFACES)
+        return 0;
+    return vjp_layout(meas->n_tracks, meas->n_hits, meas->max_hits, n_surfaces).total;
+}
+
+int kf_fit_tracks_vjp(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field,
+                      const kf_measurements* meas, const kf_seeds* seeds, const kf_cotangents* cot,
+                      const kf_gradients* grad, void* workspace, size_t workspace_bytes, void* stream_) {
+    if (!cot || !grad) return KF_E_NULL;
+    int rc = validate_inputs(cfg, surf, field, meas, seeds);
+    if (rc != KF_OK) return rc;
+    if (meas->n_hits > 0 && !grad->meas) return KF_E_NULL;
+    const VjpLayout L = vjp_layout(meas->n_tracks, meas->n_hits, meas->max_hits, surf->n);
+    if (!workspace) return KF_E_WS;
+    if (workspace_bytes < L.total) return KF_E_WS;
+    hipStream_t stream = (hipStream_t)stream_;
+    char* wsb = (char*)workspace;
+    const int S = surf->n;
+    if (meas->n_tracks == 0) {
+        if (grad->align) {
+            hipLaunchKernelGGL(k_fill_f64, dim3((6 * S + 255) / 256), dim3(256), 0, stream, grad->align,
+                               (int64_t)6 * S, 0.0);
+            if (hipGetLastError() != hipSuccess) return KF_E_HIP;
+        }
+        return KF_OK;
+    }
+    num_cu();
+    VjpArgs a;
+    memset(&a, 0, sizeof(a));
+    a.n_tracks = meas->n_tracks;
+    a.n_surf = S;
+    a.seed_sid = seeds->surface_id;
+    a.max_hits = meas->max_hits;
+    a.n_hits = meas->n_hits;
+    a.tile_doubles = L.tile_doubles;
+    a.off = meas->hit_offsets;
+    a.sid = meas->surface_id;
+    a.loc = meas->loc;
+    a.cov = meas->cov;
+    a.center = surf->center;
+    a.rot = surf->rot;
+    a.x0 = surf->x_over_X0;
+    a.align = surf->align;
+    a.seed = seeds->par;
+    a.seed_cov = seeds->cov;
+    a.field = field_def(field);
+    a.cfg = cfg_def(cfg);
+    a.g_chi2 = cot->chi2;
+    a.g_par = cot->par;
+    a.g_tgt = cot->tgt_par;
+    a.g_meas = grad->meas;
+    a.g_seed = grad->seed;
+    a.status = grad->status ? grad->status : (uint8_t*)(wsb + L.status_off);
+    a.contrib = (double*)(wsb + L.contrib_off);
+    a.n_items = L.n_items;
+    a.ws = (double*)wsb;
+    a.order = (const int32_t*)(wsb + L.order_off);
+    a.tile_counter = (int32_t*)(wsb + L.counter_off);
+    a.n_tiles = (int)((a.n_tracks + TILE - 1) / TILE);
+
+    const int sched = cfg->schedule == KF_SCHED_DIRECT ? KF_SCHED_DIRECT : KF_SCHED_SORTED;
+    {
+        const int64_t nc = 6 * L.n_items;
+        hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, stream, a.contrib, nc, 0.0);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return KF_E_HIP;
+    if (sched == KF_SCHED_SORTED) {
+        e = enqueue_length_sort(a.off, a.n_tracks, a.max_hits, (int32_t*)(wsb + L.counts_off), (int32_t*)a.order,
+                                a.tile_counter, stream);
+        if (e != hipSuccess) return KF_E_HIP;
+        e = field->kind == KF_FIELD_UNIFORM ? launch_vjp<FIELD_UNIFORM, true>(a, stream)
+                                            : launch_vjp<FIELD_SOLENOID, true>(a, stream);
+    } else {
+        e = field->kind == KF_FIELD_UNIFORM ? launch_vjp<FIELD_UNIFORM, false>(a, stream)
+                                            : launch_vjp<FIELD_SOLENOID, false>(a, stream);
+    }
+    if (e != hipSuccess) return KF_E_HIP;
+    if (grad->align) {
+        double* partial = (double*)(wsb + L.partial_off);
+        hipLaunchKernelGGL(k_align_partial, dim3(L.n_chunks), dim3(64), (size_t)S * 6 * sizeof(double), stream,
+                           (const double*)a.contrib, L.n_items, (int64_t)meas->n_hits, meas->surface_id,
+                           seeds->surface_id, S, L.chunk, partial);
+        hipLaunchKernelGGL(k_align_final, dim3(S), dim3(256), 0, stream, (const double*)partial, L.n_chunks, S,
+                           surf->align, grad->align);
+        if (hipGetLastError() != hipSuccess) return KF_E_HIP;
+    }
+    return KF_OK;
+}
+
+}  // extern "C"

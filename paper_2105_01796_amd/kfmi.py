@@ -4,14 +4,15 @@ Every step of the fit runs in the HIP library.  PyTorch provides device
 memory and the current stream.  If the library is not built or cannot be
 loaded, every call raises: there is no CPU fallback.
 
-Names mirror include/kf.h: kf_fit_tracks, kf_workspace_bytes, kf_status_string,
-kf_version.
+Names mirror include/kf.h: kf_fit_tracks, kf_fit_tracks_vjp, kf_workspace_bytes,
+kf_vjp_workspace_bytes, kf_status_string, kf_version.  TrackFit is the
+torch.autograd.Function over the fit: its backward is kf_fit_tracks_vjp.
 """
 from __future__ import annotations
 
 import ctypes as C
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 import torch
 
@@ -29,7 +30,8 @@ KF_MAX_HITS = 64
 
 
 class kf_surfaces(C.Structure):
-    _fields_ = [("n", C.c_int32), ("center", C.c_void_p), ("rot", C.c_void_p), ("x_over_X0", C.c_void_p)]
+    _fields_ = [("n", C.c_int32), ("center", C.c_void_p), ("rot", C.c_void_p), ("x_over_X0", C.c_void_p),
+                ("align", C.c_void_p)]
 
 
 class kf_field(C.Structure):
@@ -59,9 +61,17 @@ class kf_outputs(C.Structure):
                 ("filt_par", C.c_void_p), ("filt_cov", C.c_void_p)]
 
 
+class kf_cotangents(C.Structure):
+    _fields_ = [("chi2", C.c_void_p), ("par", C.c_void_p), ("tgt_par", C.c_void_p)]
+
+
+class kf_gradients(C.Structure):
+    _fields_ = [("meas", C.c_void_p), ("align", C.c_void_p), ("seed", C.c_void_p), ("status", C.c_void_p)]
+
+
 # every symbol include/kf.h declares
 EXPORTS = ("kf_version", "kf_status_string", "kf_workspace_bytes", "kf_fit_tracks", "kf_plan_create",
-           "kf_plan_launch", "kf_plan_destroy", "kf_autotune")
+           "kf_plan_launch", "kf_plan_destroy", "kf_autotune", "kf_vjp_workspace_bytes", "kf_fit_tracks_vjp")
 
 _lib = None
 
@@ -91,6 +101,10 @@ def lib():
         L.kf_plan_destroy.argtypes = [P]
         L.kf_autotune.restype = C.c_int
         L.kf_autotune.argtypes = [P, P, P, P, P, P, P, C.c_size_t, P, P, C.POINTER(C.c_float)]
+        L.kf_vjp_workspace_bytes.restype = C.c_size_t
+        L.kf_vjp_workspace_bytes.argtypes = [P, P, C.c_int32]
+        L.kf_fit_tracks_vjp.restype = C.c_int
+        L.kf_fit_tracks_vjp.argtypes = [P, P, P, P, P, P, P, P, C.c_size_t, P]
         _lib = L
     return _lib
 
@@ -104,8 +118,8 @@ def kf_status_string(code: int) -> str:
 
 
 class KFError(RuntimeError):
-    def __init__(self, code):
-        super().__init__(f"kf_fit_tracks failed: {code} ({kf_status_string(code)})")
+    def __init__(self, code, what="kf_fit_tracks"):
+        super().__init__(f"{what} failed: {code} ({kf_status_string(code)})")
         self.code = code
 
 
@@ -136,6 +150,7 @@ class Batch:
     multiple_scattering: bool = False
     mass: float = 0.1056583755
     max_hits: int = 0             # 0: computed from hit_offsets
+    align: torch.Tensor | None = None   # (6, S) f64 alignment corrections, or None
 
     @property
     def n_tracks(self) -> int:
@@ -146,7 +161,7 @@ class Batch:
         return self.surface_id.numel()
 
     @classmethod
-    def from_event(cls, ev, device="cuda", detector=None) -> "Batch":
+    def from_event(cls, ev, device="cuda", detector=None, align=None) -> "Batch":
         det = detector if detector is not None else ev.detector
         f64, i32 = torch.float64, torch.int32
         counts = (ev.hit_offsets[1:] - ev.hit_offsets[:-1]) if ev.n_tracks else []
@@ -157,7 +172,8 @@ class Batch:
                    rot=_dev(det.rot, f64, device), x_over_X0=_dev(det.x_over_X0, f64, device),
                    field_kind=int(ev.field.kind), b0=tuple(float(b) for b in ev.field.b0),
                    field_a=float(ev.field.a), multiple_scattering=bool(ev.multiple_scattering),
-                   mass=float(ev.mass), max_hits=int(max(counts)) if len(counts) else 1)
+                   mass=float(ev.mass), max_hits=int(max(counts)) if len(counts) else 1,
+                   align=None if align is None else _dev(align, f64, device))
 
 
 @dataclass
@@ -187,6 +203,27 @@ class Options:
     split_smoother: int = 0
 
 
+def _max_hits(b: Batch) -> int:
+    max_hits = b.max_hits
+    if max_hits <= 0:
+        max_hits = int((b.hit_offsets[1:] - b.hit_offsets[:-1]).max().item()) if b.n_tracks else 1
+    return max(1, min(max_hits, KF_MAX_HITS))
+
+
+def _structs(b: Batch, opt: Options):
+    """kf_config, kf_surfaces, kf_field, kf_measurements, kf_seeds for a batch."""
+    cfg = kf_config(opt.precision, int(b.multiple_scattering), b.mass, opt.rk_tol, opt.land_tol, opt.max_steps,
+                    opt.schedule, opt.block, opt.waves_per_cu, opt.occupancy, opt.split_smoother)
+    if b.align is not None and tuple(b.align.shape) != (6, b.center.shape[1]):
+        raise ValueError("align must have shape (6, S)")
+    surf = kf_surfaces(b.center.shape[1], _ptr(b.center), _ptr(b.rot), _ptr(b.x_over_X0), _ptr(b.align))
+    field = kf_field(b.field_kind, (C.c_double * 3)(*b.b0), b.field_a)
+    meas = kf_measurements(b.n_tracks, _max_hits(b), b.n_hits, _ptr(b.hit_offsets), _ptr(b.surface_id),
+                           _ptr(b.loc), _ptr(b.cov))
+    seeds = kf_seeds(_ptr(b.seed_par), _ptr(b.seed_cov), b.seed_surface)
+    return cfg, surf, field, meas, seeds
+
+
 class Plan:
     """Marshalled arguments + workspace for repeated fits of one batch shape.
 
@@ -197,18 +234,7 @@ class Plan:
         dev = b.loc.device
         N, H = b.n_tracks, b.n_hits
         self.batch, self.opt = b, opt
-        max_hits = b.max_hits
-        if max_hits <= 0:
-            max_hits = int((b.hit_offsets[1:] - b.hit_offsets[:-1]).max().item()) if N else 1
-        max_hits = max(1, min(max_hits, KF_MAX_HITS))
-        self.cfg = kf_config(opt.precision, int(b.multiple_scattering), b.mass, opt.rk_tol, opt.land_tol,
-                             opt.max_steps, opt.schedule, opt.block, opt.waves_per_cu, opt.occupancy,
-                             opt.split_smoother)
-        self.surf = kf_surfaces(b.center.shape[1], _ptr(b.center), _ptr(b.rot), _ptr(b.x_over_X0))
-        self.field = kf_field(b.field_kind, (C.c_double * 3)(*b.b0), b.field_a)
-        self.meas = kf_measurements(N, max_hits, H, _ptr(b.hit_offsets), _ptr(b.surface_id), _ptr(b.loc),
-                                    _ptr(b.cov))
-        self.seeds = kf_seeds(_ptr(b.seed_par), _ptr(b.seed_cov), b.seed_surface)
+        self.cfg, self.surf, self.field, self.meas, self.seeds = _structs(b, opt)
         f64 = dict(dtype=torch.float64, device=dev)
         if out is None:
             out = Fit(torch.empty((6, H), **f64), torch.empty((21, H), **f64), torch.empty((6, N), **f64),
@@ -289,3 +315,88 @@ def kf_fit_tracks(batch: Batch, opt: Options | None = None, extras: bool = False
     """Filter + RTS smoother of every track in `batch` on its device (async on
     the current stream)."""
     return Plan(batch, opt, extras).run()
+
+
+# ---------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------
+@dataclass
+class Grad:
+    meas: torch.Tensor                # (2, H) dL/d(loc0, loc1)
+    align: torch.Tensor | None        # (6, S) dL/d(alignment correction)
+    seed: torch.Tensor | None         # (6, N) dL/d(starting parameters)
+    status: torch.Tensor              # (N,) u8 status of the recomputed fit
+
+
+class VjpPlan:
+    """Marshalled arguments + workspace of kf_fit_tracks_vjp for one batch."""
+
+    def __init__(self, b: Batch, opt: Options | None = None, want_align: bool = True, want_seed: bool = False):
+        opt = opt or Options()
+        dev = b.loc.device
+        N, H, S = b.n_tracks, b.n_hits, b.center.shape[1]
+        self.batch, self.opt = b, opt
+        self.cfg, self.surf, self.field, self.meas, self.seeds = _structs(b, opt)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.grad = Grad(torch.empty((2, H), **f64), torch.empty((6, S), **f64) if want_align else None,
+                         torch.empty((6, N), **f64) if want_seed else None,
+                         torch.empty(N, dtype=torch.uint8, device=dev))
+        self.grads = kf_gradients(_ptr(self.grad.meas), _ptr(self.grad.align), _ptr(self.grad.seed),
+                                  _ptr(self.grad.status))
+        nbytes = lib().kf_vjp_workspace_bytes(C.byref(self.cfg), C.byref(self.meas), self.surf.n)
+        if nbytes == 0:
+            raise KFError(KF_E_SIZE, "kf_fit_tracks_vjp")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.ws_bytes = nbytes
+
+    def run(self, g_chi2=None, g_par=None, g_tgt=None, stream=None) -> Grad:
+        """Enqueue the VJP for cotangents (N,), (6, H), (6, N) (each may be None = 0)."""
+        dev = self.batch.loc.device
+        keep = [None if g is None else g.to(device=dev, dtype=torch.float64).contiguous()
+                for g in (g_chi2, g_par, g_tgt)]
+        cot = kf_cotangents(*(_ptr(g) for g in keep))
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        rc = lib().kf_fit_tracks_vjp(C.byref(self.cfg), C.byref(self.surf), C.byref(self.field),
+                                     C.byref(self.meas), C.byref(self.seeds), C.byref(cot), C.byref(self.grads),
+                                     _ptr(self.ws), self.ws_bytes, C.c_void_p(stream.cuda_stream))
+        if rc != KF_OK:
+            raise KFError(rc, "kf_fit_tracks_vjp")
+        self._keep = keep          # cotangents must outlive the enqueued work
+        return self.grad
+
+
+def kf_fit_tracks_vjp(batch: Batch, g_chi2=None, g_par=None, g_tgt=None, opt: Options | None = None,
+                      want_align: bool = True, want_seed: bool = False) -> Grad:
+    """dL/d(measurements, alignment, seeds) for L = g_chi2 . chi2 + g_par . par
+    + g_tgt . tgt_par (async on the current stream)."""
+    return VjpPlan(batch, opt, want_align, want_seed).run(g_chi2, g_par, g_tgt)
+
+
+class TrackFit(torch.autograd.Function):
+    """(loc (2, H), align (6, S) or None) -> (smoothed par (6, H), target par
+    (6, N), chi2 (N,)) by kf_fit_tracks; backward by kf_fit_tracks_vjp (FP64
+    whatever opt.precision says).  Every other input of the batch is a
+    constant."""
+
+    @staticmethod
+    def forward(ctx, loc, align, batch: Batch, opt):
+        b = replace(batch, loc=loc.detach().to(torch.float64).contiguous(),
+                    align=None if align is None else align.detach().to(torch.float64).contiguous())
+        out = Plan(b, opt).run()
+        ctx.batch, ctx.opt = b, opt
+        ctx.has_align = align is not None
+        return out.par, out.tgt_par, out.chi2
+
+    @staticmethod
+    def backward(ctx, g_par, g_tgt, g_chi2):
+        want_align = ctx.has_align and ctx.needs_input_grad[1]
+        g = VjpPlan(ctx.batch, ctx.opt, want_align=want_align).run(g_chi2, g_par, g_tgt)
+        return (g.meas if ctx.needs_input_grad[0] else None), (g.align if want_align else None), None, None
+
+
+def fit_tracks(batch: Batch, loc: torch.Tensor | None = None, align: torch.Tensor | None = None,
+               opt: Options | None = None):
+    """Differentiable fit: returns (par, tgt_par, chi2) with gradients flowing
+    to `loc` (defaults to batch.loc) and `align` (defaults to batch.align)."""
+    return TrackFit.apply(batch.loc if loc is None else loc, batch.align if align is None else align, batch, opt)

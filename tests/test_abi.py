@@ -117,7 +117,7 @@ def test_argument_validation(kf):
     # workspace
     assert _call(kf, *a, ws=None) == kf.KF_E_WS
     need = kf.lib().kf_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n)
-    assert need >= 10 * 10 * 79 * 8
+    assert need >= 64 * 10 * 90 * 8          # one 64-track tile x 10 hits x 90 doubles
     assert _call(kf, *a, nbytes=need - 1) == kf.KF_E_WS
     # nothing to do: no tracks is OK without touching the device
     meas.n_tracks = 0
@@ -134,3 +134,45 @@ def test_workspace_size_grows_with_tracks_and_hits(kf):
     assert sizes[0] == sizes[1] < sizes[2] < sizes[3]
     m = kf.kf_measurements(10, 0, 0, None, None, None, None)
     assert L.kf_workspace_bytes(C.byref(cfg), C.byref(m), 31) == 0
+
+
+def _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad, ws=C.c_void_p(0x2000), nbytes=None):
+    L = kf.lib()
+    if nbytes is None:
+        nbytes = L.kf_vjp_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n)
+    return L.kf_fit_tracks_vjp(C.byref(cfg), C.byref(surf), C.byref(fld), C.byref(meas), C.byref(seeds),
+                               C.byref(cot) if cot is not None else None,
+                               C.byref(grad) if grad is not None else None, ws, nbytes, None)
+
+
+def test_vjp_argument_validation(kf):
+    cfg, surf, fld, meas, seeds, _ = _args(kf)
+    fake = C.c_void_p(0x1000)
+    cot = kf.kf_cotangents(fake, None, None)
+    grad = kf.kf_gradients(fake, fake, None, None)
+    L = kf.lib()
+    assert L.kf_fit_tracks_vjp(None, None, None, None, None, None, None, None, 0, None) == kf.KF_E_NULL
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, None, grad) == kf.KF_E_NULL
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, None) == kf.KF_E_NULL
+    cfg.precision = 7
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_ENUM
+    cfg.precision = 0
+    fld.kind = 3
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_ENUM
+    fld.kind = 0
+    cfg.land_tol = -1.0
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_VALUE
+    cfg.land_tol = 1e-6
+    surf.n = kf.KF_MAX_SURFACES + 1
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad, nbytes=1 << 40) == kf.KF_E_SIZE
+    surf.n = 11
+    grad.meas = None                       # required when there are hits
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_NULL
+    grad.meas = fake
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad, ws=None) == kf.KF_E_WS
+    need = L.kf_vjp_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n)
+    # per-hit state (87 doubles x max_hits per track slot) + alignment contributions (6 per hit and track)
+    assert need >= 64 * 10 * 87 * 8 + 6 * (100 + 10) * 8
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad, nbytes=need - 1) == kf.KF_E_WS
+    m = kf.kf_measurements(10, 0, 0, None, None, None, None)
+    assert L.kf_vjp_workspace_bytes(C.byref(cfg), C.byref(m), 11) == 0

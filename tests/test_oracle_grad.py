@@ -70,3 +70,48 @@ def test_chi2_gradient_envelope_theorem(oracle_lib):
     env = 2 * np.stack([(V[2] * res[0] - V[1] * res[1]) / det, (-V[1] * res[0] + V[0] * res[1]) / det])
     rel = np.abs(g_meas - env).max() / np.abs(env).max()
     assert rel < 1e-3
+
+
+def _random_alignment(S, seed, shift=0.05, angle=2e-3):
+    rng = np.random.default_rng(seed)
+    A = np.zeros((6, S))
+    A[:3] = rng.normal(0.0, shift, (3, S))
+    A[3:] = rng.normal(0.0, angle, (3, S))
+    return A
+
+
+def test_alignment_input_equals_misaligned_detector(oracle_lib):
+    """The oracle's alignment input builds the same surfaces as the generator's
+    independent numpy composition c + d, R Rx Ry Rz."""
+    ev = synth.make_config(4, 40, seed=4006)
+    A = _random_alignment(ev.detector.n, 8)
+    r1 = oracle_lib.fit(ev, align=A)
+    r2 = oracle_lib.fit(ev, detector=synth.misalign(ev.detector, A))
+    assert np.array_equal(r1.status, r2.status) and np.all(r1.status == 0)
+    for name in ("par", "tgt_par", "chi2", "cov"):
+        a, b = getattr(r1, name), getattr(r2, name)
+        assert np.allclose(a, b, rtol=1e-10, atol=1e-12), name
+
+
+def test_vjp_at_nonzero_alignment_matches_central_differences(oracle_lib):
+    """g_align is the derivative with respect to the alignment correction at
+    its given (nonzero) value, not about the shifted surfaces' own axes."""
+    ev = synth.make_config(2, 3, seed=4007)
+    A = _random_alignment(ev.detector.n, 9)
+    rng = np.random.default_rng(10)
+    g = (np.ones(ev.n_tracks), rng.standard_normal((6, ev.n_hits)), rng.standard_normal((6, ev.n_tracks)))
+    g_meas, g_align, _ = oracle_lib.fit_vjp(ev, *g, align=A)
+    scale = np.abs(g_align).max(axis=1)
+    for s in [0, 4, 9]:
+        for c in range(6):
+            h = 1e-6
+            Ap, Am = A.copy(), A.copy()
+            Ap[c, s] += h
+            Am[c, s] -= h
+            fd = (_L(oracle_lib, ev, *g, align=Ap) - _L(oracle_lib, ev, *g, align=Am)) / (2 * h)
+            assert abs(fd - g_align[c, s]) < 1e-5 * max(abs(g_align[c, s]), 1e-2 * scale[c]), (s, c, fd, g_align[c, s])
+    # the rotation gradient differs from the one about the surfaces' own axes
+    # (the oracle at zero correction on the pre-aligned detector)
+    _, g_body, _ = oracle_lib.fit_vjp(ev, *g, detector=synth.misalign(ev.detector, A))
+    assert np.allclose(g_body[:3], g_align[:3], rtol=1e-6, atol=1e-9 * np.abs(g_align).max())
+    assert not np.allclose(g_body[3:5], g_align[3:5], rtol=1e-6, atol=0)
