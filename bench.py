@@ -5,16 +5,23 @@ Workload (default): 1e5 muon tracks, 10 planes normal to x at x = 30..300 mm,
 uniform Bz = 2 T, 0.5 % X0 per plane with Highland multiple scattering,
 pT 1-10 GeV, |phi| < 0.1, |eta| < 0.2, 50 um hits; seeded synthetic data.
 One step = one filter + RTS-smoother pass over all tracks (inputs resident
-in HBM).  Prints one JSON line.
+in HBM).  Prints one JSON line.  Besides the FP64 headline it times the
+mixed-precision fit and a fit + adjoint step (kf_fit_tracks then
+kf_fit_tracks_vjp with chi2, smoothed-parameter and target cotangents).
 
 The roofline entry uses the oracle's count of non-trivial floating-point
 operations per track (add/sub, mul, div, sqrt) times the tracks in a launch,
 divided by the fit launch's average duration measured with HIP events on the
-launch stream; the peak is MI355X's FP64 vector rate.
+launch stream; the peak is MI355X's FP64 vector rate.  `traffic` is the HBM
+traffic of one fit launch from the committed counter summary
+profiles/k_fwd_c2_1e5_traffic.txt (FETCH_SIZE + WRITE_SIZE, each scaled by
+the same counter's reading for a plain copy of known size), reported only
+while the fit sources still hash to the value recorded there.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,6 +41,38 @@ WORKLOADS = {
     4: "1e5 tracks, 10 planes, Bz=2 T, misaligned truth",
     5: "solenoid B=2T(1-0.1(z/1m)^2), 30 planes, pT log-uniform 0.5-100 GeV, |eta|<2.5, ragged 8-30 hits",
 }
+
+
+FIT_SOURCES = ("kf_fit.hip", "kf_common.hpp", "kf_device.hpp", "kf_dual.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fwd_c2_1e5_traffic.txt")
+
+
+def fit_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in FIT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2105_01796_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(config: int, n_tracks: int):
+    """HBM bytes per FP64 fit launch from the counter summary, or None when the
+    summary is missing, for another workload, or older than the fit sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv.get("source_hash") != fit_source_hash():
+            return None
+        if int(kv["config"]) != config or int(kv["tracks"]) != n_tracks:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def host_threads() -> int:
@@ -78,6 +117,9 @@ def main():
     ap.add_argument("--occupancy", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the fit + adjoint leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 512 MiB device copy first (reference for HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
@@ -102,6 +144,13 @@ def main():
     base_opt = dict(schedule=args.schedule, block=args.block, occupancy=args.occupancy,
                     waves_per_cu=args.waves_per_cu)
 
+    if args.copy_calibration:
+        src = torch.empty(1 << 26, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # FP64 leg (the headline value)
     plan64 = kfmi.Plan(batch, kfmi.Options(precision=kfmi.KF_PREC_FP64, **base_opt))
     ms64, kms64, per64 = time_plan(plan64, args.steps, args.warmup)
@@ -115,6 +164,27 @@ def main():
         mixed = {"value": N / (msm * 1e-3), "ms_per_step": msm, "launch_ms": kmsm,
                  "speedup_vs_fp64": ms64 / msm}
 
+    adjoint = None
+    if not args.no_adjoint:
+        rng_g = np.random.default_rng(1)
+        g_chi2 = torch.ones(N, dtype=torch.float64, device=dev)
+        g_par = torch.as_tensor(rng_g.standard_normal((6, ev.n_hits)), device=dev)
+        g_tgt = torch.as_tensor(rng_g.standard_normal((6, N)), device=dev)
+        vjp = kfmi.VjpPlan(batch, kfmi.Options(), want_align=True, want_seed=True)
+
+        class FitAndAdjoint:
+            def run(self, stream):
+                plan64.run(stream)
+                vjp.run(g_chi2, g_par, g_tgt, stream=stream)
+
+        adj_steps = max(1, min(args.steps, 5))
+        msa, kmsa, _ = time_plan(FitAndAdjoint(), adj_steps, min(args.warmup, 1))
+        st_a = vjp.grad.status.cpu().numpy()
+        adjoint = {"value": N / (msa * 1e-3), "unit": "tracks/s", "ms_per_step": msa, "steps": adj_steps,
+                   "vjp_ms": msa - ms64, "tracks_ok": int((st_a == 0).sum()),
+                   "what": "kf_fit_tracks + kf_fit_tracks_vjp (d chi2, d smoothed params, d target params "
+                           "-> d measurements, d alignment of every plane, d seeds), FP64"}
+
     # algorithmic work per track (oracle operation count on a sample)
     import oracle
     rng = np.random.default_rng(0)
@@ -126,8 +196,9 @@ def main():
     achieved = flops / (kms64 * 1e-3) / 1e12
     io_bytes = ev.n_hits * (2 + 3) * 8 + ev.n_hits * 4 + (N + 1) * 4 + N * 27 * 8 \
         + ev.n_hits * 27 * 8 + N * 27 * 8 + N * (8 + 4 + 1)
+    traffic = recorded_traffic(args.config, N)
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                 "flops_per_track": flops_per_track, "hits_per_track": hits_per_track,
                 "io_bytes_per_launch": io_bytes, "io_GBs": io_bytes / (kms64 * 1e-3) / 1e9}
 
@@ -167,6 +238,7 @@ def main():
                    "launch_ms_min": min(per64), "tracks_ok": n_ok, "options": base_opt,
                    "gen_seconds": round(t_gen, 2)},
         "mixed": mixed,
+        "adjoint": adjoint,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
