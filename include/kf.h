@@ -153,8 +153,8 @@ const char *kf_version(void);
 const char *kf_status_string(int code);
 
 /* Bytes of workspace kf_fit_tracks needs for these sizes (0 on bad arguments).
- * Grows as n_tracks * max_hits * 90 doubles (filtered and predicted state and
- * covariance, smoother gain per hit) plus small per-track and per-tile tables. */
+ * Grows as n_tracks * max_hits * 52 doubles (predicted state and covariance and
+ * transport Jacobian per hit) plus small per-track and per-tile tables. */
 size_t kf_workspace_bytes(const kf_config *cfg, const kf_measurements *meas, int32_t n_surfaces);
 
 /* Filter + RTS smoother for every track (Sect. 2; Sect. 4.1; Sect. 4.3).

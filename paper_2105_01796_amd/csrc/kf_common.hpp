@@ -192,7 +192,15 @@ __device__ inline int next_tile(int32_t* counter, int& iter) {
 }
 
 // ---- sorted schedule: order tracks by hit count, longest first ----
-// counts[b] for b = 0..KF_MAX_HITS+1 (bin of n clipped), then positions.
+// A stable counting sort: tracks of equal length keep their input order, so a
+// tile holds consecutive tracks (their CSR outputs are neighbours in memory)
+// and the order is the same on every run.
+//   k_hist:    per-block histogram over the block's 256 tracks -> counts[bin][block]
+//   k_scan:    exclusive scan of counts in (bin, block) order -> first slot per (bin, block)
+//   k_scatter: rank of each track among the block's tracks of its bin (wave ballots)
+constexpr int NBINS = KF_MAX_HITS + 2;
+constexpr int SORT_BLOCK = 256;
+
 __global__ void k_zero_i32(int32_t* p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -205,67 +213,86 @@ __device__ inline int len_bin(const int32_t* off, int t, int max_hits) {
     return (max_hits + 1) - n;      // longest first
 }
 
-// Each workgroup builds its histogram in LDS and adds it to the global one
-// with one atomic per non-empty bin (equal lengths would otherwise serialise
-// every track on one address).
-constexpr int NBINS = KF_MAX_HITS + 2;
-
-__global__ void __launch_bounds__(256) k_hist(const int32_t* off, int N, int max_hits, int32_t* counts) {
+__global__ void __launch_bounds__(SORT_BLOCK) k_hist(const int32_t* off, int N, int max_hits, int n_blocks,
+                                                     int32_t* counts) {
     __shared__ int32_t h[NBINS];
     for (int i = threadIdx.x; i < NBINS; i += blockDim.x) h[i] = 0;
     __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < N) atomicAdd(&h[len_bin(off, t, max_hits)], 1);
     __syncthreads();
-    for (int i = threadIdx.x; i < NBINS; i += blockDim.x)
-        if (h[i]) atomicAdd(&counts[i], h[i]);
+    for (int i = threadIdx.x; i < NBINS; i += blockDim.x) counts[(int64_t)i * n_blocks + blockIdx.x] = h[i];
 }
 
-// exclusive scan of the NBINS (<= 256) bins by one workgroup of 256 threads
-__global__ void __launch_bounds__(256) k_scan(int32_t* counts) {
-    __shared__ int32_t s[256];
+// Exclusive scan of M counts by one workgroup of 1024 threads: each thread
+// sums a contiguous segment, the segment totals are scanned in LDS, then each
+// thread writes its segment's prefix sums.
+__global__ void __launch_bounds__(1024) k_scan(int32_t* counts, int64_t M) {
+    __shared__ int32_t s[1024];
     const int i = threadIdx.x;
-    const int own = i < NBINS ? counts[i] : 0;
+    const int64_t seg = (M + 1023) / 1024;
+    const int64_t a = i * seg, b = a + seg < M ? a + seg : M;
+    int32_t own = 0;
+    for (int64_t k = a; k < b; ++k) own += counts[k];
     s[i] = own;
     __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
+    for (int d = 1; d < 1024; d <<= 1) {
         const int v = i >= d ? s[i - d] : 0;
         __syncthreads();
         s[i] += v;
         __syncthreads();
     }
-    if (i < NBINS) counts[i] = s[i] - own;
+    int32_t run = s[i] - own;
+    for (int64_t k = a; k < b; ++k) {
+        const int32_t c = counts[k];
+        counts[k] = run;
+        run += c;
+    }
 }
 
-// each workgroup reserves one range per bin, then places its tracks
-__global__ void __launch_bounds__(256) k_scatter(const int32_t* off, int N, int max_hits, int32_t* pos,
-                                                 int32_t* order) {
-    __shared__ int32_t h[NBINS], base[NBINS];
-    for (int i = threadIdx.x; i < NBINS; i += blockDim.x) h[i] = 0;
+__global__ void __launch_bounds__(SORT_BLOCK) k_scatter(const int32_t* off, int N, int max_hits, int n_blocks,
+                                                        const int32_t* pos, int32_t* order) {
+    constexpr int W = SORT_BLOCK / 64;
+    __shared__ int32_t wc[W][NBINS];
+    for (int i = threadIdx.x; i < W * NBINS; i += blockDim.x) wc[i / NBINS][i % NBINS] = 0;
     __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int b = 0, local = 0;
-    if (t < N) {
-        b = len_bin(off, t, max_hits);
-        local = atomicAdd(&h[b], 1);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const bool valid = t < N;
+    const int b = valid ? len_bin(off, t, max_hits) : -1;
+    // rank among the earlier lanes of this wave with the same bin
+    int rank = 0;
+    unsigned long long todo = __ballot(valid);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int bl = __shfl(b, leader);
+        const unsigned long long m = __ballot(valid && b == bl);
+        if (valid && b == bl) rank = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == leader) wc[w][bl] = __popcll(m);
+        todo &= ~m;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < NBINS; i += blockDim.x)
-        if (h[i]) base[i] = atomicAdd(&pos[i], h[i]);
-    __syncthreads();
-    if (t < N) order[base[b] + local] = t;
+    if (valid) {
+        for (int v = 0; v < w; ++v) rank += wc[v][b];
+        order[pos[(int64_t)b * n_blocks + blockIdx.x] + rank] = t;
+    }
 }
 
+inline int sort_blocks(int N) { return N > 0 ? (N + SORT_BLOCK - 1) / SORT_BLOCK : 1; }
+
+// int32 entries of the sort's count table for N tracks
+inline int64_t sort_count_entries(int N) { return (int64_t)NBINS * sort_blocks(N); }
+
 // Enqueue the length sort: order[] receives the track indices, longest
-// first; the two tile-queue heads are cleared.
+// first, equal lengths in input order; the two tile-queue heads are cleared.
 inline hipError_t enqueue_length_sort(const int32_t* off, int N, int max_hits, int32_t* counts, int32_t* order,
                                       int32_t* tile_counter, hipStream_t stream) {
-    const int tb = 256, tg = (N + tb - 1) / tb;
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(128), 0, stream, counts, NBINS);
+    const int nb = sort_blocks(N);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, tile_counter, 2);
-    hipLaunchKernelGGL(k_hist, dim3(tg), dim3(tb), 0, stream, off, N, max_hits, counts);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(256), 0, stream, counts);
-    hipLaunchKernelGGL(k_scatter, dim3(tg), dim3(tb), 0, stream, off, N, max_hits, counts, order);
+    hipLaunchKernelGGL(k_hist, dim3(nb), dim3(SORT_BLOCK), 0, stream, off, N, max_hits, nb, counts);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, counts, sort_count_entries(N));
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(SORT_BLOCK), 0, stream, off, N, max_hits, nb,
+                       (const int32_t*)counts, order);
     return hipGetLastError();
 }
 

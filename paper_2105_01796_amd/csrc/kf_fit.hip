@@ -1,15 +1,18 @@
 // kf_fit.hip -- kernels and C ABI of the MI355X batched Kalman-filter track fit.
 //
 // Forward filter + RTS smoother (Sect. 2; Sect. 4.1), one lane per track:
-//   * the surface table is staged once per workgroup in LDS;
-//   * the forward pass writes, per hit, the predicted state, the filtered
-//     state and the RTS gain of the previous state (computed as soon as the
-//     predicted covariance exists, with the FP64 Cholesky solve) to a
-//     tile-major workspace [tile][hit][component][64 lanes]: a wave's 64
-//     lanes store/load 64 consecutive doubles (coalesced), and every
-//     component sits at a compile-time offset from one per-lane base, so the
-//     addressing costs neither scalar nor vector registers per component;
-//   * the backward pass is then a light streaming pass: it reads them back,
+//   * the surface table is staged once per workgroup in LDS, next to a
+//     per-lane slot for the filtered covariance carried from hit to hit;
+//   * the forward pass writes, per hit, only what the smoother cannot
+//     recompute cheaply -- the predicted state and covariance and the
+//     transport Jacobian F (Sect. 2: the smoother uses the Jacobians stored
+//     in the forward pass) -- to a tile-major workspace
+//     [tile][hit][component][64 lanes]: a wave's 64 lanes store/load 64
+//     consecutive doubles (coalesced), and every component sits at a
+//     compile-time offset from one per-lane base;
+//   * the backward pass recomputes each filtered state from the stored
+//     prediction and the hit (the same update, bit for bit), solves the RTS
+//     gain in FP64 (Cholesky of the predicted covariance, Sect. 4.2.4),
 //     applies the smoother and writes the smoothed states to the caller's CSR
 //     outputs, and the seed-surface result to tgt_*.
 // Schedules: DIRECT (track i on lane i) and SORTED (tracks ordered by hit
@@ -26,10 +29,12 @@
 
 namespace {
 
-// workspace doubles per hit: filtered state xf 6, Cf 21; smoother gain of the
-// previous state A 36 (row-major); predicted state xp 6, Cp 21
-constexpr int NC = 90;
-constexpr int OFF_XF = 0, OFF_CF = 6, OFF_A = 27, OFF_XP = 63, OFF_CP = 69;
+// workspace doubles per hit: predicted state xp 6, Cp 21; transport Jacobian
+// F into this hit (25 stored entries)
+constexpr int NC = 52;
+constexpr int OFF_XP = 0, OFF_CP = 6, OFF_F = 27;
+// LDS per wave for the carried filtered covariance: [21][64 lanes]
+constexpr int CARRY = 21;
 
 struct FitArgs {
     int n_tracks;
@@ -68,11 +73,12 @@ struct FitArgs {
 };
 
 // Forward filter of the track held by workspace slot `slot` (track index t):
-// validation, then per hit propagation, covariance transport, RTS gain of the
-// previous state and the gain-matrix update.  Writes chi2, ndf and status;
-// a failed track gets NaN outputs here (the backward pass skips it).
+// validation, then per hit propagation, covariance transport and the
+// gain-matrix update.  `cl` is this lane's LDS slot for the filtered
+// covariance between hits (component c at cl[c * 64]).  Writes chi2, ndf and
+// status; a failed track gets NaN outputs here (the backward pass skips it).
 template <class P, int FK>
-__device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
+__device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double* cl, int64_t slot, int t) {
     const int64_t H = a.n_hits;
     const int64_t N = a.n_tracks;
     int o, n;
@@ -98,50 +104,28 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t
         if (a.trials) a.trials[o + k] = tr;
         if (status != ST_OK) break;
         phase_boundary();
-        // the previous filtered covariance is not kept live across the
-        // propagation: it is re-read from the slot written one step earlier
-        double CQ[21];
-        if (k == 0) {
-            load_rows(a.seed_cov + t, N, CQ);
-        } else {
-            const double* wprev = wl + (k - 1) * (NC * TILE);
-#pragma unroll
-            for (int q = 0; q < 21; ++q) CQ[q] = wprev[(OFF_CF + q) * TILE];
-        }
-        CQ[sy(2, 2)] += q22;
-        CQ[sy(3, 3)] += q33;
-        phase_boundary();
         double* w = wl + k * (NC * TILE);
-        {
-            double Cp[21];
-            transport_cov(F, CQ, Cp);
 #pragma unroll
-            for (int i = 0; i < 6; ++i) w[(OFF_XP + i) * TILE] = xp[i];
+        for (int i = 0; i < 6; ++i) w[(OFF_XP + i) * TILE] = xp[i];
 #pragma unroll
-            for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = Cp[q];
-            phase_boundary();
-            // RTS gain of the previous state, A = C F^T Cp^-1 (C without the noise)
-            double L[21], id[6];
-            const bool spd = chol6(Cp, L, id);
-            CQ[sy(2, 2)] -= q22;
-            CQ[sy(3, 3)] -= q33;
-            phase_boundary();
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                double g[6];
-                smoother_gain_row(F, CQ, L, id, c, g);
-                // g is column c of A^T = row c of A
-#pragma unroll
-                for (int i = 0; i < 6; ++i) w[(OFF_A + 6 * c + i) * TILE] = g[i];
-                phase_boundary();
-            }
-            if (!spd) { status = ST_NOT_SPD; break; }
-        }
-        // the update reads the predicted covariance back (L1/L2 hit) rather
-        // than holding it across the gain solve
+        for (int q = 0; q < 25; ++q) w[(OFF_F + q) * TILE] = F[q];
+        // the previous filtered covariance waits in LDS during the propagation
         double Cp[21];
+        {
+            double CQ[21];
+            if (k == 0) {
+                load_rows(a.seed_cov + t, N, CQ);
+            } else {
 #pragma unroll
-        for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
+                for (int q = 0; q < 21; ++q) CQ[q] = cl[q * TILE];
+            }
+            CQ[sy(2, 2)] += q22;
+            CQ[sy(3, 3)] += q33;
+            phase_boundary();
+            transport_cov(F, CQ, Cp);
+        }
+#pragma unroll
+        for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = Cp[q];
         double m[2], V[3];
         load_rows(a.loc + o + k, H, m);
         load_rows(a.cov + o + k, H, V);
@@ -152,9 +136,7 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t
         phase_boundary();
         chi2 += ck;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) w[(OFF_XF + i) * TILE] = x[i];
-#pragma unroll
-        for (int q = 0; q < 21; ++q) w[(OFF_CF + q) * TILE] = C[q];
+        for (int q = 0; q < 21; ++q) cl[q * TILE] = C[q];
         if (a.filt_par) {
             store_rows(a.filt_par + o + k, H, x);
             store_rows(a.filt_cov + o + k, H, C);
@@ -181,10 +163,24 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t
     a.status[t] = (uint8_t)status;
 }
 
-// RTS smoother of one track (Sect. 2), run by a separate streaming kernel
-// after the forward pass: the smoothed state of the last hit is the filtered
-// one; every earlier state, and finally the seed/target state, follows from
-// the stored gain and predicted state of the next hit.
+// Filtered state of hit k, recomputed from the stored prediction and the hit
+// (the forward pass ran the same update on the same values).
+__device__ inline void refilter(const FitArgs& a, const double* w, int64_t hit, double xf[6], double Cf[21]) {
+    double xp[6], Cp[21], m[2], V[3], ck;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) xp[i] = w[(OFF_XP + i) * TILE];
+#pragma unroll
+    for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
+    load_rows(a.loc + hit, a.n_hits, m);
+    load_rows(a.cov + hit, a.n_hits, V);
+    kalman_update(xp, Cp, m, V, xf, Cf, &ck);
+}
+
+// RTS smoother of one track (Sect. 2), fused after the forward pass or run by
+// a separate streaming kernel: the smoothed state of the last hit is its
+// filtered state; every earlier state, and finally the seed/target state,
+// follows from the next hit's stored prediction and Jacobian with the gain
+// A = Cf F^T Cp^-1 solved in FP64.
 __device__ void bwd_one(const FitArgs& a, int64_t slot, int t) {
     if (a.status[t] != ST_OK) return;
     const int o = a.off[t];
@@ -193,72 +189,84 @@ __device__ void bwd_one(const FitArgs& a, int64_t slot, int t) {
     const int64_t N = a.n_tracks;
     const double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
     double x[6], C[21];
-    {
-        const double* w = wl + (n - 1) * (NC * TILE);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) x[i] = w[(OFF_XF + i) * TILE];
-#pragma unroll
-        for (int q = 0; q < 21; ++q) C[q] = w[(OFF_CF + q) * TILE];
-    }
+    refilter(a, wl + (n - 1) * (NC * TILE), o + n - 1, x, C);
     store_rows(a.par + o + n - 1, H, x);
     store_rows(a.pcov + o + n - 1, H, C);
+    bool spd = true;
     for (int k = n - 2; k >= -1; --k) {
         const double* w1 = wl + (k + 1) * (NC * TILE);
-        const double* w = wl + k * (NC * TILE);
-        double dx[6];
+        double dx[6], L[21], id[6];
         {
             double xp1[6], Cp1[21];
 #pragma unroll
             for (int i = 0; i < 6; ++i) xp1[i] = w1[(OFF_XP + i) * TILE];
 #pragma unroll
             for (int q = 0; q < 21; ++q) Cp1[q] = w1[(OFF_CP + q) * TILE];
-            rts_diff(x, C, xp1, Cp1, dx);                // C now holds D
+            spd = chol6(Cp1, L, id) && spd;
+            rts_diff(x, C, xp1, Cp1, dx);                // C now holds D = Cs1 - Cp1
+        }
+        phase_boundary();
+        double xf[6], Cf[21];
+        if (k >= 0) {
+            refilter(a, wl + k * (NC * TILE), o + k, xf, Cf);
+        } else {
+            load_rows(a.seed + t, N, xf);
+            load_rows(a.seed_cov + t, N, Cf);
         }
         phase_boundary();
         double A[36];
-#pragma unroll
-        for (int q = 0; q < 36; ++q) A[q] = w1[(OFF_A + q) * TILE];
         {
-            double xf[6];
-            if (k >= 0) {
+            double F[25];
 #pragma unroll
-                for (int i = 0; i < 6; ++i) xf[i] = w[(OFF_XF + i) * TILE];
-            } else {
-                load_rows(a.seed + t, N, xf);
+            for (int q = 0; q < 25; ++q) F[q] = w1[(OFF_F + q) * TILE];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                double g[6];
+                smoother_gain_row(F, Cf, L, id, c, g);
+#pragma unroll
+                for (int i = 0; i < 6; ++i) A[6 * c + i] = g[i];
             }
-            rts_mean(xf, A, dx, x);
         }
         phase_boundary();
-        double R[21];
-        if (k >= 0) {
+        rts_mean(xf, A, dx, x);
+        rts_cov(A, C, Cf);
 #pragma unroll
-            for (int q = 0; q < 21; ++q) R[q] = w[(OFF_CF + q) * TILE];
-        } else {
-            load_rows(a.seed_cov + t, N, R);
-        }
-        rts_cov(A, C, R);
-#pragma unroll
-        for (int q = 0; q < 21; ++q) C[q] = R[q];
+        for (int q = 0; q < 21; ++q) C[q] = Cf[q];
         if (k >= 0) {
             store_rows(a.par + o + k, H, x);
             store_rows(a.pcov + o + k, H, C);
         }
         phase_boundary();
     }
-    store_rows(a.tgt_par + t, N, x);
-    store_rows(a.tgt_cov + t, N, C);
+    if (spd) {
+        store_rows(a.tgt_par + t, N, x);
+        store_rows(a.tgt_cov + t, N, C);
+    } else {
+        // a predicted covariance that is not positive definite: the track fails
+        const double nan = __longlong_as_double(0x7ff8000000000000LL);
+        for (int k = 0; k < n; ++k) {
+            fill_rows<6>(a.par + o + k, H, nan);
+            fill_rows<21>(a.pcov + o + k, H, nan);
+        }
+        fill_rows<6>(a.tgt_par + t, N, nan);
+        fill_rows<21>(a.tgt_cov + t, N, nan);
+        a.chi2[t] = nan;
+        a.status[t] = (uint8_t)ST_NOT_SPD;
+    }
 }
 
 // Filter (+ smoother).  SORTED selects the schedule at compile time; OCC is
 // the occupancy target in waves per SIMD, which caps the registers per lane;
 // FUSED runs the smoother for a track right after its forward pass, while
 // its workspace column is still cache-hot (otherwise k_bwd does it).
+// Dynamic LDS: the surface table, then [waves][21][64] carried covariances.
 template <class P, int FK, int OCC, bool SORTED, bool FUSED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
 k_fwd(FitArgs a) {
     extern __shared__ double sm[];
     stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, sm);
     const int lane = threadIdx.x & (TILE - 1);
+    double* cl = sm + a.n_surf * SURF_STRIDE + (threadIdx.x / TILE) * (CARRY * TILE) + lane;
     int iter = 0;
     for (;;) {
         const int tile = next_tile<SORTED>(a.tile_counter, iter);
@@ -266,7 +274,7 @@ k_fwd(FitArgs a) {
         const int64_t i = (int64_t)tile * TILE + lane;
         if (i < a.n_tracks) {
             const int t = SORTED ? a.order[i] : (int)i;
-            fwd_one<P, FK>(a, sm, i, t);
+            fwd_one<P, FK>(a, sm, cl, i, t);
             if (FUSED) bwd_one(a, i, t);
         }
     }
@@ -294,7 +302,7 @@ struct WsLayout {
     int64_t tile_doubles;
     size_t fit_bytes;     // [tiles][max_hits][NC][64] doubles
     size_t order_off;     // int32 [tiles * 64]
-    size_t counts_off;    // int32 [NBINS] histogram / positions
+    size_t counts_off;    // int32 [NBINS][sort blocks] histogram / positions
     size_t counter_off;   // int32 tile counter
     size_t total;
 };
@@ -307,7 +315,7 @@ WsLayout ws_layout(int64_t n_tracks, int max_hits) {
     L.fit_bytes = (size_t)tiles * L.tile_doubles * sizeof(double);
     L.order_off = align_up(L.fit_bytes, 256);
     L.counts_off = align_up(L.order_off + (size_t)tiles * TILE * 4, 256);
-    L.counter_off = align_up(L.counts_off + NBINS * 4, 256);
+    L.counter_off = align_up(L.counts_off + (size_t)sort_count_entries((int)n_tracks) * 4, 256);
     L.total = align_up(L.counter_off + 256, 256);
     return L;
 }
@@ -327,7 +335,7 @@ int validate(const kf_config* cfg, const kf_surfaces* surf, const kf_field* fiel
 template <class P, int FK, int OCC>
 hipError_t launch_fit_occ(const FitArgs& a, int sched, int block, int waves_per_cu, bool split,
                           hipStream_t stream) {
-    const size_t shm = (size_t)a.n_surf * SURF_STRIDE * sizeof(double);
+    const size_t shm = ((size_t)a.n_surf * SURF_STRIDE + (size_t)(block / TILE) * CARRY * TILE) * sizeof(double);
     const int need = (a.n_tiles * TILE + block - 1) / block;
     if (sched == KF_SCHED_SORTED) {
         int grid = num_cu() * waves_per_cu * TILE / block;

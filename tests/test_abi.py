@@ -117,7 +117,7 @@ def test_argument_validation(kf):
     # workspace
     assert _call(kf, *a, ws=None) == kf.KF_E_WS
     need = kf.lib().kf_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n)
-    assert need >= 64 * 10 * 90 * 8          # one 64-track tile x 10 hits x 90 doubles
+    assert need >= 64 * 10 * 52 * 8          # one 64-track tile x 10 hits x 52 doubles
     assert _call(kf, *a, nbytes=need - 1) == kf.KF_E_WS
     # nothing to do: no tracks is OK without touching the device
     meas.n_tracks = 0
