@@ -5,7 +5,10 @@ Workload (default): 1e5 muon tracks, 10 planes normal to x at x = 30..300 mm,
 uniform Bz = 2 T, 0.5 % X0 per plane with Highland multiple scattering,
 pT 1-10 GeV, |phi| < 0.1, |eta| < 0.2, 50 um hits; seeded synthetic data.
 One step = one filter + RTS-smoother pass over all tracks (inputs resident
-in HBM).  Prints one JSON line.  Besides the FP64 headline it times the
+in HBM), launched as the product runs it: the launch shape is picked by the
+library's autotuner (kf_autotune, untimed) and the whole launch sequence is
+captured once in a HIP graph (kf_plan_create) that every step replays.
+Prints one JSON line.  Besides the FP64 headline it times the
 mixed-precision fit and a fit + adjoint step (kf_fit_tracks then
 kf_fit_tracks_vjp with chi2, smoothed-parameter and target cotangents).
 
@@ -120,6 +123,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the fit + adjoint leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM counters)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the given (or default) launch settings instead of the autotuner's")
+    ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     args = ap.parse_args()
@@ -151,18 +157,31 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    def prepared_plan(precision):
+        """Plan with autotuned launch settings, captured in a HIP graph."""
+        plan = kfmi.Plan(batch, kfmi.Options(precision=precision, **base_opt))
+        tuned = None
+        if not args.no_autotune:
+            opt, tune_ms = plan.autotune()
+            tuned = {"schedule": opt.schedule, "block": opt.block, "occupancy": opt.occupancy,
+                     "waves_per_cu": opt.waves_per_cu, "split_smoother": opt.split_smoother,
+                     "tuner_ms": round(tune_ms, 4)}
+        if not args.no_graph:
+            plan.capture()
+        return plan, tuned
+
     # FP64 leg (the headline value)
-    plan64 = kfmi.Plan(batch, kfmi.Options(precision=kfmi.KF_PREC_FP64, **base_opt))
+    plan64, tuned64 = prepared_plan(kfmi.KF_PREC_FP64)
     ms64, kms64, per64 = time_plan(plan64, args.steps, args.warmup)
     st = plan64.out.status.cpu().numpy()
     n_ok = int((st == 0).sum())
 
     mixed = None
     if not args.no_mixed:
-        planm = kfmi.Plan(batch, kfmi.Options(precision=kfmi.KF_PREC_MIXED, **base_opt))
+        planm, tunedm = prepared_plan(kfmi.KF_PREC_MIXED)
         msm, kmsm, _ = time_plan(planm, args.steps, args.warmup)
         mixed = {"value": N / (msm * 1e-3), "ms_per_step": msm, "launch_ms": kmsm,
-                 "speedup_vs_fp64": ms64 / msm}
+                 "speedup_vs_fp64": ms64 / msm, "launch": tunedm}
 
     adjoint = None
     if not args.no_adjoint:
@@ -236,6 +255,7 @@ def main():
         "config": {"workload": f"C{args.config}: " + WORKLOADS[args.config], "tracks": N,
                    "hits": ev.n_hits, "precision": "fp64", "launch_ms": kms64,
                    "launch_ms_min": min(per64), "tracks_ok": n_ok, "options": base_opt,
+                   "launch": tuned64, "graph": not args.no_graph,
                    "gen_seconds": round(t_gen, 2)},
         "mixed": mixed,
         "adjoint": adjoint,

@@ -56,13 +56,17 @@ __device__ inline void fill_rows(double* p, int64_t stride, double val) {
     }
 }
 
-// Input checks of one track, in the order the CPU reference applies them:
-// CSR range, hit count, seed finite with an SPD covariance, every hit on a
-// known surface with finite coordinates and an SPD covariance.  On a corrupt
-// CSR range n is set to 0 so no hit is touched.
-__device__ inline int check_track(const int32_t* off, const int32_t* sid, const double* loc, const double* cov,
-                                  const double* seed, const double* seed_cov, int64_t H, int64_t N, int n_surf,
-                                  int max_hits, int t, int& o, int& n) {
+// One hit is usable: a known surface, finite coordinates, an SPD covariance.
+__device__ inline bool hit_ok(int s, int n_surf, const double m[2], const double V[3]) {
+    return (s >= 0 && s < n_surf) && finite(m[0]) && finite(m[1]) && finite(V[0]) && finite(V[1]) &&
+           finite(V[2]) && (V[0] > 0.0) && (V[0] * V[2] - V[1] * V[1] > 0.0);
+}
+
+// The per-track checks that need no hit: CSR range, hit count, a finite seed
+// with an SPD covariance.  On a corrupt CSR range n is set to 0 so no hit is
+// touched.
+__device__ inline int check_head(const int32_t* off, const double* seed, const double* seed_cov, int64_t H,
+                                 int64_t N, int max_hits, int t, int& o, int& n) {
     o = off[t];
     n = off[t + 1] - o;
     if (o < 0 || n < 0 || (int64_t)o + n > H) { n = 0; return ST_BAD_INPUT; }
@@ -96,15 +100,29 @@ __device__ inline int check_track(const int32_t* off, const int32_t* sid, const 
             }
         }
     }
-    for (int k = 0; k < n && ok; ++k) {
-        const int s = sid[o + k];
+    return ok ? ST_OK : ST_BAD_INPUT;
+}
+
+// Some hit in [k0, n) of the track at CSR offset o is unusable.
+__device__ inline bool any_bad_hit(const int32_t* sid, const double* loc, const double* cov, int64_t H, int n_surf,
+                                   int o, int k0, int n) {
+    for (int k = k0; k < n; ++k) {
         double m[2], V[3];
         load_rows(loc + o + k, H, m);
         load_rows(cov + o + k, H, V);
-        ok = (s >= 0 && s < n_surf) && finite(m[0]) && finite(m[1]) && finite(V[0]) && finite(V[1]) &&
-             finite(V[2]) && (V[0] > 0.0) && (V[0] * V[2] - V[1] * V[1] > 0.0);
+        if (!hit_ok(sid[o + k], n_surf, m, V)) return true;
     }
-    return ok ? ST_OK : ST_BAD_INPUT;
+    return false;
+}
+
+// Every input check of one track, as the CPU reference applies them before
+// fitting (all of them report ST_BAD_INPUT except the hit count).
+__device__ inline int check_track(const int32_t* off, const int32_t* sid, const double* loc, const double* cov,
+                                  const double* seed, const double* seed_cov, int64_t H, int64_t N, int n_surf,
+                                  int max_hits, int t, int& o, int& n) {
+    const int st = check_head(off, seed, seed_cov, H, N, max_hits, t, o, n);
+    if (st != ST_OK) return st;
+    return any_bad_hit(sid, loc, cov, H, n_surf, o, 0, n) ? ST_BAD_INPUT : ST_OK;
 }
 
 // Surface s with an alignment correction a = (dx, dy, dz, alpha, beta, gamma):
@@ -309,6 +327,30 @@ inline int num_cu() {
         if (n <= 0) n = 256;
     });
     return n;
+}
+
+// LDS one workgroup may use on this device (160 KB on gfx950).
+inline size_t lds_cap() {
+    static size_t v = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            v = p.maxSharedMemoryPerMultiProcessor > p.sharedMemPerBlock ? p.maxSharedMemoryPerMultiProcessor
+                                                                        : p.sharedMemPerBlock;
+        if (v == 0) v = 65536;
+    });
+    return v;
+}
+
+// Let `kernel` take `bytes` of dynamic LDS: beyond 64 KB the limit is raised
+// explicitly; beyond the device's LDS it is refused (no launch).
+template <class K>
+inline hipError_t allow_lds(K kernel, size_t bytes) {
+    if (bytes > lds_cap()) return hipErrorInvalidValue;
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 // Host-side checks shared by every entry point (everything but the outputs).

@@ -33,8 +33,15 @@ namespace {
 // F into this hit (25 stored entries)
 constexpr int NC = 52;
 constexpr int OFF_XP = 0, OFF_CP = 6, OFF_F = 27;
-// LDS per wave for the carried filtered covariance: [21][64 lanes]
+// LDS per wave: the carried filtered covariance [21][64 lanes] during the
+// filter; after the smoother the same area holds the output transpose of
+// flush_tile (FLUSH_GROUP components x FLUSH_HITS hits x 64 lanes doubles,
+// then two int lists of FLUSH_HITS x 64 entries)
 constexpr int CARRY = 21;
+constexpr int FLUSH_HITS = 4;
+constexpr int FLUSH_GROUP = 5;
+constexpr int FLUSH_DOUBLES = FLUSH_GROUP * FLUSH_HITS * TILE + FLUSH_HITS * TILE;
+constexpr int WAVE_LDS_DOUBLES = CARRY * TILE > FLUSH_DOUBLES ? CARRY * TILE : FLUSH_DOUBLES;
 
 struct FitArgs {
     int n_tracks;
@@ -73,16 +80,21 @@ struct FitArgs {
 };
 
 // Forward filter of the track held by workspace slot `slot` (track index t):
-// validation, then per hit propagation, covariance transport and the
-// gain-matrix update.  `cl` is this lane's LDS slot for the filtered
-// covariance between hits (component c at cl[c * 64]).  Writes chi2, ndf and
-// status; a failed track gets NaN outputs here (the backward pass skips it).
+// per hit propagation, covariance transport and the gain-matrix update.
+// Each hit is checked when the loop reaches it, with its surface id and
+// measurement loaded one hit ahead so the loads overlap the propagation; if
+// the filter fails before the last hit, the remaining hits are checked too,
+// so that a bad input anywhere wins over a filter failure (the CPU reference
+// checks every hit before it fits).  `cl` is this lane's LDS slot for the
+// filtered covariance between hits (component c at cl[c * 64]).  Writes
+// chi2, ndf and status; a failed track gets NaN outputs here (the backward
+// pass skips it).
 template <class P, int FK>
 __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double* cl, int64_t slot, int t) {
     const int64_t H = a.n_hits;
     const int64_t N = a.n_tracks;
     int o, n;
-    int status = check_track(a.off, a.sid, a.loc, a.cov, a.seed, a.seed_cov, H, N, a.n_surf, a.max_hits, t, o, n);
+    int status = check_head(a.off, a.seed, a.seed_cov, H, N, a.max_hits, t, o, n);
     double x[6];
     load_rows(a.seed + t, N, x);
     Field<P, FK> fl;
@@ -90,10 +102,28 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
     // this lane's column of its tile: component c of hit k at wl[(k * NC + c) * TILE]
     double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
     double chi2 = 0.0;
+    // hit k's surface and measurement, loaded during hit k-1
+    int s_nx = 0;
+    double m_nx[2] = {0.0, 0.0}, V_nx[3] = {0.0, 0.0, 0.0};
+    if (status == ST_OK) {
+        s_nx = a.sid[o];
+        load_rows(a.loc + o, H, m_nx);
+        load_rows(a.cov + o, H, V_nx);
+    }
     // ---- forward filter ----
     int prev = a.seed_sid;
-    for (int k = 0; k < n && status == ST_OK; ++k) {
-        const int s = a.sid[o + k];
+    int k = 0;
+    for (; k < n && status == ST_OK; ++k) {
+        const int s = s_nx;
+        const double m[2] = {m_nx[0], m_nx[1]};
+        const double V[3] = {V_nx[0], V_nx[1], V_nx[2]};
+        if (!hit_ok(s, a.n_surf, m, V)) { status = ST_BAD_INPUT; break; }
+        if (k + 1 < n) {
+            s_nx = a.sid[o + k + 1];
+            load_rows(a.loc + o + k + 1, H, m_nx);
+            load_rows(a.cov + o + k + 1, H, V_nx);
+        }
+        phase_boundary();
         const double* sa = sm + prev * SURF_STRIDE;
         const double* sb = sm + s * SURF_STRIDE;
         double q22 = 0.0, q33 = 0.0;
@@ -126,9 +156,6 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
         }
 #pragma unroll
         for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = Cp[q];
-        double m[2], V[3];
-        load_rows(a.loc + o + k, H, m);
-        load_rows(a.cov + o + k, H, V);
         double ck, C[21];
         phase_boundary();
         status = kalman_update(xp, Cp, m, V, x, C, &ck);
@@ -143,6 +170,9 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
         }
         prev = s;
     }
+    if (status != ST_OK && status != ST_BAD_INPUT && status != ST_TOO_FEW &&
+        any_bad_hit(a.sid, a.loc, a.cov, H, a.n_surf, o, k + 1, n))
+        status = ST_BAD_INPUT;
     if (status == ST_OK) {
         a.chi2[t] = chi2;
     } else {
@@ -163,95 +193,182 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
     a.status[t] = (uint8_t)status;
 }
 
-// Filtered state of hit k, recomputed from the stored prediction and the hit
-// (the forward pass ran the same update on the same values).
-__device__ inline void refilter(const FitArgs& a, const double* w, int64_t hit, double xf[6], double Cf[21]) {
-    double xp[6], Cp[21], m[2], V[3], ck;
-#pragma unroll
-    for (int i = 0; i < 6; ++i) xp[i] = w[(OFF_XP + i) * TILE];
-#pragma unroll
-    for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
-    load_rows(a.loc + hit, a.n_hits, m);
-    load_rows(a.cov + hit, a.n_hits, V);
-    kalman_update(xp, Cp, m, V, xf, Cf, &ck);
-}
-
 // RTS smoother of one track (Sect. 2), fused after the forward pass or run by
 // a separate streaming kernel: the smoothed state of the last hit is its
 // filtered state; every earlier state, and finally the seed/target state,
 // follows from the next hit's stored prediction and Jacobian with the gain
-// A = Cf F^T Cp^-1 solved in FP64.
-__device__ void bwd_one(const FitArgs& a, int64_t slot, int t) {
-    if (a.status[t] != ST_OK) return;
+// A = Cf F^T Cp^-1 solved in FP64.  The smoothed state of hit k replaces the
+// prediction in slot k once that has been read for the last time; flush_tile
+// then writes the tile's CSR outputs.  Returns true if the track's smoothed
+// states are in its slots (false: not fitted, or failed here with NaN outputs).
+__device__ bool bwd_one(const FitArgs& a, int64_t slot, int t) {
+    if (a.status[t] != ST_OK) return false;
     const int o = a.off[t];
     const int n = a.off[t + 1] - o;
     const int64_t H = a.n_hits;
     const int64_t N = a.n_tracks;
-    const double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
+    double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
+    // prediction of hit k+1 (carried from one step to the next)
+    double xp1[6], Cp1[21];
     double x[6], C[21];
-    refilter(a, wl + (n - 1) * (NC * TILE), o + n - 1, x, C);
-    store_rows(a.par + o + n - 1, H, x);
-    store_rows(a.pcov + o + n - 1, H, C);
+    {
+        const double* w = wl + (n - 1) * (NC * TILE);
+        double m[2], V[3], ck;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) xp1[i] = w[(OFF_XP + i) * TILE];
+#pragma unroll
+        for (int q = 0; q < 21; ++q) Cp1[q] = w[(OFF_CP + q) * TILE];
+        load_rows(a.loc + o + n - 1, H, m);
+        load_rows(a.cov + o + n - 1, H, V);
+        kalman_update(xp1, Cp1, m, V, x, C, &ck);
+    }
     bool spd = true;
     for (int k = n - 2; k >= -1; --k) {
-        const double* w1 = wl + (k + 1) * (NC * TILE);
-        double dx[6], L[21], id[6];
-        {
-            double xp1[6], Cp1[21];
+        double* w1 = wl + (k + 1) * (NC * TILE);
+        // every load of this step at once: F of hit k+1, the prediction and
+        // measurement of hit k (or the seed)
+        double F[25], xp[6], Cp[21], m[2], V[3], xf[6], Cf[21];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) xp1[i] = w1[(OFF_XP + i) * TILE];
-#pragma unroll
-            for (int q = 0; q < 21; ++q) Cp1[q] = w1[(OFF_CP + q) * TILE];
-            spd = chol6(Cp1, L, id) && spd;
-            rts_diff(x, C, xp1, Cp1, dx);                // C now holds D = Cs1 - Cp1
-        }
-        phase_boundary();
-        double xf[6], Cf[21];
+        for (int q = 0; q < 25; ++q) F[q] = w1[(OFF_F + q) * TILE];
         if (k >= 0) {
-            refilter(a, wl + k * (NC * TILE), o + k, xf, Cf);
+            const double* w = wl + k * (NC * TILE);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) xp[i] = w[(OFF_XP + i) * TILE];
+#pragma unroll
+            for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
+            load_rows(a.loc + o + k, H, m);
+            load_rows(a.cov + o + k, H, V);
         } else {
             load_rows(a.seed + t, N, xf);
             load_rows(a.seed_cov + t, N, Cf);
         }
+        // slot k+1 is done: it now keeps the smoothed state of hit k+1
+#pragma unroll
+        for (int i = 0; i < 6; ++i) w1[(OFF_XP + i) * TILE] = x[i];
+#pragma unroll
+        for (int q = 0; q < 21; ++q) w1[(OFF_CP + q) * TILE] = C[q];
+        double dx[6], L[21], id[6];
+        spd = chol6(Cp1, L, id) && spd;
+        rts_diff(x, C, xp1, Cp1, dx);                    // C now holds D = Cs1 - Cp1
+        if (k >= 0) {
+            double ck;
+            kalman_update(xp, Cp, m, V, xf, Cf, &ck);    // filtered state of hit k, as in the forward pass
+#pragma unroll
+            for (int i = 0; i < 6; ++i) xp1[i] = xp[i];
+#pragma unroll
+            for (int q = 0; q < 21; ++q) Cp1[q] = Cp[q];
+        }
         phase_boundary();
         double A[36];
-        {
-            double F[25];
 #pragma unroll
-            for (int q = 0; q < 25; ++q) F[q] = w1[(OFF_F + q) * TILE];
+        for (int c = 0; c < 6; ++c) {
+            double g[6];
+            smoother_gain_row(F, Cf, L, id, c, g);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                double g[6];
-                smoother_gain_row(F, Cf, L, id, c, g);
-#pragma unroll
-                for (int i = 0; i < 6; ++i) A[6 * c + i] = g[i];
-            }
+            for (int i = 0; i < 6; ++i) A[6 * c + i] = g[i];
         }
         phase_boundary();
         rts_mean(xf, A, dx, x);
         rts_cov(A, C, Cf);
 #pragma unroll
         for (int q = 0; q < 21; ++q) C[q] = Cf[q];
-        if (k >= 0) {
-            store_rows(a.par + o + k, H, x);
-            store_rows(a.pcov + o + k, H, C);
-        }
         phase_boundary();
     }
     if (spd) {
         store_rows(a.tgt_par + t, N, x);
         store_rows(a.tgt_cov + t, N, C);
-    } else {
-        // a predicted covariance that is not positive definite: the track fails
-        const double nan = __longlong_as_double(0x7ff8000000000000LL);
-        for (int k = 0; k < n; ++k) {
-            fill_rows<6>(a.par + o + k, H, nan);
-            fill_rows<21>(a.pcov + o + k, H, nan);
+        return true;
+    }
+    // a predicted covariance that is not positive definite: the track fails
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    for (int k = 0; k < n; ++k) {
+        fill_rows<6>(a.par + o + k, H, nan);
+        fill_rows<21>(a.pcov + o + k, H, nan);
+    }
+    fill_rows<6>(a.tgt_par + t, N, nan);
+    fill_rows<21>(a.tgt_cov + t, N, nan);
+    a.chi2[t] = nan;
+    a.status[t] = (uint8_t)ST_NOT_SPD;
+    return false;
+}
+
+// All lanes of the wave, in step: LDS written by one lane is then visible to
+// the others (the waves of a workgroup run different tiles, so no workgroup
+// barrier may be used here).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Write the smoothed states of a tile's tracks (left in their workspace slots
+// by bwd_one) to the CSR outputs.  One lane per track computed them; a store
+// from each lane would touch a different cache line per lane.  Instead, for a
+// block of FLUSH_HITS hits: every lane loads its 27 x FLUSH_HITS values at
+// once (coalesced: the slots are tile-major), the wave lists which (lane,
+// hit) owns each entry of the block's CSR ranges, and then, FLUSH_GROUP
+// components at a time, the values pass through LDS so that consecutive
+// lanes store consecutive CSR entries.  Every lane of the wave must call it
+// (done: this lane's track has results; o, n: its CSR range).  lw: this
+// wave's LDS area (free once the smoother has finished).
+__device__ void flush_tile(const FitArgs& a, double* lw, const double* wtile, bool done, int o, int n) {
+    const int lane = threadIdx.x & (TILE - 1);
+    double* tb = lw;                                                    // [FLUSH_GROUP][FLUSH_HITS][64]
+    int32_t* own = (int32_t*)(lw + FLUSH_GROUP * FLUSH_HITS * TILE);   // [FLUSH_HITS * 64]: lane | hit << 6
+    int32_t* dst = own + FLUSH_HITS * TILE;                             // [FLUSH_HITS * 64]: CSR index
+    const int nl = done ? n : 0;
+    int nmax = nl;
+#pragma unroll
+    for (int d = 1; d < TILE; d <<= 1) {
+        const int v = __shfl_xor(nmax, d, TILE);
+        nmax = v > nmax ? v : nmax;
+    }
+    const int64_t H = a.n_hits;
+    for (int hb = 0; hb < nmax; hb += FLUSH_HITS) {
+        const int cnt = nl - hb < 0 ? 0 : (nl - hb > FLUSH_HITS ? FLUSH_HITS : nl - hb);
+        // every value of this block first: one wait for all of them
+        double v[27][FLUSH_HITS];
+        const double* src = wtile + (int64_t)hb * (NC * TILE) + OFF_XP * TILE + lane;
+#pragma unroll
+        for (int c = 0; c < 27; ++c)
+#pragma unroll
+            for (int h = 0; h < FLUSH_HITS; ++h)
+                v[c][h] = h < cnt ? src[(int64_t)h * (NC * TILE) + c * TILE] : 0.0;
+        // exclusive prefix of cnt over the wave
+        int inc = cnt;
+#pragma unroll
+        for (int d = 1; d < TILE; d <<= 1) {
+            const int u = __shfl_up(inc, d, TILE);
+            if (lane >= d) inc += u;
         }
-        fill_rows<6>(a.tgt_par + t, N, nan);
-        fill_rows<21>(a.tgt_cov + t, N, nan);
-        a.chi2[t] = nan;
-        a.status[t] = (uint8_t)ST_NOT_SPD;
+        const int start = inc - cnt;
+        const int total = __shfl(inc, TILE - 1, TILE);
+#pragma unroll
+        for (int h = 0; h < FLUSH_HITS; ++h)
+            if (h < cnt) {
+                own[start + h] = lane | (h << 6);
+                dst[start + h] = o + hb + h;
+            }
+#pragma unroll
+        for (int c0 = 0; c0 < 27; c0 += FLUSH_GROUP) {
+#pragma unroll
+            for (int c = c0; c < c0 + FLUSH_GROUP && c < 27; ++c)
+#pragma unroll
+                for (int h = 0; h < FLUSH_HITS; ++h)
+                    if (h < cnt) tb[((c - c0) * FLUSH_HITS + h) * TILE + lane] = v[c][h];
+            wave_sync();
+            for (int g = lane; g < total; g += TILE) {
+                const int e = own[g];
+                const int64_t d = dst[g];
+                const int from = (e >> 6) * TILE + (e & 63);
+#pragma unroll
+                for (int c = c0; c < c0 + FLUSH_GROUP && c < 27; ++c) {
+                    double* out = c < 6 ? a.par + (int64_t)c * H : a.pcov + (int64_t)(c - 6) * H;
+                    out[d] = tb[(c - c0) * FLUSH_HITS * TILE + from];
+                }
+            }
+            wave_sync();
+        }
     }
 }
 
@@ -259,39 +376,56 @@ __device__ void bwd_one(const FitArgs& a, int64_t slot, int t) {
 // the occupancy target in waves per SIMD, which caps the registers per lane;
 // FUSED runs the smoother for a track right after its forward pass, while
 // its workspace column is still cache-hot (otherwise k_bwd does it).
-// Dynamic LDS: the surface table, then [waves][21][64] carried covariances.
+// Dynamic LDS: the surface table, then per wave the carried covariances.
 template <class P, int FK, int OCC, bool SORTED, bool FUSED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
 k_fwd(FitArgs a) {
     extern __shared__ double sm[];
     stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, sm);
     const int lane = threadIdx.x & (TILE - 1);
-    double* cl = sm + a.n_surf * SURF_STRIDE + (threadIdx.x / TILE) * (CARRY * TILE) + lane;
+    double* cl = sm + a.n_surf * SURF_STRIDE + (threadIdx.x / TILE) * WAVE_LDS_DOUBLES + lane;
     int iter = 0;
     for (;;) {
         const int tile = next_tile<SORTED>(a.tile_counter, iter);
         if (tile >= a.n_tiles) break;
         const int64_t i = (int64_t)tile * TILE + lane;
+        bool done = false;
+        int o = 0, n = 0;
         if (i < a.n_tracks) {
             const int t = SORTED ? a.order[i] : (int)i;
             fwd_one<P, FK>(a, sm, cl, i, t);
-            if (FUSED) bwd_one(a, i, t);
+            if (FUSED) {
+                done = bwd_one(a, i, t);
+                o = a.off[t];
+                n = a.off[t + 1] - o;
+            }
         }
+        if (FUSED) flush_tile(a, cl - lane, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
     }
 }
 
-// Backward (smoother) pass: a streaming pass with a small live set, run at
-// two waves per SIMD (no spills) so the per-step workspace reads overlap.
+// Backward (smoother) pass as its own kernel.  Dynamic LDS: per wave the
+// output transpose.
 template <bool SORTED>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_bwd(FitArgs a) {
+    extern __shared__ double sm[];
     const int lane = threadIdx.x & (TILE - 1);
+    double* lw = sm + (threadIdx.x / TILE) * WAVE_LDS_DOUBLES;
     int iter = 0;
     for (;;) {
         const int tile = next_tile<SORTED>(a.tile_counter + 1, iter);
         if (tile >= a.n_tiles) break;
         const int64_t i = (int64_t)tile * TILE + lane;
-        if (i < a.n_tracks) bwd_one(a, i, SORTED ? a.order[i] : (int)i);
+        bool done = false;
+        int o = 0, n = 0;
+        if (i < a.n_tracks) {
+            const int t = SORTED ? a.order[i] : (int)i;
+            done = bwd_one(a, i, t);
+            o = a.off[t];
+            n = a.off[t + 1] - o;
+        }
+        flush_tile(a, lw, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
     }
 }
 
@@ -335,24 +469,32 @@ int validate(const kf_config* cfg, const kf_surfaces* surf, const kf_field* fiel
 template <class P, int FK, int OCC>
 hipError_t launch_fit_occ(const FitArgs& a, int sched, int block, int waves_per_cu, bool split,
                           hipStream_t stream) {
-    const size_t shm = ((size_t)a.n_surf * SURF_STRIDE + (size_t)(block / TILE) * CARRY * TILE) * sizeof(double);
+    const size_t shm = ((size_t)a.n_surf * SURF_STRIDE + (size_t)(block / TILE) * WAVE_LDS_DOUBLES) * sizeof(double);
+    const size_t shm_b = (size_t)(block / TILE) * WAVE_LDS_DOUBLES * sizeof(double);
     const int need = (a.n_tiles * TILE + block - 1) / block;
+    hipError_t e = hipSuccess;
     if (sched == KF_SCHED_SORTED) {
         int grid = num_cu() * waves_per_cu * TILE / block;
         grid = grid > need ? need : (grid < 1 ? 1 : grid);
         if (split) {
             int gridb = num_cu() * 8 * TILE / block;
             gridb = gridb > need ? need : (gridb < 1 ? 1 : gridb);
+            if ((e = allow_lds(k_fwd<P, FK, OCC, true, false>, shm)) != hipSuccess) return e;
+            if ((e = allow_lds(k_bwd<true>, shm_b)) != hipSuccess) return e;
             hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, false>), dim3(grid), dim3(block), shm, stream, a);
-            hipLaunchKernelGGL((k_bwd<true>), dim3(gridb), dim3(block), 0, stream, a);
+            hipLaunchKernelGGL((k_bwd<true>), dim3(gridb), dim3(block), shm_b, stream, a);
         } else {
+            if ((e = allow_lds(k_fwd<P, FK, OCC, true, true>, shm)) != hipSuccess) return e;
             hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, true>), dim3(grid), dim3(block), shm, stream, a);
         }
     } else {
         if (split) {
+            if ((e = allow_lds(k_fwd<P, FK, OCC, false, false>, shm)) != hipSuccess) return e;
+            if ((e = allow_lds(k_bwd<false>, shm_b)) != hipSuccess) return e;
             hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, false>), dim3(need), dim3(block), shm, stream, a);
-            hipLaunchKernelGGL((k_bwd<false>), dim3(need), dim3(block), 0, stream, a);
+            hipLaunchKernelGGL((k_bwd<false>), dim3(need), dim3(block), shm_b, stream, a);
         } else {
+            if ((e = allow_lds(k_fwd<P, FK, OCC, false, true>, shm)) != hipSuccess) return e;
             hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, true>), dim3(need), dim3(block), shm, stream, a);
         }
     }
@@ -430,6 +572,7 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     else
         e = mixed ? launch_fit<float, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, stream)
                   : launch_fit<double, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, stream);
+    if (e == hipErrorInvalidValue) return KF_E_VALUE;     // workgroup needs more LDS than the device has
     return e == hipSuccess ? KF_OK : KF_E_HIP;
 }
 
@@ -626,6 +769,7 @@ int kf_autotune(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
                         c.split_smoother = sp;
                         c.waves_per_cu = wp;
                         rc = enqueue_fit(&c, surf, field, meas, seeds, out, workspace, stream);   // warm-up
+                        if (rc == KF_E_VALUE) { rc = KF_OK; continue; }   // does not fit this device
                         if (rc != KF_OK) break;
                         (void)hipEventRecord(e0, stream);
                         for (int rep = 0; rep < 3 && rc == KF_OK; ++rep)
