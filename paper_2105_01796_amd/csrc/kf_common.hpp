@@ -213,9 +213,12 @@ __device__ inline int next_tile(int32_t* counter, int& iter) {
 // A stable counting sort: tracks of equal length keep their input order, so a
 // tile holds consecutive tracks (their CSR outputs are neighbours in memory)
 // and the order is the same on every run.
-//   k_hist:    per-block histogram over the block's 256 tracks -> counts[bin][block]
-//   k_scan:    exclusive scan of counts in (bin, block) order -> first slot per (bin, block)
-//   k_scatter: rank of each track among the block's tracks of its bin (wave ballots)
+//   k_hist:     per-block histogram over the block's 256 tracks -> counts[bin][block],
+//               and the per-bin totals (integer sums: order-independent)
+//   k_bin_scan: one workgroup per bin: exclusive scan of the bin's per-block
+//               counts, offset by the totals of the earlier bins -> first slot
+//               per (bin, block)
+//   k_scatter:  rank of each track among the block's tracks of its bin (wave ballots)
 constexpr int NBINS = KF_MAX_HITS + 2;
 constexpr int SORT_BLOCK = 256;
 
@@ -232,39 +235,45 @@ __device__ inline int len_bin(const int32_t* off, int t, int max_hits) {
 }
 
 __global__ void __launch_bounds__(SORT_BLOCK) k_hist(const int32_t* off, int N, int max_hits, int n_blocks,
-                                                     int32_t* counts) {
+                                                     int32_t* counts, int32_t* totals) {
     __shared__ int32_t h[NBINS];
     for (int i = threadIdx.x; i < NBINS; i += blockDim.x) h[i] = 0;
     __syncthreads();
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < N) atomicAdd(&h[len_bin(off, t, max_hits)], 1);
     __syncthreads();
-    for (int i = threadIdx.x; i < NBINS; i += blockDim.x) counts[(int64_t)i * n_blocks + blockIdx.x] = h[i];
+    for (int i = threadIdx.x; i < NBINS; i += blockDim.x) {
+        counts[(int64_t)i * n_blocks + blockIdx.x] = h[i];
+        if (h[i]) atomicAdd(&totals[i], h[i]);
+    }
 }
 
-// Exclusive scan of M counts by one workgroup of 1024 threads: each thread
-// sums a contiguous segment, the segment totals are scanned in LDS, then each
-// thread writes its segment's prefix sums.
-__global__ void __launch_bounds__(1024) k_scan(int32_t* counts, int64_t M) {
-    __shared__ int32_t s[1024];
-    const int i = threadIdx.x;
-    const int64_t seg = (M + 1023) / 1024;
-    const int64_t a = i * seg, b = a + seg < M ? a + seg : M;
-    int32_t own = 0;
-    for (int64_t k = a; k < b; ++k) own += counts[k];
-    s[i] = own;
-    __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const int v = i >= d ? s[i - d] : 0;
-        __syncthreads();
-        s[i] += v;
-        __syncthreads();
+__global__ void __launch_bounds__(SORT_BLOCK) k_bin_scan(int32_t* counts, const int32_t* totals, int n_blocks) {
+    __shared__ int32_t sc[SORT_BLOCK];
+    __shared__ int32_t base;
+    const int bin = blockIdx.x, i = threadIdx.x;
+    if (i == 0) {
+        int b = 0;
+        for (int k = 0; k < bin; ++k) b += totals[k];
+        base = b;
     }
-    int32_t run = s[i] - own;
-    for (int64_t k = a; k < b; ++k) {
-        const int32_t c = counts[k];
-        counts[k] = run;
-        run += c;
+    __syncthreads();
+    int32_t carry = base;
+    int32_t* row = counts + (int64_t)bin * n_blocks;
+    for (int c0 = 0; c0 < n_blocks; c0 += SORT_BLOCK) {
+        const int k = c0 + i;
+        const int32_t own = k < n_blocks ? row[k] : 0;
+        sc[i] = own;
+        __syncthreads();
+        for (int d = 1; d < SORT_BLOCK; d <<= 1) {
+            const int32_t v = i >= d ? sc[i - d] : 0;
+            __syncthreads();
+            sc[i] += v;
+            __syncthreads();
+        }
+        if (k < n_blocks) row[k] = carry + sc[i] - own;
+        carry += sc[SORT_BLOCK - 1];
+        __syncthreads();
     }
 }
 
@@ -302,13 +311,16 @@ inline int sort_blocks(int N) { return N > 0 ? (N + SORT_BLOCK - 1) / SORT_BLOCK
 inline int64_t sort_count_entries(int N) { return (int64_t)NBINS * sort_blocks(N); }
 
 // Enqueue the length sort: order[] receives the track indices, longest
-// first, equal lengths in input order; the two tile-queue heads are cleared.
+// first, equal lengths in input order.  heads: the two tile-queue heads
+// followed by the NBINS per-bin totals (all cleared here).
+constexpr int SORT_HEADS = 2 + NBINS;
+
 inline hipError_t enqueue_length_sort(const int32_t* off, int N, int max_hits, int32_t* counts, int32_t* order,
-                                      int32_t* tile_counter, hipStream_t stream) {
+                                      int32_t* heads, hipStream_t stream) {
     const int nb = sort_blocks(N);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, tile_counter, 2);
-    hipLaunchKernelGGL(k_hist, dim3(nb), dim3(SORT_BLOCK), 0, stream, off, N, max_hits, nb, counts);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, counts, sort_count_entries(N));
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(128), 0, stream, heads, SORT_HEADS);
+    hipLaunchKernelGGL(k_hist, dim3(nb), dim3(SORT_BLOCK), 0, stream, off, N, max_hits, nb, counts, heads + 2);
+    hipLaunchKernelGGL(k_bin_scan, dim3(NBINS), dim3(SORT_BLOCK), 0, stream, counts, (const int32_t*)(heads + 2), nb);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(SORT_BLOCK), 0, stream, off, N, max_hits, nb,
                        (const int32_t*)counts, order);
     return hipGetLastError();

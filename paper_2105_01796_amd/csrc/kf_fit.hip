@@ -450,7 +450,7 @@ WsLayout ws_layout(int64_t n_tracks, int max_hits) {
     L.order_off = align_up(L.fit_bytes, 256);
     L.counts_off = align_up(L.order_off + (size_t)tiles * TILE * 4, 256);
     L.counter_off = align_up(L.counts_off + (size_t)sort_count_entries((int)n_tracks) * 4, 256);
-    L.total = align_up(L.counter_off + 256, 256);
+    L.total = align_up(L.counter_off + SORT_HEADS * 4, 256);
     return L;
 }
 

@@ -574,7 +574,7 @@ VjpLayout vjp_layout(int64_t n_tracks, int64_t n_hits, int max_hits, int n_surf)
     L.order_off = align_up(p, 256);
     L.counts_off = align_up(L.order_off + (size_t)tiles * TILE * 4, 256);
     L.counter_off = align_up(L.counts_off + (size_t)sort_count_entries((int)n_tracks) * 4, 256);
-    L.total = align_up(L.counter_off + 256, 256);
+    L.total = align_up(L.counter_off + SORT_HEADS * 4, 256);
     return L;
 }
 
