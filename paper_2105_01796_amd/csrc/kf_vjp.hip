@@ -14,11 +14,12 @@
 //   backward (k = n-1 .. 0): the RTS mean recursion xs_{k-1} = xf_{k-1} + A
 //            (xs_k - xp_k) (with A dx = C_{k-1} F_k^T Cp_k^-1 dx), and the
 //            reverse of the update, the rank-one smoother-gain adjoint, the
-//            covariance transport and the propagation.  The propagation is
-//            recomputed in dual numbers, one pass per input direction (five
-//            start-state directions, six alignment directions of each of the
-//            two surfaces), and each pass is contracted with the adjoints of
-//            its outputs (predicted state, F, noise).
+//            covariance transport and the propagation.  The propagation of
+//            each gap is replayed and reversed by hand, step by step, through
+//            the RKN stages, the tangent-column (transport Jacobian) update,
+//            the capped step sizes, the final move onto the plane and the
+//            local <-> global conversions (kf_gap_reverse.hpp); the small
+//            thin-scatterer noise term by dual numbers.
 //
 // Per-hit alignment contributions go to a [6][H + N] buffer; a deterministic
 // two-level reduction (fixed chunks, then a fixed-order tree per surface)
@@ -30,6 +31,7 @@
 #include <math.h>
 #include "kf_common.hpp"
 #include "kf_adjoint.hpp"
+#include "kf_gap_reverse.hpp"
 
 namespace {
 
@@ -171,103 +173,60 @@ __device__ int vjp_fwd(const VjpArgs& a, const double* __restrict__ sm, double* 
     return status;
 }
 
-// sum of (adjoint . tangent) over the outputs of one gap: xp, F and the two
-// noise terms of the start surface
-__device__ inline double contract(const double* w, const Dual<1> xp[6], const Dual<1> F[25]) {
-    double acc = 0.0;
+// Adjoint of the thin-scatterer noise of the start surface (Highland):
+// dual-number passes over the five start-state directions and the six
+// alignment directions of surface a (the noise depends on it through n only).
+__device__ inline void noise_vjp(const double* sa, const double x[6], double mass, double q22b, double q33b,
+                                 double xb[6], double ga[6]) {
+    using D = Dual<1>;
+#pragma unroll 1
+    for (int dir = 0; dir < 11; ++dir) {
+        D xd[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) acc += w[(V_XP + i) * TILE] * xp[i].d[0];
+        for (int i = 0; i < 6; ++i) {
+            xd[i] = D(x[i]);
+            xd[i].d[0] = (i == dir) ? 1.0 : 0.0;
+        }
+        D sad[SURF_STRIDE];
+        surface_tangent<1>(sa, dir - 5, sad, 0);
+        D q22, q33;
+        highland_t<D, D>(sad, xd, mass, &q22, &q33);
+        const double acc = q22b * q22.d[0] + q33b * q33.d[0];
 #pragma unroll
-    for (int q = 0; q < 25; ++q) acc += w[(V_F + q) * TILE] * F[q].d[0];
-    return acc;
+        for (int i = 0; i < 5; ++i) xb[i] += (i == dir) ? acc : 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) ga[i] += (i == dir - 5) ? acc : 0.0;
+    }
 }
 
 // Reverse of one gap (start state x on surface sa -> predicted state on sb):
 // adds d(contracted outputs)/d(x) to xb and the derivatives with respect to
 // the alignment of sa and sb to ga and gb.  w holds the adjoints (V_XP, V_F,
-// V_Q); the start state is read from xsrc (stride xs).
+// V_Q); the start state is read from xsrc (stride xs).  The propagation is
+// reversed by hand (kf_gap_reverse.hpp), the noise by dual numbers.
 template <int FK>
 __device__ void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const double* __restrict__ sb,
-                        const double* xsrc, int64_t xs, const double* w, double xb[6], double ga[6],
-                        double gb[6]) {
-    using D = Dual<1>;
-    Field<D, FK> fl;
-    fl.init(a.field);
-    const bool noise = a.cfg.ms && sa[12] > 0.0;
-    // start-state directions loc0, loc1, phi, theta, q/p (t only shifts t)
-#pragma unroll 1
-    for (int dir = 0; dir < 5; ++dir) {
-        D x[6];
-        {
-            double xv[6];
-            load_rows(xsrc, xs, xv);
+                            const double* xsrc, int64_t xs, const double* w, double xb[6], double ga[6],
+                            double gb[6]) {
+    double x[6], xpb[6], Fb[25];
+    load_rows(xsrc, xs, x);
 #pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                x[i] = D(xv[i]);
-                x[i].d[0] = (i == dir) ? 1.0 : 0.0;
-            }
-        }
-        double acc = 0.0;
-        if (noise) {
-            D q22, q33;
-            highland_t<D, double>(sa, x, a.cfg.mass, &q22, &q33);
-            acc += w[(V_Q + 0) * TILE] * q22.d[0] + w[(V_Q + 1) * TILE] * q33.d[0];
-        }
-        D xp[6], F[25];
-        int tr;
-        transport_t<D, D, FK, double, double>(fl, a.field, a.cfg, sa, sb, x, xp, F, &tr);
-        acc += contract(w, xp, F);
+    for (int i = 0; i < 6; ++i) xpb[i] = w[(V_XP + i) * TILE];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) xb[i] += (i == dir) ? acc : 0.0;
-        phase_boundary();
-    }
-    xb[5] += w[(V_XP + 5) * TILE];
-    // alignment of the start surface
-#pragma unroll 1
-    for (int p = 0; p < 6; ++p) {
-        D x[6];
-        {
-            double xv[6];
-            load_rows(xsrc, xs, xv);
+    for (int q = 0; q < 25; ++q) Fb[q] = w[(V_F + q) * TILE];
+    double sab[13], sbb[13];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) x[i] = D(xv[i]);
-        }
-        D sad[SURF_STRIDE];
-        surface_tangent<1>(sa, p, sad, 0);
-        double acc = 0.0;
-        if (noise) {
-            D q22, q33;
-            highland_t<D, D>(sad, x, a.cfg.mass, &q22, &q33);
-            acc += w[(V_Q + 0) * TILE] * q22.d[0] + w[(V_Q + 1) * TILE] * q33.d[0];
-        }
-        D xp[6], F[25];
-        int tr;
-        transport_t<D, D, FK, D, double>(fl, a.field, a.cfg, sad, sb, x, xp, F, &tr);
-        acc += contract(w, xp, F);
+    for (int i = 0; i < 13; ++i) { sab[i] = 0.0; sbb[i] = 0.0; }
+    gap_reverse<FK>(a.field, a.cfg, sa, sb, x, xpb, Fb, xb, sab, sbb);
+    double t[6];
+    placement_to_alignment(sa, sab, t);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) ga[i] += (i == p) ? acc : 0.0;
-        phase_boundary();
-    }
-    // alignment of the target surface
-#pragma unroll 1
-    for (int p = 0; p < 6; ++p) {
-        D x[6];
-        {
-            double xv[6];
-            load_rows(xsrc, xs, xv);
+    for (int i = 0; i < 6; ++i) ga[i] += t[i];
+    placement_to_alignment(sb, sbb, t);
 #pragma unroll
-            for (int i = 0; i < 6; ++i) x[i] = D(xv[i]);
-        }
-        D sbd[SURF_STRIDE];
-        surface_tangent<1>(sb, p, sbd, 0);
-        D xp[6], F[25];
-        int tr;
-        transport_t<D, D, FK, double, D>(fl, a.field, a.cfg, sa, sbd, x, xp, F, &tr);
-        const double acc = contract(w, xp, F);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) gb[i] += (i == p) ? acc : 0.0;
-        phase_boundary();
-    }
+    for (int i = 0; i < 6; ++i) gb[i] += t[i];
+    if (a.cfg.ms && sa[12] > 0.0)
+        noise_vjp(sa, x, a.cfg.mass, w[(V_Q + 0) * TILE], w[(V_Q + 1) * TILE], xb, ga);
 }
 
 // ---------------------------------------------------------------------------
