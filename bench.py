@@ -46,7 +46,7 @@ WORKLOADS = {
 }
 
 
-FIT_SOURCES = ("kf_fit.hip", "kf_common.hpp", "kf_device.hpp", "kf_dual.hpp")
+FIT_SOURCES = ("kf_fit.hip", "kf_common.hpp", "kf_device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fwd_c2_1e5_traffic.txt")
 
 

@@ -5,10 +5,8 @@
 // (Sect. 2), the gain-matrix update, the FP64 smoother-gain solve and the
 // covariance transport by hand-derived matrix adjoints below.  The
 // propagation (RKN stepping with its transport Jacobian, landing, local <->
-// global conversions, thin-scatterer noise) is differentiated by forward
-// tangents (dual numbers) in every input direction that matters -- the start
-// state and the alignment of both surfaces -- and contracted with the
-// adjoints of its outputs; it is recomputed, never stored.
+// global conversions) is reversed step by step in kf_gap_reverse.hpp; it is
+// recomputed, never stored.
 //
 // Symmetric matrices are held packed (21 entries, sy(i, j)).  The adjoint of
 // a symmetric matrix X is kept as the symmetric matrix Xb with
@@ -196,33 +194,6 @@ __device__ inline void covtransport_vjp(const double F[25], const double CQ[21],
             for (int k = 0; k < 6; ++k) acc += W[i][k] * CQ[sy(k, j)];
             Fb[frow(i) * 5 + j] += 2.0 * acc;
         }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// alignment a = (dx, dy, dz, alpha, beta, gamma) of a surface about its
-// current placement: c <- c + d, R <- R Rx(alpha) Ry(beta) Rz(gamma)
-// (rotations about the local u, v, n axes).  Tangent of the 13 surface values
-// in direction p: e_p on the centre for p < 3; for a rotation about local
-// axis a = p - 3, column j of dR is R (e_a x e_j).  Written without branches
-// on p: a branch-per-axis form of this function was miscompiled for gfx950
-// (ROCm 7.2) inside the adjoint kernel (one axis received stale registers).
-// ---------------------------------------------------------------------------
-template <int K>
-__device__ inline void surface_tangent(const double* s, int p, Dual<K>* o, int slot_k) {
-#pragma unroll
-    for (int i = 0; i < 13; ++i) o[i] = Dual<K>(s[i]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) o[i].d[slot_k] = (i == p) ? 1.0 : 0.0;
-    const double ea[3] = {p == 3 ? 1.0 : 0.0, p == 4 ? 1.0 : 0.0, p == 5 ? 1.0 : 0.0};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const double ej[3] = {j == 0 ? 1.0 : 0.0, j == 1 ? 1.0 : 0.0, j == 2 ? 1.0 : 0.0};
-        const double c[3] = {ea[1] * ej[2] - ea[2] * ej[1], ea[2] * ej[0] - ea[0] * ej[2],
-                             ea[0] * ej[1] - ea[1] * ej[0]};
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-            o[3 + 3 * i + j].d[slot_k] = s[3 + 3 * i + 0] * c[0] + s[3 + 3 * i + 1] * c[1] + s[3 + 3 * i + 2] * c[2];
     }
 }
 

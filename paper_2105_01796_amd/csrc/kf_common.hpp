@@ -21,13 +21,24 @@ constexpr int TILE = 64;    // tracks per tile = lanes per wave
 
 __device__ inline bool finite(double v) { return isfinite(v); }
 
+// Device-memory pointers in the global address space.  Kernel arguments and
+// pointers passed through structs are generic (flat) to the compiler; a flat
+// access also counts against the LDS/scalar wait counter, so every LDS wait
+// behind it would wait for the memory access as well.  Casting to address
+// space 1 makes the compiler emit global_load / global_store.
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* gbl(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // Component-major rows: v[i] lives at p + i * stride.  The running pointer
 // is kept opaque so the compiler adds the stride per row at the point of use
 // instead of computing all N per-lane addresses once and keeping them live
 // across the whole fit (27 64-bit addresses would otherwise occupy 54
 // registers for the track's lifetime).
 template <int N>
-__device__ inline void store_rows(double* p, int64_t stride, const double (&v)[N]) {
+__device__ inline void store_rows(double* p0, int64_t stride, const double (&v)[N]) {
+    auto p = gbl(p0);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         *p = v[i];
@@ -37,7 +48,8 @@ __device__ inline void store_rows(double* p, int64_t stride, const double (&v)[N
 }
 
 template <int N>
-__device__ inline void load_rows(const double* p, int64_t stride, double (&v)[N]) {
+__device__ inline void load_rows(const double* p0, int64_t stride, double (&v)[N]) {
+    auto p = gbl(p0);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         v[i] = *p;
@@ -47,7 +59,8 @@ __device__ inline void load_rows(const double* p, int64_t stride, double (&v)[N]
 }
 
 template <int N>
-__device__ inline void fill_rows(double* p, int64_t stride, double val) {
+__device__ inline void fill_rows(double* p0, int64_t stride, double val) {
+    auto p = gbl(p0);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         *p = val;

@@ -13,7 +13,6 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
-#include "kf_dual.hpp"
 
 namespace kfm {
 
@@ -221,14 +220,14 @@ __device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& 
 // FP64 anchor; the landing loop stops at an FP32-resolvable distance and the
 // same FP64 second-order move finishes it.
 // ---------------------------------------------------------------------------
-// R is the type of the FP64-precision quantities (double, or a dual number in
-// the adjoint); P the stepping type (double, float for MIXED, or the same
-// dual type).  Surfaces a and b are read as SA / SB values, 13 each
-// (c, R, x/X0): plain doubles, or dual numbers carrying an alignment tangent.
-template <class R, class P, int FK, class SA, class SB>
-__device__ inline int transport_t(const Field<P, FK>& fl, const FieldDef& fd, const Cfg& cfg, const SA* sa,
-                                  const SB* sb, const R x[6], R xp[6], R F[25], int* trials_out) {
-    using V = typename ValueOf<P>::type;    // plain type for step-control bookkeeping
+// P is the stepping type (double, or float for MIXED); everything else is
+// FP64.  Surfaces a and b are 13 values each (c, R, x/X0).
+template <class P, int FK>
+__device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, const Cfg& cfg,
+                                const double* __restrict__ sa, const double* __restrict__ sb,
+                                const double x[6], double xp[6], double F[25], int* trials_out) {
+    using R = double;
+    using V = P;    // step-control bookkeeping
     // bound -> free on surface a
     R sp, cp, st, ct;
     sincos(x[2], &sp, &cp);
@@ -282,17 +281,17 @@ __device__ inline int transport_t(const Field<P, FK>& fl, const FieldDef& fd, co
         const R nTd = nb[0] * Td[0] + nb[1] * Td[1] + nb[2] * Td[2];
         const R distd = d0 - (nb[0] * rl[0] + nb[1] * rl[1] + nb[2] * rl[2])
                             - (nb[0] * R(dr[0]) + nb[1] * R(dr[1]) + nb[2] * R(dr[2]));
-        if (::fabs(val(nTd)) < 1e-6) { status = ST_NO_INTERSECT; break; }
+        if (::fabs(nTd) < 1e-6) { status = ST_NO_INTERSECT; break; }
         // FP32 curvature increments resolve ~1e-7 mm; the FP64 move below finishes the landing
         const double ltol = mixed ? 1e-5 : cfg.land_tol;
-        if (::fabs(val(distd)) < ltol) break;
+        if (::fabs(distd) < ltol) break;
         if (trials >= cfg.max_steps) { status = ST_STEP_CAP; break; }
         const P d = P(distd / nTd);
-        const V dv = V(val(d));
+        const V dv = d;
         if (hmag < V(0)) hmag = dv < V(0) ? -dv : dv;
         const P h = ((dv < V(0) ? -dv : dv) <= hmag) ? d : P(dv < V(0) ? -hmag : hmag);
         P k[4][3];
-        const V err = V(val(rkn_trial<P, FK>(fl, rabs, T, lam, h, S, k)));
+        const V err = rkn_trial<P, FK>(fl, rabs, T, lam, h, S, k);
         ++trials;
         phase_boundary();
         const V tiny = V(mixed ? 1e-30 : 1e-300);
@@ -311,7 +310,7 @@ __device__ inline int transport_t(const Field<P, FK>& fl, const FieldDef& fd, co
             }
             dt = dt + hd * gd;
         }
-        const V hv = V(val(h));
+        const V hv = h;
         hmag = (hv < V(0) ? -hv : hv) * fac;
     }
     *trials_out = trials;
@@ -386,35 +385,23 @@ __device__ inline int transport_t(const Field<P, FK>& fl, const FieldDef& fd, co
     return ST_OK;
 }
 
-template <class P, int FK>
-__device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, const Cfg& cfg,
-                                const double* __restrict__ sa, const double* __restrict__ sb,
-                                const double x[6], double xp[6], double F[25], int* trials_out) {
-    return transport_t<double, P, FK, double, double>(fl, fd, cfg, sa, sb, x, xp, F, trials_out);
-}
-
 // ---------------------------------------------------------------------------
 // thin-scatterer noise on surface s for the filtered state x (PDG Highland)
 // Q = diag(0, 0, theta0^2 / sin^2(theta), theta0^2, 0, 0)
 // ---------------------------------------------------------------------------
-template <class R, class Surf>
-__device__ inline void highland_t(const Surf* s, const R x[6], double mass, R* q22, R* q33) {
-    const double x0 = val(s[12]);
-    if (!(x0 > 0.0)) { *q22 = R(0.0); *q33 = R(0.0); return; }
-    R sp, cp, st, ct;
+__device__ inline void highland(const double* __restrict__ s, const double x[6], double mass, double* q22, double* q33) {
+    const double x0 = s[12];
+    if (!(x0 > 0.0)) { *q22 = 0.0; *q33 = 0.0; return; }
+    double sp, cp, st, ct;
     sincos(x[2], &sp, &cp);
     sincos(x[3], &st, &ct);
-    const R nT = s[3 + 2] * cp * st + s[3 + 5] * sp * st + s[3 + 8] * ct;
-    const R path = x0 / fabs(nT);
-    const R p = 1.0 / fabs(x[4]);
-    const R beta = p / sqrt(p * p + mass * mass);
-    const R th0 = 0.0136 / (beta * p) * sqrt(path) * (1.0 + 0.038 * log(path / (beta * beta)));
+    const double nT = s[3 + 2] * cp * st + s[3 + 5] * sp * st + s[3 + 8] * ct;
+    const double path = x0 / fabs(nT);
+    const double p = 1.0 / fabs(x[4]);
+    const double beta = p / sqrt(p * p + mass * mass);
+    const double th0 = 0.0136 / (beta * p) * sqrt(path) * (1.0 + 0.038 * log(path / (beta * beta)));
     *q33 = th0 * th0;
     *q22 = th0 * th0 / (st * st);
-}
-
-__device__ inline void highland(const double* __restrict__ s, const double x[6], double mass, double* q22, double* q33) {
-    highland_t<double, double>(s, x, mass, q22, q33);
 }
 
 // ---------------------------------------------------------------------------

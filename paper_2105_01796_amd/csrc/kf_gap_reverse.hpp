@@ -9,7 +9,7 @@
 //
 // The step sequence is the forward pass's: gap_run replays the adaptive loop
 // with the same routines (rkn_trial, rkn_tangent) and the same expressions as
-// transport_t, so it takes the same decisions.  Reverse order: the final part
+// transport, so it takes the same decisions.  Reverse order: the final part
 // (free -> bound, F, final move) at the landed state, then the accepted steps
 // from last to first, the state at the start of each recovered by replaying
 // the gap from its start (a few steps per gap, so the quadratic replay cost
@@ -75,7 +75,7 @@ __device__ inline void gap_start(const Cfg& cfg, const double* sa, const double*
     g.accepted = 0;
 }
 
-// Replay the adaptive loop (the expressions of transport_t with R = P =
+// Replay the adaptive loop (the expressions of transport with P =
 // double).  Returns 1 when the accepted step number `stop` is reached, with
 // the state at its start and its h, capped flag, stages and k; 0 when the gap
 // has landed (state before the final move); -1 if the replay fails.
@@ -355,6 +355,7 @@ __device__ inline void step_reverse(const Field<double, FK>& fl, const double* s
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) { gb.Mr[i][j] = Mrb[i]; gb.MT[i][j] = MTb[i]; }
+        phase_boundary();   // one column's temporaries at a time
     }
     // (d) primal stages, 4 -> 1: k_st = lk T_st x B(r_st)
 #pragma unroll

@@ -78,14 +78,16 @@ struct VjpArgs {
 
 template <int N>
 __device__ inline void ld(const double* w, int off, double (&v)[N]) {
+    auto g = gbl(w);
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = w[(off + i) * TILE];
+    for (int i = 0; i < N; ++i) v[i] = g[(off + i) * TILE];
 }
 
 template <int N>
 __device__ inline void st(double* w, int off, const double (&v)[N]) {
+    auto g = gbl(w);
 #pragma unroll
-    for (int i = 0; i < N; ++i) w[(off + i) * TILE] = v[i];
+    for (int i = 0; i < N; ++i) g[(off + i) * TILE] = v[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -107,7 +109,7 @@ __device__ int vjp_fwd(const VjpArgs& a, const double* __restrict__ sm, double* 
     int prev = a.seed_sid;
     int status = ST_OK;
     for (int k = 0; k < n; ++k) {
-        const int s = a.sid[o + k];
+        const int s = gbl(a.sid)[o + k];
         const double* sa = sm + prev * SURF_STRIDE;
         const double* sb = sm + s * SURF_STRIDE;
         double q[2] = {0.0, 0.0};
@@ -173,51 +175,70 @@ __device__ int vjp_fwd(const VjpArgs& a, const double* __restrict__ sm, double* 
     return status;
 }
 
-// Adjoint of the thin-scatterer noise of the start surface (Highland):
-// dual-number passes over the five start-state directions and the six
-// alignment directions of surface a (the noise depends on it through n only).
+// Adjoint of the thin-scatterer noise of the start surface (PDG Highland
+// width as in highland): q33 = th0^2, q22 = th0^2 / sin^2(theta) with
+// th0 = K / (beta p) sqrt(l) (1 + c log(l / beta^2)), l = x/X0 / |n.T|,
+// p = 1 / |q/p|, beta = p / sqrt(p^2 + m^2).  Adds to xb (phi, theta, q/p)
+// and to the adjoint of surface a's normal n (column 2 of R, entries
+// sab[3 + 3 i + 2]).
 __device__ inline void noise_vjp(const double* sa, const double x[6], double mass, double q22b, double q33b,
-                                 double xb[6], double ga[6]) {
-    using D = Dual<1>;
-#pragma unroll 1
-    for (int dir = 0; dir < 11; ++dir) {
-        D xd[6];
+                                 double xb[6], double sab[13]) {
+    constexpr double K = 0.0136, c = 0.038;
+    const double x0 = sa[12];
+    double sp, cp, st, ct;
+    sincos(x[2], &sp, &cp);
+    sincos(x[3], &st, &ct);
+    const double n[3] = {sa[3 + 2], sa[3 + 5], sa[3 + 8]};
+    const double T[3] = {cp * st, sp * st, ct};
+    const double dTdp[3] = {-sp * st, cp * st, 0.0};
+    const double dTdt[3] = {cp * ct, sp * ct, -st};
+    const double a = n[0] * T[0] + n[1] * T[1] + n[2] * T[2];
+    const double ell = x0 / fabs(a);
+    const double p = 1.0 / fabs(x[4]);
+    const double E = sqrt(p * p + mass * mass);
+    const double beta = p / E;
+    const double A = K / (beta * p);
+    const double sq = sqrt(ell);
+    const double th0 = A * sq * (1.0 + c * log(ell / (beta * beta)));
+    const double is2 = 1.0 / (st * st);
+    const double th0b = 2.0 * th0 * (q33b + q22b * is2);
+    xb[3] += q22b * (-2.0 * th0 * th0 * ct * is2 / st);
+    // through the path length l = x0 / |a|, a = n.T
+    const double ab = th0b * (th0 / (2.0 * ell) + A * c / sq) * (-ell / a);
+    xb[2] += ab * (n[0] * dTdp[0] + n[1] * dTdp[1] + n[2] * dTdp[2]);
+    xb[3] += ab * (n[0] * dTdt[0] + n[1] * dTdt[1] + n[2] * dTdt[2]);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            xd[i] = D(x[i]);
-            xd[i].d[0] = (i == dir) ? 1.0 : 0.0;
-        }
-        D sad[SURF_STRIDE];
-        surface_tangent<1>(sa, dir - 5, sad, 0);
-        D q22, q33;
-        highland_t<D, D>(sad, xd, mass, &q22, &q33);
-        const double acc = q22b * q22.d[0] + q33b * q33.d[0];
-#pragma unroll
-        for (int i = 0; i < 5; ++i) xb[i] += (i == dir) ? acc : 0.0;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) ga[i] += (i == dir - 5) ? acc : 0.0;
-    }
+    for (int i = 0; i < 3; ++i) sab[3 + 3 * i + 2] += ab * T[i];
+    // through p and beta
+    const double dth_dp = -th0 / p;
+    const double dth_dbeta = -th0 / beta - 2.0 * A * c * sq / beta;
+    const double dbeta_dp = mass * mass / (E * E * E);
+    const double dp_dlam = (x[4] < 0.0 ? 1.0 : -1.0) * p * p;
+    xb[4] += th0b * (dth_dp + dth_dbeta * dbeta_dp) * dp_dlam;
 }
 
 // Reverse of one gap (start state x on surface sa -> predicted state on sb):
 // adds d(contracted outputs)/d(x) to xb and the derivatives with respect to
 // the alignment of sa and sb to ga and gb.  w holds the adjoints (V_XP, V_F,
 // V_Q); the start state is read from xsrc (stride xs).  The propagation is
-// reversed by hand (kf_gap_reverse.hpp), the noise by dual numbers.
+// reversed by hand (kf_gap_reverse.hpp), the noise by its closed-form
+// derivative.
 template <int FK>
 __device__ void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const double* __restrict__ sb,
-                            const double* xsrc, int64_t xs, const double* w, double xb[6], double ga[6],
-                            double gb[6]) {
+                        const double* xsrc, int64_t xs, const double* w, double xb[6], double ga[6],
+                        double gb[6]) {
     double x[6], xpb[6], Fb[25];
     load_rows(xsrc, xs, x);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) xpb[i] = w[(V_XP + i) * TILE];
+    for (int i = 0; i < 6; ++i) xpb[i] = gbl(w)[(V_XP + i) * TILE];
 #pragma unroll
-    for (int q = 0; q < 25; ++q) Fb[q] = w[(V_F + q) * TILE];
+    for (int q = 0; q < 25; ++q) Fb[q] = gbl(w)[(V_F + q) * TILE];
     double sab[13], sbb[13];
 #pragma unroll
     for (int i = 0; i < 13; ++i) { sab[i] = 0.0; sbb[i] = 0.0; }
     gap_reverse<FK>(a.field, a.cfg, sa, sb, x, xpb, Fb, xb, sab, sbb);
+    if (a.cfg.ms && sa[12] > 0.0)
+        noise_vjp(sa, x, a.cfg.mass, gbl(w)[(V_Q + 0) * TILE], gbl(w)[(V_Q + 1) * TILE], xb, sab);
     double t[6];
     placement_to_alignment(sa, sab, t);
 #pragma unroll
@@ -225,8 +246,6 @@ __device__ void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const d
     placement_to_alignment(sb, sbb, t);
 #pragma unroll
     for (int i = 0; i < 6; ++i) gb[i] += t[i];
-    if (a.cfg.ms && sa[12] > 0.0)
-        noise_vjp(sa, x, a.cfg.mass, w[(V_Q + 0) * TILE], w[(V_Q + 1) * TILE], xb, ga);
 }
 
 // ---------------------------------------------------------------------------
@@ -235,7 +254,7 @@ __device__ void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const d
 template <int FK>
 __device__ void vjp_bwd(const VjpArgs& a, const double* __restrict__ sm, double* wl, int t, int o, int n) {
     const int64_t H = a.n_hits, N = a.n_tracks;
-    const double chi2b = a.g_chi2 ? a.g_chi2[t] : 0.0;
+    const double chi2b = a.g_chi2 ? gbl(a.g_chi2)[t] : 0.0;
     double xs[6], xsb[6], xfb[6], Cfb[21], aab[6];
     {
         const double* w = wl + (n - 1) * (NCV * TILE);
@@ -256,8 +275,8 @@ __device__ void vjp_bwd(const VjpArgs& a, const double* __restrict__ sm, double*
     for (int k = n - 1; k >= 0; --k) {
         double* w = wl + k * (NCV * TILE);
         const double* wp = w - NCV * TILE;           // slot k-1 (used only for k > 0)
-        const int s = a.sid[o + k];
-        const int prev = k > 0 ? a.sid[o + k - 1] : a.seed_sid;
+        const int s = gbl(a.sid)[o + k];
+        const int prev = k > 0 ? gbl(a.sid)[o + k - 1] : a.seed_sid;
         double xpb[6], Cpb[21], wv[6];
         // ---- update adjoint, and w = Cp^-1 (xs_k - xp_k) ----
         {
@@ -389,7 +408,7 @@ __device__ void vjp_one(const VjpArgs& a, const double* __restrict__ sm, int64_t
         for (int k = 0; k < n; ++k) fill_rows<2>(a.g_meas + o + k, H, nan);
         if (a.g_seed) fill_rows<6>(a.g_seed + t, N, nan);
     }
-    a.status[t] = (uint8_t)status;
+    gbl(a.status)[t] = (uint8_t)status;
 }
 
 template <int FK, bool SORTED>
