@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--occupancy", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--jacobians", choices=("store", "recompute"), default="store",
+                    help="without --autotune: transport Jacobians stored for the smoother or recomputed by it")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the fit + adjoint leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -148,7 +150,8 @@ def main():
     batch = kfmi.Batch.from_event(ev, device=dev)
     N = ev.n_tracks
     base_opt = dict(schedule=args.schedule, block=args.block, occupancy=args.occupancy,
-                    waves_per_cu=args.waves_per_cu)
+                    waves_per_cu=args.waves_per_cu,
+                    jacobians=kfmi.KF_JAC_RECOMPUTE if args.jacobians == "recompute" else kfmi.KF_JAC_STORE)
 
     if args.copy_calibration:
         src = torch.empty(1 << 26, dtype=torch.float64, device=dev).fill_(1.0)
@@ -165,6 +168,7 @@ def main():
             opt, tune_ms = plan.autotune()
             tuned = {"schedule": opt.schedule, "block": opt.block, "occupancy": opt.occupancy,
                      "waves_per_cu": opt.waves_per_cu, "split_smoother": opt.split_smoother,
+                     "jacobians": "recompute" if opt.jacobians == kfmi.KF_JAC_RECOMPUTE else "store",
                      "tuner_ms": round(tune_ms, 4)}
         if not args.no_graph:
             plan.capture()

@@ -83,6 +83,9 @@ extern "C" {
 #define KF_SCHED_SORTED 2      /* tracks sorted by hit count (longest first), persistent waves
                                   pull 64-track tiles from a queue */
 
+#define KF_JAC_STORE 0         /* transport Jacobians stored by the filter, read by the smoother */
+#define KF_JAC_RECOMPUTE 1     /* smoother re-propagates the filtered state (less memory traffic) */
+
 #define KF_MAX_SURFACES 512     /* the surface table is staged in LDS (13 doubles each) */
 #define KF_MAX_HITS 64         /* per track */
 
@@ -133,6 +136,10 @@ typedef struct {
     int32_t waves_per_cu;        /* persistent schedule: resident waves per CU, 0 = autotuned */
     int32_t occupancy;           /* register budget as waves per SIMD (1, 2, 3), 0 = autotuned */
     int32_t split_smoother;      /* 0: smoother in the same kernel as the filter; 1: separate kernel */
+    int32_t jacobians;           /* KF_JAC_STORE: the filter stores each transport Jacobian for the
+                                    smoother (52 workspace doubles per hit); KF_JAC_RECOMPUTE: the
+                                    smoother propagates each filtered state again instead (27 doubles
+                                    per hit; fused smoother only) */
 } kf_config;
 
 typedef struct {
@@ -183,7 +190,8 @@ void kf_plan_destroy(kf_plan *plan);
 /* Launch-shape autotuner (the paper's grid/block/register studies, Sect. 5.3,
  * made automatic): times every candidate schedule (direct / length-sorted
  * persistent), workgroup size, register budget (waves per SIMD), fused or
- * separate smoother kernel and persistent waves per CU on these very buffers
+ * separate smoother kernel, stored or recomputed transport Jacobians and
+ * persistent waves per CU on these very buffers
  * (outputs are overwritten), synchronising `stream`.  Writes the fastest
  * setting to *best (and its time per fit to *best_ms if not NULL) and
  * remembers it: later calls with AUTO (0) settings and the same precision,
@@ -203,9 +211,10 @@ int kf_autotune(const kf_config *cfg, const kf_surfaces *surf, const kf_field *f
  * adaptive RKN propagation with its transport Jacobian (Sect. 4.1), including
  * the dependence of that Jacobian on the state.  The forward fit is recomputed
  * per track (nothing from an earlier kf_fit_tracks call is reused); the
- * propagation of each gap is recomputed again, in forward-mode dual numbers,
- * for the start state and the alignment of both surfaces, and contracted with
- * the reverse-mode adjoints of the Kalman and smoother algebra.  Every step of
+ * propagation of each gap is replayed with the forward pass's own step
+ * decisions and reversed step by step (stages, transport-Jacobian columns,
+ * step sizes capped at the target plane, landing, local <-> global maps), so
+ * the gradient is that of the discrete fit the forward call computes.  Every step of
  * the adjoint runs in FP64 whatever cfg->precision says.  The alignment
  * gradient of a surface sums over all tracks in a fixed order: the result is
  * bitwise reproducible.  A track whose recomputed fit fails contributes

@@ -3,13 +3,15 @@
 // Forward filter + RTS smoother (Sect. 2; Sect. 4.1), one lane per track:
 //   * the surface table is staged once per workgroup in LDS, next to a
 //     per-lane slot for the filtered covariance carried from hit to hit;
-//   * the forward pass writes, per hit, only what the smoother cannot
-//     recompute cheaply -- the predicted state and covariance and the
-//     transport Jacobian F (Sect. 2: the smoother uses the Jacobians stored
-//     in the forward pass) -- to a tile-major workspace
+//   * the forward pass writes, per hit, the predicted state and covariance
+//     and the transport Jacobian F (Sect. 2: the smoother uses the Jacobians
+//     stored in the forward pass) to a tile-major workspace
 //     [tile][hit][component][64 lanes]: a wave's 64 lanes store/load 64
 //     consecutive doubles (coalesced), and every component sits at a
-//     compile-time offset from one per-lane base;
+//     compile-time offset from one per-lane base.  With KF_JAC_RECOMPUTE the
+//     Jacobian is not stored: the smoother propagates each filtered state
+//     again (27 instead of 52 doubles per hit travel through memory, one more
+//     propagation per hit);
 //   * the backward pass recomputes each filtered state from the stored
 //     prediction and the hit (the same update, bit for bit), solves the RTS
 //     gain in FP64 (Cholesky of the predicted covariance, Sect. 4.2.4),
@@ -30,9 +32,12 @@
 namespace {
 
 // workspace doubles per hit: predicted state xp 6, Cp 21; transport Jacobian
-// F into this hit (25 stored entries)
+// F into this hit (25 stored entries) unless the smoother recomputes it
 constexpr int NC = 52;
+constexpr int NC_RECOMPUTE = 27;
 constexpr int OFF_XP = 0, OFF_CP = 6, OFF_F = 27;
+template <bool STOREF>
+constexpr int nc_of() { return STOREF ? NC : NC_RECOMPUTE; }
 // LDS per wave: the carried filtered covariance [21][64 lanes] during the
 // filter; after the smoother the same area holds the output transpose of
 // flush_tile (FLUSH_GROUP components x FLUSH_HITS hits x 64 lanes doubles,
@@ -49,7 +54,7 @@ struct FitArgs {
     int seed_sid;
     int max_hits;
     int64_t n_hits;
-    int64_t tile_doubles;       // workspace doubles per 64-track tile = max_hits * NC * 64
+    int64_t tile_doubles;       // workspace doubles per 64-track tile = max_hits * (NC or NC_RECOMPUTE) * 64
     const int32_t* off;
     const int32_t* sid;
     const double* loc;
@@ -88,9 +93,10 @@ struct FitArgs {
 // checks every hit before it fits).  `cl` is this lane's LDS slot for the
 // filtered covariance between hits (component c at cl[c * 64]).  Writes
 // chi2, ndf and status; a failed track gets NaN outputs here (the backward
-// pass skips it).
-template <class P, int FK>
+// pass skips it).  STOREF: store the transport Jacobians for the smoother.
+template <class P, int FK, bool STOREF>
 __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double* cl, int64_t slot, int t) {
+    constexpr int NW = nc_of<STOREF>();
     const int64_t H = a.n_hits;
     const int64_t N = a.n_tracks;
     int o, n;
@@ -99,7 +105,7 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
     load_rows(a.seed + t, N, x);
     Field<P, FK> fl;
     fl.init(a.field);
-    // this lane's column of its tile: component c of hit k at wl[(k * NC + c) * TILE]
+    // this lane's column of its tile: component c of hit k at wl[(k * NW + c) * TILE]
     double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
     double chi2 = 0.0;
     // hit k's surface and measurement, loaded during hit k-1
@@ -134,11 +140,13 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
         if (a.trials) a.trials[o + k] = tr;
         if (status != ST_OK) break;
         phase_boundary();
-        double* w = wl + k * (NC * TILE);
+        double* w = wl + k * (NW * TILE);
 #pragma unroll
         for (int i = 0; i < 6; ++i) w[(OFF_XP + i) * TILE] = xp[i];
+        if (STOREF) {
 #pragma unroll
-        for (int q = 0; q < 25; ++q) w[(OFF_F + q) * TILE] = F[q];
+            for (int q = 0; q < 25; ++q) w[(OFF_F + q) * TILE] = F[q];
+        }
         // the previous filtered covariance waits in LDS during the propagation
         double Cp[21];
         {
@@ -199,20 +207,27 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
 // follows from the next hit's stored prediction and Jacobian with the gain
 // A = Cf F^T Cp^-1 solved in FP64.  The smoothed state of hit k replaces the
 // prediction in slot k once that has been read for the last time; flush_tile
-// then writes the tile's CSR outputs.  Returns true if the track's smoothed
-// states are in its slots (false: not fitted, or failed here with NaN outputs).
-__device__ bool bwd_one(const FitArgs& a, int64_t slot, int t) {
+// then writes the tile's CSR outputs.  Without stored Jacobians (STOREF
+// false; fused only, sm is the surface table) F of the gap k -> k+1 comes from
+// propagating the recomputed filtered state of hit k (or the seed) again with
+// the forward pass's routine.  Returns true if the track's smoothed states are
+// in its slots (false: not fitted, or failed here with NaN outputs).
+template <class P, int FK, bool STOREF>
+__device__ bool bwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
+    constexpr int NW = nc_of<STOREF>();
     if (a.status[t] != ST_OK) return false;
     const int o = a.off[t];
     const int n = a.off[t + 1] - o;
     const int64_t H = a.n_hits;
     const int64_t N = a.n_tracks;
     double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
+    Field<P, FK> fl;
+    if (!STOREF) fl.init(a.field);
     // prediction of hit k+1 (carried from one step to the next)
     double xp1[6], Cp1[21];
     double x[6], C[21];
     {
-        const double* w = wl + (n - 1) * (NC * TILE);
+        const double* w = wl + (n - 1) * (NW * TILE);
         double m[2], V[3], ck;
 #pragma unroll
         for (int i = 0; i < 6; ++i) xp1[i] = w[(OFF_XP + i) * TILE];
@@ -223,21 +238,27 @@ __device__ bool bwd_one(const FitArgs& a, int64_t slot, int t) {
         kalman_update(xp1, Cp1, m, V, x, C, &ck);
     }
     bool spd = true;
+    int fail = ST_OK;
+    int s1 = STOREF ? 0 : a.sid[o + n - 1];          // surface of hit k+1
     for (int k = n - 2; k >= -1; --k) {
-        double* w1 = wl + (k + 1) * (NC * TILE);
-        // every load of this step at once: F of hit k+1, the prediction and
-        // measurement of hit k (or the seed)
+        double* w1 = wl + (k + 1) * (NW * TILE);
+        // every load of this step at once: F of hit k+1 (if stored), the
+        // prediction and measurement of hit k (or the seed)
         double F[25], xp[6], Cp[21], m[2], V[3], xf[6], Cf[21];
+        if (STOREF) {
 #pragma unroll
-        for (int q = 0; q < 25; ++q) F[q] = w1[(OFF_F + q) * TILE];
+            for (int q = 0; q < 25; ++q) F[q] = w1[(OFF_F + q) * TILE];
+        }
+        int s0 = a.seed_sid;
         if (k >= 0) {
-            const double* w = wl + k * (NC * TILE);
+            const double* w = wl + k * (NW * TILE);
 #pragma unroll
             for (int i = 0; i < 6; ++i) xp[i] = w[(OFF_XP + i) * TILE];
 #pragma unroll
             for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
             load_rows(a.loc + o + k, H, m);
             load_rows(a.cov + o + k, H, V);
+            if (!STOREF) s0 = a.sid[o + k];
         } else {
             load_rows(a.seed + t, N, xf);
             load_rows(a.seed_cov + t, N, Cf);
@@ -258,6 +279,16 @@ __device__ bool bwd_one(const FitArgs& a, int64_t slot, int t) {
 #pragma unroll
             for (int q = 0; q < 21; ++q) Cp1[q] = Cp[q];
         }
+        if (!STOREF) {
+            // F of the gap from hit k (or the seed) to hit k+1, as the forward pass propagated it
+            phase_boundary();
+            double xq[6];
+            int tr = 0;
+            const int st = transport<P, FK>(fl, a.field, a.cfg, sm + s0 * SURF_STRIDE, sm + s1 * SURF_STRIDE, xf,
+                                            xq, F, &tr);
+            if (st != ST_OK && fail == ST_OK) fail = st;
+            s1 = s0;
+        }
         phase_boundary();
         double A[36];
 #pragma unroll
@@ -274,12 +305,13 @@ __device__ bool bwd_one(const FitArgs& a, int64_t slot, int t) {
         for (int q = 0; q < 21; ++q) C[q] = Cf[q];
         phase_boundary();
     }
-    if (spd) {
+    if (spd && fail == ST_OK) {
         store_rows(a.tgt_par + t, N, x);
         store_rows(a.tgt_cov + t, N, C);
         return true;
     }
-    // a predicted covariance that is not positive definite: the track fails
+    // a predicted covariance that is not positive definite (or a propagation
+    // that did not repeat): the track fails
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
     for (int k = 0; k < n; ++k) {
         fill_rows<6>(a.par + o + k, H, nan);
@@ -288,7 +320,7 @@ __device__ bool bwd_one(const FitArgs& a, int64_t slot, int t) {
     fill_rows<6>(a.tgt_par + t, N, nan);
     fill_rows<21>(a.tgt_cov + t, N, nan);
     a.chi2[t] = nan;
-    a.status[t] = (uint8_t)ST_NOT_SPD;
+    a.status[t] = (uint8_t)(fail != ST_OK ? fail : ST_NOT_SPD);
     return false;
 }
 
@@ -310,7 +342,9 @@ __device__ inline void wave_sync() {
 // components at a time, the values pass through LDS so that consecutive
 // lanes store consecutive CSR entries.  Every lane of the wave must call it
 // (done: this lane's track has results; o, n: its CSR range).  lw: this
-// wave's LDS area (free once the smoother has finished).
+// wave's LDS area (free once the smoother has finished).  NW: workspace
+// doubles per hit.
+template <int NW>
 __device__ void flush_tile(const FitArgs& a, double* lw, const double* wtile, bool done, int o, int n) {
     const int lane = threadIdx.x & (TILE - 1);
     double* tb = lw;                                                    // [FLUSH_GROUP][FLUSH_HITS][64]
@@ -328,12 +362,12 @@ __device__ void flush_tile(const FitArgs& a, double* lw, const double* wtile, bo
         const int cnt = nl - hb < 0 ? 0 : (nl - hb > FLUSH_HITS ? FLUSH_HITS : nl - hb);
         // every value of this block first: one wait for all of them
         double v[27][FLUSH_HITS];
-        const double* src = wtile + (int64_t)hb * (NC * TILE) + OFF_XP * TILE + lane;
+        const double* src = wtile + (int64_t)hb * (NW * TILE) + OFF_XP * TILE + lane;
 #pragma unroll
         for (int c = 0; c < 27; ++c)
 #pragma unroll
             for (int h = 0; h < FLUSH_HITS; ++h)
-                v[c][h] = h < cnt ? src[(int64_t)h * (NC * TILE) + c * TILE] : 0.0;
+                v[c][h] = h < cnt ? src[(int64_t)h * (NW * TILE) + c * TILE] : 0.0;
         // exclusive prefix of cnt over the wave
         int inc = cnt;
 #pragma unroll
@@ -375,11 +409,14 @@ __device__ void flush_tile(const FitArgs& a, double* lw, const double* wtile, bo
 // Filter (+ smoother).  SORTED selects the schedule at compile time; OCC is
 // the occupancy target in waves per SIMD, which caps the registers per lane;
 // FUSED runs the smoother for a track right after its forward pass, while
-// its workspace column is still cache-hot (otherwise k_bwd does it).
+// its workspace column is still cache-hot (otherwise k_bwd does it); STOREF
+// (always with a split smoother) stores the transport Jacobians, otherwise the
+// fused smoother recomputes them.
 // Dynamic LDS: the surface table, then per wave the carried covariances.
-template <class P, int FK, int OCC, bool SORTED, bool FUSED>
+template <class P, int FK, int OCC, bool SORTED, bool FUSED, bool STOREF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
 k_fwd(FitArgs a) {
+    static_assert(FUSED || STOREF, "the split smoother reads stored Jacobians");
     extern __shared__ double sm[];
     stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, sm);
     const int lane = threadIdx.x & (TILE - 1);
@@ -393,14 +430,14 @@ k_fwd(FitArgs a) {
         int o = 0, n = 0;
         if (i < a.n_tracks) {
             const int t = SORTED ? a.order[i] : (int)i;
-            fwd_one<P, FK>(a, sm, cl, i, t);
+            fwd_one<P, FK, STOREF>(a, sm, cl, i, t);
             if (FUSED) {
-                done = bwd_one(a, i, t);
+                done = bwd_one<P, FK, STOREF>(a, sm, i, t);
                 o = a.off[t];
                 n = a.off[t + 1] - o;
             }
         }
-        if (FUSED) flush_tile(a, cl - lane, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
+        if (FUSED) flush_tile<nc_of<STOREF>()>(a, cl - lane, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
     }
 }
 
@@ -421,11 +458,11 @@ k_bwd(FitArgs a) {
         int o = 0, n = 0;
         if (i < a.n_tracks) {
             const int t = SORTED ? a.order[i] : (int)i;
-            done = bwd_one(a, i, t);
+            done = bwd_one<double, FIELD_UNIFORM, true>(a, nullptr, i, t);
             o = a.off[t];
             n = a.off[t + 1] - o;
         }
-        flush_tile(a, lw, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
+        flush_tile<NC>(a, lw, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
     }
 }
 
@@ -466,48 +503,58 @@ int validate(const kf_config* cfg, const kf_surfaces* surf, const kf_field* fiel
     return KF_OK;
 }
 
-template <class P, int FK, int OCC>
-hipError_t launch_fit_occ(const FitArgs& a, int sched, int block, int waves_per_cu, bool split,
-                          hipStream_t stream) {
-    const size_t shm = ((size_t)a.n_surf * SURF_STRIDE + (size_t)(block / TILE) * WAVE_LDS_DOUBLES) * sizeof(double);
-    const size_t shm_b = (size_t)(block / TILE) * WAVE_LDS_DOUBLES * sizeof(double);
+template <class P, int FK, int OCC, bool STOREF>
+hipError_t launch_fit_fused(const FitArgs& a, int sched, int block, int waves_per_cu, size_t shm,
+                            hipStream_t stream) {
     const int need = (a.n_tiles * TILE + block - 1) / block;
     hipError_t e = hipSuccess;
     if (sched == KF_SCHED_SORTED) {
         int grid = num_cu() * waves_per_cu * TILE / block;
         grid = grid > need ? need : (grid < 1 ? 1 : grid);
-        if (split) {
-            int gridb = num_cu() * 8 * TILE / block;
-            gridb = gridb > need ? need : (gridb < 1 ? 1 : gridb);
-            if ((e = allow_lds(k_fwd<P, FK, OCC, true, false>, shm)) != hipSuccess) return e;
-            if ((e = allow_lds(k_bwd<true>, shm_b)) != hipSuccess) return e;
-            hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, false>), dim3(grid), dim3(block), shm, stream, a);
-            hipLaunchKernelGGL((k_bwd<true>), dim3(gridb), dim3(block), shm_b, stream, a);
-        } else {
-            if ((e = allow_lds(k_fwd<P, FK, OCC, true, true>, shm)) != hipSuccess) return e;
-            hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, true>), dim3(grid), dim3(block), shm, stream, a);
-        }
+        if ((e = allow_lds(k_fwd<P, FK, OCC, true, true, STOREF>, shm)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, true, STOREF>), dim3(grid), dim3(block), shm, stream, a);
     } else {
-        if (split) {
-            if ((e = allow_lds(k_fwd<P, FK, OCC, false, false>, shm)) != hipSuccess) return e;
-            if ((e = allow_lds(k_bwd<false>, shm_b)) != hipSuccess) return e;
-            hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, false>), dim3(need), dim3(block), shm, stream, a);
-            hipLaunchKernelGGL((k_bwd<false>), dim3(need), dim3(block), shm_b, stream, a);
-        } else {
-            if ((e = allow_lds(k_fwd<P, FK, OCC, false, true>, shm)) != hipSuccess) return e;
-            hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, true>), dim3(need), dim3(block), shm, stream, a);
-        }
+        if ((e = allow_lds(k_fwd<P, FK, OCC, false, true, STOREF>, shm)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, true, STOREF>), dim3(need), dim3(block), shm, stream, a);
+    }
+    return hipGetLastError();
+}
+
+template <class P, int FK, int OCC>
+hipError_t launch_fit_occ(const FitArgs& a, int sched, int block, int waves_per_cu, bool split, bool storef,
+                          hipStream_t stream) {
+    const size_t shm = ((size_t)a.n_surf * SURF_STRIDE + (size_t)(block / TILE) * WAVE_LDS_DOUBLES) * sizeof(double);
+    const size_t shm_b = (size_t)(block / TILE) * WAVE_LDS_DOUBLES * sizeof(double);
+    const int need = (a.n_tiles * TILE + block - 1) / block;
+    hipError_t e = hipSuccess;
+    if (!split)
+        return storef ? launch_fit_fused<P, FK, OCC, true>(a, sched, block, waves_per_cu, shm, stream)
+                      : launch_fit_fused<P, FK, OCC, false>(a, sched, block, waves_per_cu, shm, stream);
+    if (sched == KF_SCHED_SORTED) {
+        int grid = num_cu() * waves_per_cu * TILE / block;
+        grid = grid > need ? need : (grid < 1 ? 1 : grid);
+        int gridb = num_cu() * 8 * TILE / block;
+        gridb = gridb > need ? need : (gridb < 1 ? 1 : gridb);
+        if ((e = allow_lds(k_fwd<P, FK, OCC, true, false, true>, shm)) != hipSuccess) return e;
+        if ((e = allow_lds(k_bwd<true>, shm_b)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, false, true>), dim3(grid), dim3(block), shm, stream, a);
+        hipLaunchKernelGGL((k_bwd<true>), dim3(gridb), dim3(block), shm_b, stream, a);
+    } else {
+        if ((e = allow_lds(k_fwd<P, FK, OCC, false, false, true>, shm)) != hipSuccess) return e;
+        if ((e = allow_lds(k_bwd<false>, shm_b)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, false, true>), dim3(need), dim3(block), shm, stream, a);
+        hipLaunchKernelGGL((k_bwd<false>), dim3(need), dim3(block), shm_b, stream, a);
     }
     return hipGetLastError();
 }
 
 template <class P, int FK>
-hipError_t launch_fit(const FitArgs& a, int sched, int block, int waves_per_cu, int occ, bool split,
+hipError_t launch_fit(const FitArgs& a, int sched, int block, int waves_per_cu, int occ, bool split, bool storef,
                       hipStream_t stream) {
     switch (occ) {
-        case 1: return launch_fit_occ<P, FK, 1>(a, sched, block, waves_per_cu, split, stream);
-        case 3: return launch_fit_occ<P, FK, 3>(a, sched, block, waves_per_cu, split, stream);
-        default: return launch_fit_occ<P, FK, 2>(a, sched, block, waves_per_cu, split, stream);
+        case 1: return launch_fit_occ<P, FK, 1>(a, sched, block, waves_per_cu, split, storef, stream);
+        case 3: return launch_fit_occ<P, FK, 3>(a, sched, block, waves_per_cu, split, storef, stream);
+        default: return launch_fit_occ<P, FK, 2>(a, sched, block, waves_per_cu, split, storef, stream);
     }
 }
 
@@ -524,7 +571,9 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     a.seed_sid = seeds->surface_id;
     a.max_hits = meas->max_hits;
     a.n_hits = meas->n_hits;
-    a.tile_doubles = L.tile_doubles;
+    // the workspace is sized for stored Jacobians; without them a tile packs tighter
+    a.tile_doubles = cfg->jacobians == KF_JAC_RECOMPUTE ? (int64_t)meas->max_hits * NC_RECOMPUTE * TILE
+                                                         : L.tile_doubles;
     a.off = meas->hit_offsets;
     a.sid = meas->surface_id;
     a.loc = meas->loc;
@@ -566,12 +615,14 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     const bool mixed = cfg->precision == KF_PREC_MIXED;
     const int occ = cfg->occupancy;
     const bool split = cfg->split_smoother != 0;
+    const bool storef = cfg->jacobians != KF_JAC_RECOMPUTE;
+    if (!storef && split) return KF_E_VALUE;
     if (field->kind == KF_FIELD_UNIFORM)
-        e = mixed ? launch_fit<float, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, stream)
-                  : launch_fit<double, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, stream);
+        e = mixed ? launch_fit<float, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, storef, stream)
+                  : launch_fit<double, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, storef, stream);
     else
-        e = mixed ? launch_fit<float, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, stream)
-                  : launch_fit<double, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, stream);
+        e = mixed ? launch_fit<float, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, stream)
+                  : launch_fit<double, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, stream);
     if (e == hipErrorInvalidValue) return KF_E_VALUE;     // workgroup needs more LDS than the device has
     return e == hipSuccess ? KF_OK : KF_E_HIP;
 }
@@ -613,7 +664,11 @@ kf_config resolve(const kf_config* cfg, const kf_field* field, const kf_measurem
         auto it = g_tune.find(tune_key(cfg, field, meas));
         if (it != g_tune.end()) d = it->second;
     }
-    if (r.schedule == KF_SCHED_AUTO) { r.schedule = d.schedule; r.split_smoother = d.split_smoother; }
+    if (r.schedule == KF_SCHED_AUTO) {
+        r.schedule = d.schedule;
+        r.split_smoother = d.split_smoother;
+        r.jacobians = d.jacobians;
+    }
     if (r.block == 0) r.block = d.block;
     if (r.occupancy == 0) r.occupancy = d.occupancy;
     if (r.waves_per_cu == 0) r.waves_per_cu = d.waves_per_cu;
@@ -752,7 +807,7 @@ int kf_autotune(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     static const int scheds[] = {KF_SCHED_DIRECT, KF_SCHED_SORTED};
     static const int blocks[] = {64, 256};
     static const int occs[] = {1, 2, 3};
-    static const int splits[] = {0, 1};
+    static const int splits[] = {0, 1, 2};     // 2: fused smoother recomputing the Jacobians
     static const int wpcs[] = {4, 8};
     float best_t = 1e30f;
     kf_config win = *best;
@@ -766,7 +821,8 @@ int kf_autotune(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
                         c.schedule = sc;
                         c.block = bl;
                         c.occupancy = oc;
-                        c.split_smoother = sp;
+                        c.split_smoother = sp == 1;
+                        c.jacobians = sp == 2 ? KF_JAC_RECOMPUTE : KF_JAC_STORE;
                         c.waves_per_cu = wp;
                         rc = enqueue_fit(&c, surf, field, meas, seeds, out, workspace, stream);   // warm-up
                         if (rc == KF_E_VALUE) { rc = KF_OK; continue; }   // does not fit this device

@@ -537,8 +537,13 @@ VjpLayout vjp_layout(int64_t n_tracks, int64_t n_hits, int max_hits, int n_surf)
     const int64_t tiles = n_tracks > 0 ? (n_tracks + TILE - 1) / TILE : 1;
     L.tile_doubles = (int64_t)max_hits * NCV * TILE;
     L.n_items = n_hits + n_tracks;
-    int64_t nc = (L.n_items + 511) / 512;
-    nc = nc < 1 ? 1 : (nc > 2048 ? 2048 : nc);
+    // Chunks of ~128 items: each wave of k_align_partial adds its chunk
+    // serially, so short chunks keep that pass short; the partial sums are
+    // capped at 32 MiB for wide detectors.
+    const int64_t nc_cap = ((int64_t)32 << 20) / ((int64_t)n_surf * 6 * sizeof(double));
+    int64_t nc = (L.n_items + 127) / 128;
+    nc = nc > nc_cap ? nc_cap : nc;
+    nc = nc < 1 ? 1 : nc;
     L.n_chunks = (int)nc;
     L.chunk = (L.n_items + nc - 1) / nc;
     if (L.chunk < 1) L.chunk = 1;

@@ -88,6 +88,13 @@ def test_argument_validation(kf):
     cfg.split_smoother = 2
     assert _call(kf, *a) == kf.KF_E_VALUE
     cfg.split_smoother = 0
+    cfg.jacobians = 2
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.jacobians = kf.KF_JAC_RECOMPUTE
+    cfg.split_smoother = 1                     # the split smoother needs stored Jacobians
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.split_smoother = 0
+    cfg.jacobians = kf.KF_JAC_STORE
     fld.b0[2] = float("nan")
     assert _call(kf, *a) == kf.KF_E_VALUE
     fld.b0[2] = 2.0

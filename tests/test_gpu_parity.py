@@ -69,6 +69,18 @@ def test_configs_fp64_small(kf, cfg, n):
         compare(out, _ref(ev), tol=TOL[cfg], label=f"C{cfg} sched {sched}")
 
 
+@pytest.mark.parametrize("cfg,n", [(1, 100), (2, 3000), (3, 3000), (5, 2000)])
+def test_recomputed_jacobians_fp64(kf, cfg, n):
+    """KF_JAC_RECOMPUTE: the smoother propagates each filtered state again
+    instead of reading a stored Jacobian; same bar as the stored variant."""
+    _announce(f"C{cfg} fp64 recomputed Jacobians n={n}")
+    ev = synth.make_config(cfg, n)
+    ref = _ref(ev)
+    for sched, block, occ in ((1, 256, 1), (2, 64, 1), (2, 128, 2)):
+        out = _fit(kf, ev, schedule=sched, block=block, occupancy=occ, jacobians=kf.KF_JAC_RECOMPUTE)
+        compare(out, ref, tol=TOL[cfg], label=f"C{cfg} recompute sched {sched} occ {occ}")
+
+
 def test_field_free_and_misaligned_geometry(kf):
     _announce("B=0 and misaligned planes, fp64")
     ev = synth.telescope_event(1000, 31, bz=0.0)
@@ -112,11 +124,12 @@ def test_full_size_solenoid_sampled_fp64(kf):
     compare(_sampled(out, ev, idx), _ref(ev.subset(idx)), tol=TOL[5], label="C5 sampled")
 
 
-@pytest.mark.parametrize("cfg,n", [(1, 100), (2, 3000), (3, 3000), (5, 2000)])
-def test_mixed_precision_within_1e3_sigma(kf, cfg, n):
-    _announce(f"C{cfg} mixed n={n}")
+@pytest.mark.parametrize("cfg,n,jac", [(1, 100, 0), (2, 3000, 0), (3, 3000, 0), (5, 2000, 0), (2, 3000, 1),
+                                       (5, 2000, 1)])
+def test_mixed_precision_within_1e3_sigma(kf, cfg, n, jac):
+    _announce(f"C{cfg} mixed n={n} jacobians={'recompute' if jac else 'store'}")
     ev = synth.make_config(cfg, n)
-    out = _fit(kf, ev, precision=kf.KF_PREC_MIXED)
+    out = _fit(kf, ev, precision=kf.KF_PREC_MIXED, jacobians=jac)
     ref = _ref(ev)
     assert np.array_equal(out.status.cpu().numpy(), ref.status)
     _, sp = par_err(out.par, ref.par, ref.cov)
@@ -156,10 +169,10 @@ def test_edge_cases(kf):
         cnt[t] = k
     ev.loc, ev.cov, ev.surface_id, ev.truth_hit = ev.loc[:, keep], ev.cov[:, keep], ev.surface_id[keep], ev.truth_hit[:, keep]
     ev.hit_offsets = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
-    for sched in (1, 2):
-        out = _fit(kf, ev, schedule=sched)
+    for sched, jac in ((1, 0), (2, 0), (2, 1)):
+        out = _fit(kf, ev, schedule=sched, jacobians=jac)
         ref = _ref(ev)
-        compare(out, ref, label=f"edge sched {sched}")
+        compare(out, ref, label=f"edge sched {sched} jacobians {jac}")
         st = out.status.cpu().numpy()
         assert st[3] == kf.KF_ST_BAD_INPUT and st[5] == kf.KF_ST_BAD_INPUT and st[7] == kf.KF_ST_BAD_INPUT
         assert st[9] == kf.KF_ST_BAD_INPUT and st[11] == kf.KF_ST_NO_INTERSECT
