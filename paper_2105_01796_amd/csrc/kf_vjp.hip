@@ -94,7 +94,7 @@ __device__ inline void st(double* w, int off, const double (&v)[N]) {
 // forward sweep: filter recompute + reverse RTS mean recursion
 // ---------------------------------------------------------------------------
 template <int FK>
-__device__ int vjp_fwd(const VjpArgs& a, const double* __restrict__ sm, double* wl, int t, int o, int n) {
+__device__ __attribute__((always_inline)) int vjp_fwd(const VjpArgs& a, const double* __restrict__ sm, double* wl, int t, int o, int n) {
     const int64_t H = a.n_hits, N = a.n_tracks;
     Field<double, FK> fl;
     fl.init(a.field);
@@ -224,7 +224,7 @@ __device__ inline void noise_vjp(const double* sa, const double x[6], double mas
 // reversed by hand (kf_gap_reverse.hpp), the noise by its closed-form
 // derivative.
 template <int FK>
-__device__ void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const double* __restrict__ sb,
+__device__ __attribute__((always_inline)) void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const double* __restrict__ sb,
                         const double* xsrc, int64_t xs, const double* w, double xb[6], double ga[6],
                         double gb[6]) {
     double x[6], xpb[6], Fb[25];
@@ -252,7 +252,7 @@ __device__ void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const d
 // backward sweep
 // ---------------------------------------------------------------------------
 template <int FK>
-__device__ void vjp_bwd(const VjpArgs& a, const double* __restrict__ sm, double* wl, int t, int o, int n) {
+__device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const double* __restrict__ sm, double* wl, int t, int o, int n) {
     const int64_t H = a.n_hits, N = a.n_tracks;
     const double chi2b = a.g_chi2 ? gbl(a.g_chi2)[t] : 0.0;
     double xs[6], xsb[6], xfb[6], Cfb[21], aab[6];
@@ -394,8 +394,12 @@ __device__ void vjp_bwd(const VjpArgs& a, const double* __restrict__ sm, double*
     store_rows(a.contrib + H + t, a.n_items, aab);
 }
 
+// One track's adjoint, a called function that holds the whole per-track
+// body (the sweeps above are inlined into it).  At two waves per SIMD (half
+// the registers) its spills made the C2 adjoint 1.8x slower (measured), so the
+// kernels are built for one wave per SIMD only.
 template <int FK>
-__device__ void vjp_one(const VjpArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
+__device__ __attribute__((noinline)) void vjp_one(const VjpArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
     const int64_t H = a.n_hits, N = a.n_tracks;
     int o, n;
     int status = check_track(a.off, a.sid, a.loc, a.cov, a.seed, a.seed_cov, H, N, a.n_surf, a.max_hits, t, o, n);
