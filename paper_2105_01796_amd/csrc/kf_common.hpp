@@ -21,16 +21,6 @@ constexpr int TILE = 64;    // tracks per tile = lanes per wave
 
 __device__ inline bool finite(double v) { return isfinite(v); }
 
-// Device-memory pointers in the global address space.  Kernel arguments and
-// pointers passed through structs are generic (flat) to the compiler; a flat
-// access also counts against the LDS/scalar wait counter, so every LDS wait
-// behind it would wait for the memory access as well.  Casting to address
-// space 1 makes the compiler emit global_load / global_store.
-template <class T>
-__device__ inline __attribute__((address_space(1))) T* gbl(T* p) {
-    return (__attribute__((address_space(1))) T*)p;
-}
-
 // Component-major rows: v[i] lives at p + i * stride.  The running pointer
 // is kept opaque so the compiler adds the stride per row at the point of use
 // instead of computing all N per-lane addresses once and keeping them live
@@ -143,9 +133,9 @@ __device__ inline int check_track(const int32_t* off, const int32_t* sid, const 
 // plane turned about its own u, v, n axes.
 __device__ inline void apply_alignment(const double al[6], double s[SURF_STRIDE]) {
     double sa, ca, sb, cb, sg, cg;
-    sincos(al[3], &sa, &ca);
-    sincos(al[4], &sb, &cb);
-    sincos(al[5], &sg, &cg);
+    angle_sincos(al[3], &sa, &ca);
+    angle_sincos(al[4], &sb, &cb);
+    angle_sincos(al[5], &sg, &cg);
     const double Rx[3][3] = {{1.0, 0.0, 0.0}, {0.0, ca, -sa}, {0.0, sa, ca}};
     const double Ry[3][3] = {{cb, 0.0, sb}, {0.0, 1.0, 0.0}, {-sb, 0.0, cb}};
     const double Rz[3][3] = {{cg, -sg, 0.0}, {sg, cg, 0.0}, {0.0, 0.0, 1.0}};

@@ -56,6 +56,63 @@ template <class P> __device__ inline P pabs(P x) { return x < P(0) ? -x : x; }
 // neighbouring phases for ILP would add their live sets together.
 __device__ inline void phase_boundary() { __builtin_amdgcn_sched_barrier(0); }
 
+// Device-memory pointers in the global address space.  Kernel arguments and
+// pointers passed through structs are generic (flat) to the compiler; a flat
+// access also counts against the LDS/scalar wait counter, so every LDS wait
+// behind it would wait for the memory access as well.  Casting to address
+// space 1 makes the compiler emit global_load / global_store.
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* gbl(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
+// sin and cos of an angle of the track model.  The library routine carries a
+// large-argument reduction (Payne-Hanek) whose registers make the compiler
+// spill in the hot loops although it never runs for these angles.  Here:
+// k = nearest integer to x / (pi/2); r = x - k pi/2 with pi/2 split into three
+// doubles (A + B + C, each the rounded remainder of the previous) and fused
+// multiply-adds, so every product k A, k B, k C enters exactly and r carries
+// an absolute error of ~2e-16 up to |x| ~ 2^50 (beyond that only the
+// reduction's accuracy degrades; inf and NaN give NaN); then the Taylor series
+// of sin and cos on |r| <= pi/4, cut after the r^17 and r^18 terms (remainder
+// below 1e-19), and the quadrant k mod 4.
+__device__ inline void angle_sincos(double x, double* s, double* c) {
+    constexpr double TWO_OVER_PI = 0x1.45f306dc9c883p-1;
+    constexpr double PIO2_A = 0x1.921fb54442d18p+0, PIO2_B = 0x1.1a62633145c07p-54,
+                     PIO2_C = -0x1.f1976b7ed8fbcp-110;
+    const double k = rint(x * TWO_OVER_PI);
+    double r = fma(-k, PIO2_A, x);
+    r = fma(-k, PIO2_B, r);
+    r = fma(-k, PIO2_C, r);
+    const double z = r * r;
+    // sin r = r (1 - z/3! + z^2/5! - ... + z^8/17!)
+    double ps = 1.0 / 355687428096000.0;
+    ps = fma(ps, z, -1.0 / 1307674368000.0);
+    ps = fma(ps, z, 1.0 / 6227020800.0);
+    ps = fma(ps, z, -1.0 / 39916800.0);
+    ps = fma(ps, z, 1.0 / 362880.0);
+    ps = fma(ps, z, -1.0 / 5040.0);
+    ps = fma(ps, z, 1.0 / 120.0);
+    ps = fma(ps, z, -1.0 / 6.0);
+    const double sr = fma(r * z, ps, r);
+    // cos r = 1 - z/2! + z^2/4! - ... - z^9/18!
+    double pc = -1.0 / 6402373705728000.0;
+    pc = fma(pc, z, 1.0 / 20922789888000.0);
+    pc = fma(pc, z, -1.0 / 87178291200.0);
+    pc = fma(pc, z, 1.0 / 479001600.0);
+    pc = fma(pc, z, -1.0 / 3628800.0);
+    pc = fma(pc, z, 1.0 / 40320.0);
+    pc = fma(pc, z, -1.0 / 720.0);
+    pc = fma(pc, z, 1.0 / 24.0);
+    pc = fma(pc, z, -0.5);
+    const double cr = fma(pc, z, 1.0);
+    const int n = (int)(k - 4.0 * floor(k * 0.25));      // k mod 4, exact for |k| < 2^53
+    const double sa = (n & 1) ? cr : sr;
+    const double ca = (n & 1) ? sr : cr;
+    *s = (n & 2) ? -sa : sa;
+    *c = ((n + 1) & 2) ? -ca : ca;
+}
+
 template <class P>
 __device__ inline void cross(const P a[3], const P b[3], P o[3]) {
     o[0] = a[1] * b[2] - a[2] * b[1];
@@ -230,8 +287,8 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
     using V = P;    // step-control bookkeeping
     // bound -> free on surface a
     R sp, cp, st, ct;
-    sincos(x[2], &sp, &cp);
-    sincos(x[3], &st, &ct);
+    angle_sincos(x[2], &sp, &cp);
+    angle_sincos(x[3], &st, &ct);
     R r0[3], T0[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) r0[i] = sa[i] + x[0] * sa[3 + 3 * i + 0] + x[1] * sa[3 + 3 * i + 1];
@@ -393,8 +450,8 @@ __device__ inline void highland(const double* __restrict__ s, const double x[6],
     const double x0 = s[12];
     if (!(x0 > 0.0)) { *q22 = 0.0; *q33 = 0.0; return; }
     double sp, cp, st, ct;
-    sincos(x[2], &sp, &cp);
-    sincos(x[3], &st, &ct);
+    angle_sincos(x[2], &sp, &cp);
+    angle_sincos(x[3], &st, &ct);
     const double nT = s[3 + 2] * cp * st + s[3 + 5] * sp * st + s[3 + 8] * ct;
     const double path = x0 / fabs(nT);
     const double p = 1.0 / fabs(x[4]);

@@ -45,8 +45,8 @@ template <int FK>
 __device__ inline void gap_start(const Cfg& cfg, const double* sa, const double* sb, const double x[6],
                                  GapRun<FK>& g) {
     double sp, cp, st, ct;
-    sincos(x[2], &sp, &cp);
-    sincos(x[3], &st, &ct);
+    angle_sincos(x[2], &sp, &cp);
+    angle_sincos(x[3], &st, &ct);
 #pragma unroll
     for (int i = 0; i < 3; ++i) g.r0[i] = sa[i] + x[0] * sa[3 + 3 * i + 0] + x[1] * sa[3 + 3 * i + 1];
     g.T0[0] = cp * st; g.T0[1] = sp * st; g.T0[2] = ct;
@@ -428,10 +428,11 @@ __device__ inline void step_reverse(const Field<double, FK>& fl, const double* s
 // Reverse of the gap's end: final second-order move onto plane b, free ->
 // bound on b, and the transport Jacobian (path correction, J_fb) built from
 // the tangent columns.  g holds the landed state (before the final move); the
-// adjoints of xp and F are read through xpb[6] and Fb[25].  Sets gb.
+// adjoints of xp and F are read through xpb[6] and Fb (entry q of F at
+// Fb[q * fs], device memory, read one column at a time).  Sets gb.
 template <int FK>
 __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa, const double* sb,
-                                   const GapRun<FK>& g, double t0, const double xpb[6], const double Fb[25],
+                                   const GapRun<FK>& g, double t0, const double xpb[6], const double* Fb, int64_t fs,
                                    GapBar& gb) {
     const double lam = g.lam, lk = lam * kKappa;
     // landed state and the final move
@@ -515,8 +516,9 @@ __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa
             mrp[i] = mr[i] - T[i] * sc;
             mtp[i] = mt[i] - lk * TxB[i] * sc;
         }
-        const double F0b = Fb[0 * 5 + j], F1b = Fb[1 * 5 + j], F2b = Fb[2 * 5 + j], F3b = Fb[3 * 5 + j],
-                     F4b = Fb[4 * 5 + j];
+        const auto Fg = gbl(Fb);
+        const double F0b = Fg[(0 * 5 + j) * fs], F1b = Fg[(1 * 5 + j) * fs], F2b = Fg[(2 * 5 + j) * fs],
+                     F3b = Fg[(3 * 5 + j) * fs], F4b = Fg[(4 * 5 + j) * fs];
         double mrpb[3], mtpb[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -637,8 +639,8 @@ template <int FK>
 __device__ inline void start_reverse(const Cfg& cfg, const double* sa, const double x[6], const GapRun<FK>& g,
                                      GapBar& gb, double xb[6]) {
     double sp, cp, st, ct;
-    sincos(x[2], &sp, &cp);
-    sincos(x[3], &st, &ct);
+    angle_sincos(x[2], &sp, &cp);
+    angle_sincos(x[3], &st, &ct);
     const double ua[3] = {sa[3 + 0], sa[3 + 3], sa[3 + 6]};
     const double va[3] = {sa[3 + 1], sa[3 + 4], sa[3 + 7]};
     // r0 = c_a + x0 u_a + x1 v_a
@@ -679,11 +681,12 @@ __device__ inline void start_reverse(const Cfg& cfg, const double* sa, const dou
 
 // Reverse of one gap: xb += dL/dx, sab/sbb (13 each: c, R row-major; x/X0
 // unused) += dL/d(surface placement), for the adjoints xpb of the predicted
-// state and Fb of the stored transport Jacobian.  Returns false if the replay
-// did not reproduce a successful gap.
+// state and Fb of the stored transport Jacobian (entry q at Fb[q * fs], in
+// device memory).  Returns false if the replay did not reproduce a
+// successful gap.
 template <int FK>
 __device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg, const double* sa, const double* sb,
-                                   const double x[6], const double xpb[6], const double Fb[25], double xb[6],
+                                   const double x[6], const double xpb[6], const double* Fb, int64_t fs, double xb[6],
                                    double sab[13], double sbb[13]) {
     Field<double, FK> fl;
     fl.init(fd);
@@ -695,7 +698,7 @@ __device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg, const dou
     if (gap_run<FK>(fl, cfg, 1 << 30, g, h, capped, S, k) != 0) return false;
     const int n_acc = g.accepted;
     GapBar gb;
-    end_reverse<FK>(fl, sa, sb, g, x[5], xpb, Fb, gb);
+    end_reverse<FK>(fl, sa, sb, g, x[5], xpb, Fb, fs, gb);
     for (int s = n_acc - 1; s >= 0; --s) {
         gap_start<FK>(cfg, sa, sb, x, g);
         if (gap_run<FK>(fl, cfg, s, g, h, capped, S, k) != 1) return false;

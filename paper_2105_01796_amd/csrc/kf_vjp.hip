@@ -186,8 +186,8 @@ __device__ inline void noise_vjp(const double* sa, const double x[6], double mas
     constexpr double K = 0.0136, c = 0.038;
     const double x0 = sa[12];
     double sp, cp, st, ct;
-    sincos(x[2], &sp, &cp);
-    sincos(x[3], &st, &ct);
+    angle_sincos(x[2], &sp, &cp);
+    angle_sincos(x[3], &st, &ct);
     const double n[3] = {sa[3 + 2], sa[3 + 5], sa[3 + 8]};
     const double T[3] = {cp * st, sp * st, ct};
     const double dTdp[3] = {-sp * st, cp * st, 0.0};
@@ -221,22 +221,20 @@ __device__ inline void noise_vjp(const double* sa, const double x[6], double mas
 // adds d(contracted outputs)/d(x) to xb and the derivatives with respect to
 // the alignment of sa and sb to ga and gb.  w holds the adjoints (V_XP, V_F,
 // V_Q); the start state is read from xsrc (stride xs).  The propagation is
-// reversed by hand (kf_gap_reverse.hpp), the noise by its closed-form
-// derivative.
+// reversed by hand (kf_gap_reverse.hpp; it reads the adjoint of F from w
+// column by column), the noise by its closed-form derivative.
 template <int FK>
 __device__ __attribute__((always_inline)) void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const double* __restrict__ sb,
                         const double* xsrc, int64_t xs, const double* w, double xb[6], double ga[6],
                         double gb[6]) {
-    double x[6], xpb[6], Fb[25];
+    double x[6], xpb[6];
     load_rows(xsrc, xs, x);
 #pragma unroll
     for (int i = 0; i < 6; ++i) xpb[i] = gbl(w)[(V_XP + i) * TILE];
-#pragma unroll
-    for (int q = 0; q < 25; ++q) Fb[q] = gbl(w)[(V_F + q) * TILE];
     double sab[13], sbb[13];
 #pragma unroll
     for (int i = 0; i < 13; ++i) { sab[i] = 0.0; sbb[i] = 0.0; }
-    gap_reverse<FK>(a.field, a.cfg, sa, sb, x, xpb, Fb, xb, sab, sbb);
+    gap_reverse<FK>(a.field, a.cfg, sa, sb, x, xpb, w + V_F * TILE, TILE, xb, sab, sbb);
     if (a.cfg.ms && sa[12] > 0.0)
         noise_vjp(sa, x, a.cfg.mass, gbl(w)[(V_Q + 0) * TILE], gbl(w)[(V_Q + 1) * TILE], xb, sab);
     double t[6];
@@ -513,8 +511,8 @@ __global__ void __launch_bounds__(256) k_align_final(const double* partial, int 
         for (int q = 0; q < 6; ++q) g[q] = red[q][0];
         if (align) {
             double sb, cb, sg, cg;
-            sincos(align[4 * S + s], &sb, &cb);
-            sincos(align[5 * S + s], &sg, &cg);
+            angle_sincos(align[4 * S + s], &sb, &cb);
+            angle_sincos(align[5 * S + s], &sg, &cg);
             const double e1 = g[3], e2 = g[4], e3 = g[5];
             g[3] = cg * cb * e1 - sg * cb * e2 + sb * e3;
             g[4] = sg * e1 + cg * e2;
