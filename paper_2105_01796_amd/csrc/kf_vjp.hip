@@ -22,7 +22,8 @@
 //            thin-scatterer noise term by dual numbers.
 //
 // Per-hit alignment contributions go to a [6][H + N] buffer; a deterministic
-// two-level reduction (fixed chunks, then a fixed-order tree per surface)
+// two-level reduction (fixed chunks summed in a fixed order, then a
+// fixed-order tree per surface)
 // sums them per surface and converts the rotation part from the surface's own
 // frame to the (alpha, beta, gamma) of its alignment correction.
 #include <hip/hip_runtime.h>
@@ -482,6 +483,41 @@ __global__ void __launch_bounds__(64) k_align_partial(const double* contrib, int
     for (int i = lane; i < S * 6; i += 64) partial[(int64_t)blockIdx.x * S * 6 + i] = tab[i];
 }
 
+// Surfaces up to which k_align_lanes is used: its LDS table of 64 x S x 6
+// doubles must fit one workgroup's LDS (160 KB on gfx950).
+constexpr int ALIGN_LANES_MAX_S = 53;
+constexpr int ALIGN_LANES_CHUNK = 1024;
+
+// One wave per chunk of items, every lane with its own table [S][6] in LDS
+// (entry e of lane l at tab[e * 64 + l]): lane l adds the chunk's items l,
+// l + 64, l + 128, ... in that order, then the lane owning entry e (e mod 64)
+// sums it over the 64 lane tables starting at lane table e mod 64 (a fixed
+// order per entry; the rotation keeps the lanes on different LDS banks).  The
+// chunk's partial sum is thus a fixed-order sum, and no item waits for the
+// previous one.
+__global__ void __launch_bounds__(64) k_align_lanes(const double* contrib, int64_t n_items, int64_t H,
+                                                    const int32_t* sid, int seed_sid, int S, int64_t chunk,
+                                                    double* partial) {
+    extern __shared__ double tab[];
+    const int lane = threadIdx.x;
+    const int E = S * 6;
+    for (int e = 0; e < E; ++e) tab[e * TILE + lane] = 0.0;
+    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t b1 = b0 + chunk < n_items ? b0 + chunk : n_items;
+    for (int64_t i = b0 + lane; i < b1; i += TILE) {
+        const int s = i < H ? sid[i] : seed_sid;
+        if (s < 0 || s >= S) continue;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) tab[(s * 6 + c) * TILE + lane] += contrib[c * n_items + i];
+    }
+    __syncthreads();
+    for (int e = lane; e < E; e += TILE) {
+        double acc = 0.0;
+        for (int l = 0; l < TILE; ++l) acc += tab[e * TILE + ((l + e) & (TILE - 1))];
+        partial[(int64_t)blockIdx.x * E + e] = acc;
+    }
+}
+
 // One workgroup per surface: each thread sums a fixed stride of chunks, then
 // a fixed tree in LDS.  The rotation part is converted from rotations about
 // the aligned surface's own axes (e1, e2, e3) to (alpha, beta, gamma):
@@ -539,12 +575,17 @@ VjpLayout vjp_layout(int64_t n_tracks, int64_t n_hits, int max_hits, int n_surf)
     const int64_t tiles = n_tracks > 0 ? (n_tracks + TILE - 1) / TILE : 1;
     L.tile_doubles = (int64_t)max_hits * NCV * TILE;
     L.n_items = n_hits + n_tracks;
-    // Chunks of ~128 items: each wave of k_align_partial adds its chunk
-    // serially, so short chunks keep that pass short; the partial sums are
-    // capped at 32 MiB for wide detectors.
-    const int64_t nc_cap = ((int64_t)32 << 20) / ((int64_t)n_surf * 6 * sizeof(double));
-    int64_t nc = (L.n_items + 127) / 128;
-    nc = nc > nc_cap ? nc_cap : nc;
+    // k_align_lanes: chunks of 1024 items.  k_align_partial (wide detectors)
+    // adds its chunk serially, so chunks of ~128 items keep that pass short;
+    // its partial sums are capped at 32 MiB.
+    int64_t nc;
+    if (n_surf <= ALIGN_LANES_MAX_S) {
+        nc = (L.n_items + ALIGN_LANES_CHUNK - 1) / ALIGN_LANES_CHUNK;
+    } else {
+        const int64_t nc_cap = ((int64_t)32 << 20) / ((int64_t)n_surf * 6 * sizeof(double));
+        nc = (L.n_items + 127) / 128;
+        nc = nc > nc_cap ? nc_cap : nc;
+    }
     nc = nc < 1 ? 1 : nc;
     L.n_chunks = (int)nc;
     L.chunk = (L.n_items + nc - 1) / nc;
@@ -662,9 +703,17 @@ int kf_fit_tracks_vjp(const kf_config* cfg, const kf_surfaces* surf, const kf_fi
     if (e != hipSuccess) return KF_E_HIP;
     if (grad->align) {
         double* partial = (double*)(wsb + L.partial_off);
-        hipLaunchKernelGGL(k_align_partial, dim3(L.n_chunks), dim3(64), (size_t)S * 6 * sizeof(double), stream,
-                           (const double*)a.contrib, L.n_items, (int64_t)meas->n_hits, meas->surface_id,
-                           seeds->surface_id, S, L.chunk, partial);
+        if (S <= ALIGN_LANES_MAX_S) {
+            const size_t shm = (size_t)S * 6 * TILE * sizeof(double);
+            if (allow_lds(k_align_lanes, shm) != hipSuccess) return KF_E_HIP;
+            hipLaunchKernelGGL(k_align_lanes, dim3(L.n_chunks), dim3(64), shm, stream, (const double*)a.contrib,
+                               L.n_items, (int64_t)meas->n_hits, meas->surface_id, seeds->surface_id, S, L.chunk,
+                               partial);
+        } else {
+            hipLaunchKernelGGL(k_align_partial, dim3(L.n_chunks), dim3(64), (size_t)S * 6 * sizeof(double), stream,
+                               (const double*)a.contrib, L.n_items, (int64_t)meas->n_hits, meas->surface_id,
+                               seeds->surface_id, S, L.chunk, partial);
+        }
         hipLaunchKernelGGL(k_align_final, dim3(S), dim3(256), 0, stream, (const double*)partial, L.n_chunks, S,
                            surf->align, grad->align);
         if (hipGetLastError() != hipSuccess) return KF_E_HIP;

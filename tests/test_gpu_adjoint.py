@@ -87,6 +87,21 @@ def test_vjp_matches_oracle(kf, cfg, n):
         _close(out.seed.cpu().numpy(), ref_s, f"C{cfg} sched {sched} seed")
 
 
+def test_vjp_wide_detector(kf):
+    """60 planes (61 surfaces): past the per-lane-table limit of the alignment
+    reduction, so the serial per-chunk reduction runs."""
+    _announce("vjp 60-plane telescope, n=40")
+    ev = synth.telescope_event(40, 61, n_planes=60, bz=2.0, x_over_X0=0.005, ms=True)
+    g = _cotangents(ev, 61)
+    ref_m, ref_a, ref_s = oracle.fit_vjp(ev, *g)
+    for sched in (1, 2):
+        out = _gpu_vjp(kf, ev, g, schedule=sched)
+        assert np.all(out.status.cpu().numpy() == 0)
+        _close(out.meas.cpu().numpy(), ref_m, f"wide sched {sched} meas")
+        _close(out.align.cpu().numpy(), ref_a, f"wide sched {sched} align")
+        _close(out.seed.cpu().numpy(), ref_s, f"wide sched {sched} seed")
+
+
 def test_fit_and_vjp_at_nonzero_alignment(kf):
     """Alignment corrections applied in the surface staging: the fit matches
     the oracle's, and the gradient is taken with respect to the corrections
