@@ -200,6 +200,35 @@ int kf_autotune(const kf_config *cfg, const kf_surfaces *surf, const kf_field *f
                 const kf_measurements *meas, const kf_seeds *seeds, const kf_outputs *out,
                 void *workspace, size_t workspace_bytes, void *stream, kf_config *best, float *best_ms);
 
+/* ---- fit from host memory, copies overlapped with the fit ----
+ *
+ * The paper's timeline (Sect. 5.3) counts the host <-> device transfers next
+ * to the kernel (about 17 % of the run time with one stream; overlapping them
+ * with several streams is limited by the transfer time).  kf_fit_tracks_staged
+ * takes the measurements, seeds and outputs in HOST memory (surfaces and field
+ * as for kf_fit_tracks, in device memory) and cuts the batch into n_chunks
+ * ranges of consecutive tracks.  Chunk i runs on streams[i % n_streams]: its
+ * inputs are copied in (rows of the component-major arrays as 2D copies), its
+ * CSR offsets rebased on the device, the fit of kf_fit_tracks is enqueued on
+ * them, and the outputs are copied back; with n_streams >= 2 the copies of one
+ * chunk overlap the fit of another.  Results are those of kf_fit_tracks on the
+ * whole batch, bit for bit (tracks are independent).  Host buffers must stay
+ * valid until the streams are synchronised and should be pinned (page-locked,
+ * e.g. hipHostMalloc), otherwise the copies do not overlap.  The optional
+ * outputs (trials, filtered states) are not supported: they must be NULL.
+ * cfg launch settings resolve per chunk as for kf_fit_tracks.  Streams must
+ * not be NULL; the library synchronises nothing.  Returns KF_E_VALUE for
+ * n_chunks < 1 or n_streams < 1 (n_chunks above n_tracks is clamped).
+ *
+ * Workspace: n_streams slots, each with device buffers for one chunk's
+ * inputs, outputs and fit workspace, sized for the largest chunk. */
+size_t kf_staged_workspace_bytes(const kf_config *cfg, const kf_measurements *host_meas, int32_t n_surfaces,
+                                 int32_t n_chunks, int32_t n_streams);
+int kf_fit_tracks_staged(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
+                         const kf_measurements *host_meas, const kf_seeds *host_seeds,
+                         const kf_outputs *host_out, void *workspace, size_t workspace_bytes,
+                         int32_t n_chunks, void *const *streams, int32_t n_streams);
+
 /* ---- adjoint (vector-Jacobian product) of the fit ----
  *
  * For the scalar L = sum_t g_chi2[t] chi2_t + sum_hits g_par . (smoothed

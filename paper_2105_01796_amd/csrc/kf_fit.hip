@@ -681,6 +681,65 @@ int check_ws(const kf_measurements* meas, void* workspace, size_t workspace_byte
     return KF_OK;
 }
 
+// ---- host-staged chunked fit ----
+// CSR offsets of a chunk copied from the host start at the chunk's first hit;
+// the fit wants them to start at 0.
+__global__ void k_rebase(int32_t* off, int n1, int32_t base) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n1) off[i] -= base;
+}
+
+struct StagedLayout {
+    int n_chunks;
+    int64_t max_nc, max_hc;                 // largest chunk in tracks and in hits
+    size_t off, sid, loc, cov, seed, seed_cov, par, pcov, tgt_par, tgt_cov, chi2, ndf, status, fit;
+    size_t slot_bytes;
+};
+
+inline int64_t chunk_begin(int64_t N, int n_chunks, int i) { return (int64_t)i * N / n_chunks; }
+
+StagedLayout staged_layout(const kf_measurements* meas, int n_chunks) {
+    StagedLayout L;
+    const int64_t N = meas->n_tracks;
+    L.n_chunks = (int)(n_chunks > N ? (N > 0 ? N : 1) : n_chunks);
+    L.max_nc = 0;
+    L.max_hc = 0;
+    for (int i = 0; i < L.n_chunks; ++i) {
+        const int64_t t0 = chunk_begin(N, L.n_chunks, i), t1 = chunk_begin(N, L.n_chunks, i + 1);
+        const int64_t nc = t1 - t0;
+        const int64_t hc = N > 0 ? (int64_t)meas->hit_offsets[t1] - meas->hit_offsets[t0] : 0;
+        L.max_nc = nc > L.max_nc ? nc : L.max_nc;
+        L.max_hc = hc > L.max_hc ? hc : L.max_hc;
+    }
+    const size_t nc = (size_t)(L.max_nc > 0 ? L.max_nc : 1), hc = (size_t)(L.max_hc > 0 ? L.max_hc : 1);
+    size_t p = 0;
+    auto take = [&](size_t bytes) { const size_t at = p; p = align_up(p + bytes, 256); return at; };
+    L.off = take((nc + 1) * 4);
+    L.sid = take(hc * 4);
+    L.loc = take(2 * hc * 8);
+    L.cov = take(3 * hc * 8);
+    L.seed = take(6 * nc * 8);
+    L.seed_cov = take(21 * nc * 8);
+    L.par = take(6 * hc * 8);
+    L.pcov = take(21 * hc * 8);
+    L.tgt_par = take(6 * nc * 8);
+    L.tgt_cov = take(21 * nc * 8);
+    L.chi2 = take(nc * 8);
+    L.ndf = take(nc * 4);
+    L.status = take(nc);
+    L.fit = take(ws_layout((int64_t)nc, meas->max_hits).total);
+    L.slot_bytes = p;
+    return L;
+}
+
+// rows r of a component-major [R][len] array: elements [at, at + n) of every
+// row, between host (row stride len) and a compact device block (row stride n)
+hipError_t copy_rows(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width, size_t rows,
+                     hipMemcpyKind kind, hipStream_t stream) {
+    if (width == 0 || rows == 0) return hipSuccess;
+    return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, rows, kind, stream);
+}
+
 }  // namespace
 
 extern "C" {
@@ -847,6 +906,86 @@ int kf_autotune(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     }
     *best = win;
     if (best_ms) *best_ms = best_t;
+    return KF_OK;
+}
+
+size_t kf_staged_workspace_bytes(const kf_config* cfg, const kf_measurements* meas, int32_t n_surfaces,
+                                 int32_t n_chunks, int32_t n_streams) {
+    (void)cfg;
+    if (!meas || !meas->hit_offsets || meas->n_tracks < 0 || meas->max_hits < 1 || meas->max_hits > KF_MAX_HITS ||
+        n_surfaces < 1 || n_chunks < 1 || n_streams < 1)
+        return 0;
+    return staged_layout(meas, n_chunks).slot_bytes * (size_t)n_streams;
+}
+
+int kf_fit_tracks_staged(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field,
+                         const kf_measurements* meas, const kf_seeds* seeds, const kf_outputs* out, void* workspace,
+                         size_t workspace_bytes, int32_t n_chunks, void* const* streams, int32_t n_streams) {
+    int rc = validate(cfg, surf, field, meas, seeds, out);
+    if (rc != KF_OK) return rc;
+    if (n_chunks < 1 || n_streams < 1) return KF_E_VALUE;
+    if (!streams) return KF_E_NULL;
+    for (int i = 0; i < n_streams; ++i)
+        if (!streams[i]) return KF_E_NULL;
+    if (out->trials || out->filt_par || out->filt_cov) return KF_E_VALUE;
+    const int64_t N = meas->n_tracks, H = meas->n_hits;
+    if (N == 0) return KF_OK;
+    if (!meas->hit_offsets || meas->hit_offsets[0] != 0 || meas->hit_offsets[N] != H) return KF_E_SIZE;
+    const StagedLayout L = staged_layout(meas, n_chunks);
+    if (!workspace || workspace_bytes < L.slot_bytes * (size_t)n_streams) return KF_E_WS;
+    num_cu();
+    for (int i = 0; i < L.n_chunks; ++i) {
+        hipStream_t st = (hipStream_t)streams[i % n_streams];
+        char* slot = (char*)workspace + (size_t)(i % n_streams) * L.slot_bytes;
+        const int64_t t0 = chunk_begin(N, L.n_chunks, i), t1 = chunk_begin(N, L.n_chunks, i + 1);
+        const int64_t nc = t1 - t0;
+        const int32_t h0 = meas->hit_offsets[t0];
+        const int64_t hc = (int64_t)meas->hit_offsets[t1] - h0;
+        if (hc < 0) return KF_E_SIZE;
+        const size_t hb = (size_t)hc * 8, nb = (size_t)nc * 8;
+        const hipMemcpyKind in = hipMemcpyHostToDevice, outk = hipMemcpyDeviceToHost;
+        hipError_t e = hipMemcpyAsync(slot + L.off, meas->hit_offsets + t0, (size_t)(nc + 1) * 4, in, st);
+        if (e == hipSuccess && hc > 0)
+            e = hipMemcpyAsync(slot + L.sid, meas->surface_id + h0, (size_t)hc * 4, in, st);
+        if (e == hipSuccess) e = copy_rows(slot + L.loc, hb, meas->loc + h0, (size_t)H * 8, hb, 2, in, st);
+        if (e == hipSuccess) e = copy_rows(slot + L.cov, hb, meas->cov + h0, (size_t)H * 8, hb, 3, in, st);
+        if (e == hipSuccess) e = copy_rows(slot + L.seed, nb, seeds->par + t0, (size_t)N * 8, nb, 6, in, st);
+        if (e == hipSuccess) e = copy_rows(slot + L.seed_cov, nb, seeds->cov + t0, (size_t)N * 8, nb, 21, in, st);
+        if (e != hipSuccess) return KF_E_HIP;
+        hipLaunchKernelGGL(k_rebase, dim3((unsigned)((nc + 1 + 255) / 256)), dim3(256), 0, st, (int32_t*)(slot + L.off),
+                           (int)(nc + 1), h0);
+        if (hipGetLastError() != hipSuccess) return KF_E_HIP;
+        kf_measurements mc = *meas;
+        mc.n_tracks = (int32_t)nc;
+        mc.n_hits = hc;
+        mc.hit_offsets = (const int32_t*)(slot + L.off);
+        mc.surface_id = (const int32_t*)(slot + L.sid);
+        mc.loc = (const double*)(slot + L.loc);
+        mc.cov = (const double*)(slot + L.cov);
+        kf_seeds sc = *seeds;
+        sc.par = (const double*)(slot + L.seed);
+        sc.cov = (const double*)(slot + L.seed_cov);
+        kf_outputs oc;
+        memset(&oc, 0, sizeof(oc));
+        oc.par = (double*)(slot + L.par);
+        oc.cov = (double*)(slot + L.pcov);
+        oc.tgt_par = (double*)(slot + L.tgt_par);
+        oc.tgt_cov = (double*)(slot + L.tgt_cov);
+        oc.chi2 = (double*)(slot + L.chi2);
+        oc.ndf = (int32_t*)(slot + L.ndf);
+        oc.status = (uint8_t*)(slot + L.status);
+        const kf_config r = resolve(cfg, field, &mc);
+        rc = enqueue_fit(&r, surf, field, &mc, &sc, &oc, slot + L.fit, st);
+        if (rc != KF_OK) return rc;
+        e = copy_rows(out->par + h0, (size_t)H * 8, slot + L.par, hb, hb, 6, outk, st);
+        if (e == hipSuccess) e = copy_rows(out->cov + h0, (size_t)H * 8, slot + L.pcov, hb, hb, 21, outk, st);
+        if (e == hipSuccess) e = copy_rows(out->tgt_par + t0, (size_t)N * 8, slot + L.tgt_par, nb, nb, 6, outk, st);
+        if (e == hipSuccess) e = copy_rows(out->tgt_cov + t0, (size_t)N * 8, slot + L.tgt_cov, nb, nb, 21, outk, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(out->chi2 + t0, slot + L.chi2, nb, outk, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(out->ndf + t0, slot + L.ndf, (size_t)nc * 4, outk, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(out->status + t0, slot + L.status, (size_t)nc, outk, st);
+        if (e != hipSuccess) return KF_E_HIP;
+    }
     return KF_OK;
 }
 

@@ -72,7 +72,8 @@ class kf_gradients(C.Structure):
 
 # every symbol include/kf.h declares
 EXPORTS = ("kf_version", "kf_status_string", "kf_workspace_bytes", "kf_fit_tracks", "kf_plan_create",
-           "kf_plan_launch", "kf_plan_destroy", "kf_autotune", "kf_vjp_workspace_bytes", "kf_fit_tracks_vjp")
+           "kf_plan_launch", "kf_plan_destroy", "kf_autotune", "kf_vjp_workspace_bytes", "kf_fit_tracks_vjp",
+           "kf_staged_workspace_bytes", "kf_fit_tracks_staged")
 
 _lib = None
 
@@ -106,6 +107,10 @@ def lib():
         L.kf_vjp_workspace_bytes.argtypes = [P, P, C.c_int32]
         L.kf_fit_tracks_vjp.restype = C.c_int
         L.kf_fit_tracks_vjp.argtypes = [P, P, P, P, P, P, P, P, C.c_size_t, P]
+        L.kf_staged_workspace_bytes.restype = C.c_size_t
+        L.kf_staged_workspace_bytes.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32]
+        L.kf_fit_tracks_staged.restype = C.c_int
+        L.kf_fit_tracks_staged.argtypes = [P, P, P, P, P, P, P, C.c_size_t, C.c_int32, P, C.c_int32]
         _lib = L
     return _lib
 
@@ -160,6 +165,15 @@ class Batch:
     @property
     def n_hits(self) -> int:
         return self.surface_id.numel()
+
+    @classmethod
+    def staged_from_event(cls, ev, device="cuda", detector=None, align=None) -> "Batch":
+        """Measurements and seeds in pinned host memory, the detector on the
+        device: the input of kf_fit_tracks_staged."""
+        b = cls.from_event(ev, device=device, detector=detector, align=align)
+        for name in ("hit_offsets", "surface_id", "loc", "cov", "seed_par", "seed_cov"):
+            setattr(b, name, getattr(b, name).cpu().pin_memory())
+        return b
 
     @classmethod
     def from_event(cls, ev, device="cuda", detector=None, align=None) -> "Batch":
@@ -328,6 +342,52 @@ class Grad:
     align: torch.Tensor | None        # (6, S) dL/d(alignment correction)
     seed: torch.Tensor | None         # (6, N) dL/d(starting parameters)
     status: torch.Tensor              # (N,) u8 status of the recomputed fit
+
+
+class StagedPlan:
+    """kf_fit_tracks_staged for a batch from Batch.staged_from_event: pinned
+    host inputs and outputs, n_chunks chunks pipelined over n_streams streams
+    (default priority) so that copies overlap the fit."""
+
+    def __init__(self, b: Batch, opt: Options | None = None, n_chunks: int = 8, n_streams: int = 2):
+        opt = opt or Options()
+        dev = b.center.device
+        N, H = b.n_tracks, b.n_hits
+        self.batch, self.opt, self.device = b, opt, dev
+        self.cfg, self.surf, self.field, self.meas, self.seeds = _structs(b, opt)
+        pin = dict(pin_memory=True)
+        out = Fit(torch.empty((6, H), dtype=torch.float64, **pin), torch.empty((21, H), dtype=torch.float64, **pin),
+                  torch.empty((6, N), dtype=torch.float64, **pin), torch.empty((21, N), dtype=torch.float64, **pin),
+                  torch.empty(N, dtype=torch.float64, **pin), torch.empty(N, dtype=torch.int32, **pin),
+                  torch.empty(N, dtype=torch.uint8, **pin))
+        self.out = out
+        self.outs = kf_outputs(_ptr(out.par), _ptr(out.cov), _ptr(out.tgt_par), _ptr(out.tgt_cov), _ptr(out.chi2),
+                               _ptr(out.ndf), _ptr(out.status), None, None, None)
+        self.n_chunks, self.n_streams = int(n_chunks), int(n_streams)
+        nbytes = lib().kf_staged_workspace_bytes(C.byref(self.cfg), C.byref(self.meas), self.surf.n, self.n_chunks,
+                                                 self.n_streams)
+        if nbytes == 0:
+            raise KFError(KF_E_SIZE, "kf_staged_workspace_bytes")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.ws_bytes = nbytes
+        self.streams = [torch.cuda.Stream(device=dev) for _ in range(self.n_streams)]
+        self._handles = (C.c_void_p * self.n_streams)(*[s.cuda_stream for s in self.streams])
+
+    def run(self, stream=None) -> Fit:
+        """Enqueue behind `stream` (default: current); on return `stream`
+        waits for every chunk, so work later on it sees the host outputs."""
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        for s in self.streams:
+            s.wait_stream(stream)
+        rc = lib().kf_fit_tracks_staged(C.byref(self.cfg), C.byref(self.surf), C.byref(self.field),
+                                        C.byref(self.meas), C.byref(self.seeds), C.byref(self.outs), _ptr(self.ws),
+                                        self.ws_bytes, self.n_chunks, self._handles, self.n_streams)
+        if rc != KF_OK:
+            raise KFError(rc, "kf_fit_tracks_staged")
+        for s in self.streams:
+            stream.wait_stream(s)
+        return self.out
 
 
 class VjpPlan:

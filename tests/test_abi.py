@@ -40,7 +40,7 @@ def test_status_strings(kf):
 
 def _args(kf, N=10, H=100, max_hits=10, S=11):
     fake = C.c_void_p(0x1000)     # never dereferenced on the host
-    cfg = kf.kf_config(0, 0, 0.1056583755, 1e-4, 1e-6, 1000, 0, 0, 0, 0, 0)
+    cfg = kf.kf_config(0, 0, 0.1056583755, 1e-4, 1e-6, 1000, 0, 0, 0, 0, 0, 0)
     surf = kf.kf_surfaces(S, fake, fake, fake)
     fld = kf.kf_field(0, (C.c_double * 3)(0, 0, 2), 0.0)
     meas = kf.kf_measurements(N, max_hits, H, fake, fake, fake, fake)
@@ -183,3 +183,38 @@ def test_vjp_argument_validation(kf):
     assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad, nbytes=need - 1) == kf.KF_E_WS
     m = kf.kf_measurements(10, 0, 0, None, None, None, None)
     assert L.kf_vjp_workspace_bytes(C.byref(cfg), C.byref(m), 11) == 0
+
+
+def test_staged_argument_validation(kf):
+    """kf_fit_tracks_staged: host-side checks, and a workspace of one chunk
+    slot per stream sized for the largest chunk."""
+    import numpy as np
+    L = kf.lib()
+    cfg, surf, fld, _, seeds, out = _args(kf)
+    off = np.array([0, 10, 25, 25, 40], dtype=np.int32)          # host CSR, chunk sizes 10+15 | 0+15 hits
+    meas = kf.kf_measurements(4, 15, 40, C.c_void_p(off.ctypes.data), C.c_void_p(0x1000), C.c_void_p(0x1000),
+                              C.c_void_p(0x1000))
+    one = L.kf_staged_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n, 2, 1)
+    assert one > 0 and L.kf_staged_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n, 2, 3) == 3 * one
+    assert L.kf_staged_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n, 0, 1) == 0
+    assert L.kf_staged_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n, 2, 0) == 0
+    # more chunks than tracks are clamped to one track per chunk
+    assert L.kf_staged_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n, 99, 1) > 0
+    streams = (C.c_void_p * 2)(0x3000, 0x3000)
+
+    def call(n_chunks=2, n_streams=2, ws=C.c_void_p(0x2000), nbytes=1 << 40, st=streams):
+        return L.kf_fit_tracks_staged(C.byref(cfg), C.byref(surf), C.byref(fld), C.byref(meas), C.byref(seeds),
+                                      C.byref(out), ws, nbytes, n_chunks, st, n_streams)
+    assert call(n_chunks=0) == kf.KF_E_VALUE
+    assert call(n_streams=0) == kf.KF_E_VALUE
+    assert call(st=None) == kf.KF_E_NULL
+    out.trials = C.c_void_p(0x1000)                              # optional outputs are not staged
+    assert call() == kf.KF_E_VALUE
+    out.trials = None
+    assert call(ws=None) == kf.KF_E_WS
+    assert call(nbytes=2 * one - 1) == kf.KF_E_WS
+    off[4] = 41                                                  # offsets disagree with n_hits
+    assert call() == kf.KF_E_SIZE
+    off[4] = 40
+    meas.n_tracks = 0
+    assert call() == kf.KF_OK

@@ -81,6 +81,23 @@ def test_recomputed_jacobians_fp64(kf, cfg, n):
         compare(out, ref, tol=TOL[cfg], label=f"C{cfg} recompute sched {sched} occ {occ}")
 
 
+@pytest.mark.parametrize("cfg,n,chunks,streams", [(3, 3000, 5, 2), (5, 2000, 3, 3), (2, 1000, 1, 1), (1, 100, 200, 2)])
+def test_staged_fit_equals_device_fit(kf, cfg, n, chunks, streams):
+    """kf_fit_tracks_staged (pinned host buffers, chunks pipelined over
+    streams) gives the device-resident fit bit for bit."""
+    _announce(f"C{cfg} staged n={n} chunks={chunks} streams={streams}")
+    import torch
+    ev = synth.make_config(cfg, n)
+    ref = _fit(kf, ev, extras=False, schedule=2)
+    b = kf.Batch.staged_from_event(ev)
+    p = kf.StagedPlan(b, kf.Options(schedule=2), n_chunks=chunks, n_streams=streams)
+    out = p.run()
+    torch.cuda.synchronize()
+    for name in ("par", "cov", "tgt_par", "tgt_cov", "chi2", "ndf", "status"):
+        got, want = getattr(out, name).numpy(), getattr(ref, name).cpu().numpy()
+        assert np.array_equal(got, want, equal_nan=True), name
+
+
 def test_field_free_and_misaligned_geometry(kf):
     _announce("B=0 and misaligned planes, fp64")
     ev = synth.telescope_event(1000, 31, bz=0.0)
