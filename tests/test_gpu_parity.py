@@ -69,6 +69,19 @@ def test_configs_fp64_small(kf, cfg, n):
         compare(out, _ref(ev), tol=TOL[cfg], label=f"C{cfg} sched {sched}")
 
 
+@pytest.mark.parametrize("cfg,n", [(2, 3000), (3, 3000), (5, 2000)])
+def test_fused_one_wave_per_simd_shapes(kf, cfg, n):
+    """The fused kernel at one wave per SIMD (the benchmarked shape family):
+    direct and sorted schedules, 64- to 256-thread groups."""
+    _announce(f"C{cfg} fp64 fused occ 1 shapes n={n}")
+    ev = synth.make_config(cfg, n)
+    ref = _ref(ev)
+    for sched, block in ((1, 256), (2, 256), (2, 64), (1, 128)):
+        for prec in (kf.KF_PREC_FP64,):
+            out = _fit(kf, ev, schedule=sched, block=block, occupancy=1, split_smoother=0, precision=prec)
+            compare(out, ref, tol=TOL[cfg], label=f"C{cfg} fused occ1 sched {sched} block {block}")
+
+
 @pytest.mark.parametrize("cfg,n", [(1, 100), (2, 3000), (3, 3000), (5, 2000)])
 def test_recomputed_jacobians_fp64(kf, cfg, n):
     """KF_JAC_RECOMPUTE: the smoother propagates each filtered state again
