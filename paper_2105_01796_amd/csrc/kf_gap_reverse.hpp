@@ -429,10 +429,11 @@ __device__ inline void step_reverse(const Field<double, FK>& fl, const double* s
 // bound on b, and the transport Jacobian (path correction, J_fb) built from
 // the tangent columns.  g holds the landed state (before the final move); the
 // adjoints of xp and F are read through xpb[6] and Fb (entry q of F at
-// Fb[q * fs], device memory, read one column at a time).  Sets gb.
-template <int FK>
+// Fb[q * fs], read one column at a time; FbP is the pointer type, so the
+// caller decides the memory it lives in).  Sets gb.
+template <int FK, class FbP>
 __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa, const double* sb,
-                                   const GapRun<FK>& g, double t0, const double xpb[6], const double* Fb, int64_t fs,
+                                   const GapRun<FK>& g, double t0, const double xpb[6], FbP Fb, int64_t fs,
                                    GapBar& gb) {
     const double lam = g.lam, lk = lam * kKappa;
     // landed state and the final move
@@ -516,9 +517,8 @@ __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa
             mrp[i] = mr[i] - T[i] * sc;
             mtp[i] = mt[i] - lk * TxB[i] * sc;
         }
-        const auto Fg = gbl(Fb);
-        const double F0b = Fg[(0 * 5 + j) * fs], F1b = Fg[(1 * 5 + j) * fs], F2b = Fg[(2 * 5 + j) * fs],
-                     F3b = Fg[(3 * 5 + j) * fs], F4b = Fg[(4 * 5 + j) * fs];
+        const double F0b = Fb[(0 * 5 + j) * fs], F1b = Fb[(1 * 5 + j) * fs], F2b = Fb[(2 * 5 + j) * fs],
+                     F3b = Fb[(3 * 5 + j) * fs], F4b = Fb[(4 * 5 + j) * fs];
         double mrpb[3], mtpb[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -681,13 +681,16 @@ __device__ inline void start_reverse(const Cfg& cfg, const double* sa, const dou
 
 // Reverse of one gap: xb += dL/dx, sab/sbb (13 each: c, R row-major; x/X0
 // unused) += dL/d(surface placement), for the adjoints xpb of the predicted
-// state and Fb of the stored transport Jacobian (entry q at Fb[q * fs], in
-// device memory).  Returns false if the replay did not reproduce a
+// state and Fb of the stored transport Jacobian (entry q at Fb[q * fs]; FbP
+// as in end_reverse).  Returns false if the replay did not reproduce a
 // successful gap.
-template <int FK>
-__device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg, const double* sa, const double* sb,
-                                   const double x[6], const double xpb[6], const double* Fb, int64_t fs, double xb[6],
+template <int FK, class FbP>
+__device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg_in, const double* sa, const double* sb,
+                                   const double x[6], const double xpb[6], FbP Fb, int64_t fs, double xb[6],
                                    double sab[13], double sbb[13]) {
+    // a private copy: the replay loops read these settings from registers
+    // instead of reloading them through the reference after every store
+    const Cfg cfg = cfg_in;
     Field<double, FK> fl;
     fl.init(fd);
     GapRun<FK> g;

@@ -39,10 +39,15 @@ namespace {
 // per-hit adjoint workspace [tile][hit][NCV][64 lanes]
 constexpr int NCV = 87;
 constexpr int V_XF = 0, V_CF = 6, V_XP = 27, V_CP = 33, V_F = 54, V_Q = 79, V_U = 81;
-// The backward sweep reuses a hit's slot once its own algebra is done:
-//   V_XF <- xs_{k-1}, V_XP <- adjoint of xp_k, V_CP <- adjoint of C_{k-1},
-//   V_F <- adjoint of F_k, V_Q <- adjoints of the two noise terms,
-//   V_U <- xsb_{k-1}.
+// Per lane, the backward sweep keeps what one hit's step produces for later in
+// the same step in LDS ([SX_N][64 lanes] doubles per wave): in device memory
+// every reload would also wait for all earlier stores (one counter covers
+// loads and stores), LDS reads do not.
+//   SX_XS: xs_{k-1}, SX_XPB: adjoint of xp_k, SX_CB: adjoint of C_{k-1},
+//   SX_FB: adjoint of F_k, SX_QB: adjoints of the two noise terms,
+//   SX_AV: xsb_{k-1}.
+constexpr int SX_XS = 0, SX_XPB = 6, SX_CB = 12, SX_FB = 33, SX_QB = 58, SX_AV = 60, SX_N = 66;
+typedef __attribute__((address_space(3))) double ldouble;
 
 struct VjpArgs {
     int n_tracks;
@@ -89,6 +94,18 @@ __device__ inline void st(double* w, int off, const double (&v)[N]) {
     auto g = gbl(w);
 #pragma unroll
     for (int i = 0; i < N; ++i) g[(off + i) * TILE] = v[i];
+}
+
+template <int N>
+__device__ inline void ldl(const ldouble* x, int off, double (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = x[(off + i) * TILE];
+}
+
+template <int N>
+__device__ inline void stl(ldouble* x, int off, const double (&v)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[(off + i) * TILE] = v[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -220,24 +237,22 @@ __device__ inline void noise_vjp(const double* sa, const double x[6], double mas
 
 // Reverse of one gap (start state x on surface sa -> predicted state on sb):
 // adds d(contracted outputs)/d(x) to xb and the derivatives with respect to
-// the alignment of sa and sb to ga and gb.  w holds the adjoints (V_XP, V_F,
-// V_Q); the start state is read from xsrc (stride xs).  The propagation is
-// reversed by hand (kf_gap_reverse.hpp; it reads the adjoint of F from w
-// column by column), the noise by its closed-form derivative.
+// the alignment of sa and sb to ga and gb.  sx (LDS) holds the adjoints
+// (SX_XPB, SX_FB, SX_QB); the start state is read from xsrc (stride xs).  The
+// propagation is reversed by hand (kf_gap_reverse.hpp; it reads the adjoint
+// of F column by column), the noise by its closed-form derivative.
 template <int FK>
 __device__ __attribute__((always_inline)) void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const double* __restrict__ sb,
-                        const double* xsrc, int64_t xs, const double* w, double xb[6], double ga[6],
+                        const double* xsrc, int64_t xs, const ldouble* sx, double xb[6], double ga[6],
                         double gb[6]) {
     double x[6], xpb[6];
     load_rows(xsrc, xs, x);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) xpb[i] = gbl(w)[(V_XP + i) * TILE];
+    ldl(sx, SX_XPB, xpb);
     double sab[13], sbb[13];
 #pragma unroll
     for (int i = 0; i < 13; ++i) { sab[i] = 0.0; sbb[i] = 0.0; }
-    gap_reverse<FK>(a.field, a.cfg, sa, sb, x, xpb, w + V_F * TILE, TILE, xb, sab, sbb);
-    if (a.cfg.ms && sa[12] > 0.0)
-        noise_vjp(sa, x, a.cfg.mass, gbl(w)[(V_Q + 0) * TILE], gbl(w)[(V_Q + 1) * TILE], xb, sab);
+    gap_reverse<FK>(a.field, a.cfg, sa, sb, x, xpb, sx + SX_FB * TILE, TILE, xb, sab, sbb);
+    if (a.cfg.ms && sa[12] > 0.0) noise_vjp(sa, x, a.cfg.mass, sx[SX_QB * TILE], sx[(SX_QB + 1) * TILE], xb, sab);
     double t[6];
     placement_to_alignment(sa, sab, t);
 #pragma unroll
@@ -251,7 +266,8 @@ __device__ __attribute__((always_inline)) void gap_vjp(const VjpArgs& a, const d
 // backward sweep
 // ---------------------------------------------------------------------------
 template <int FK>
-__device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const double* __restrict__ sm, double* wl, int t, int o, int n) {
+__device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const double* __restrict__ sm, double* wl,
+                                                       ldouble* sx, int t, int o, int n) {
     const int64_t H = a.n_hits, N = a.n_tracks;
     const double chi2b = a.g_chi2 ? gbl(a.g_chi2)[t] : 0.0;
     double xs[6], xsb[6], xfb[6], Cfb[21], aab[6];
@@ -338,7 +354,7 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
 #pragma unroll
             for (int i = 0; i < 6; ++i) xn[i] += xprev[i];
             xn[2] = wrap_phi(xn[2]);
-            st(w, V_XF, xn);                          // xs_{k-1}
+            stl(sx, SX_XS, xn);                       // xs_{k-1}
         }
         phase_boundary();
         // ---- covariance-transport adjoint ----
@@ -351,12 +367,12 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
 #pragma unroll
             for (int i = 0; i < 21; ++i) Cb[i] += CQb[i];
             const double qb[2] = {CQb[sy(2, 2)], CQb[sy(3, 3)]};
-            st(w, V_Q, qb);
+            stl(sx, SX_QB, qb);
         }
-        st(w, V_XP, xpb);
-        st(w, V_F, Fb);
-        st(w, V_CP, Cb);
-        st(w, V_U, av);
+        stl(sx, SX_XPB, xpb);
+        stl(sx, SX_FB, Fb);
+        stl(sx, SX_CB, Cb);
+        stl(sx, SX_AV, av);
         // hit k's surface receives aab (from gap k+1, where it was the start)
         // now and gb (gap k, where it is the target) below
         store_rows(a.contrib + o + k, a.n_items, aab);
@@ -365,8 +381,8 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
         double xb[6], ga[6], gb[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) { xb[i] = 0.0; ga[i] = 0.0; gb[i] = 0.0; }
-        if (k > 0) gap_vjp<FK>(a, sm + prev * SURF_STRIDE, sm + s * SURF_STRIDE, wp + V_XF * TILE, TILE, w, xb, ga, gb);
-        else gap_vjp<FK>(a, sm + prev * SURF_STRIDE, sm + s * SURF_STRIDE, a.seed + t, N, w, xb, ga, gb);
+        if (k > 0) gap_vjp<FK>(a, sm + prev * SURF_STRIDE, sm + s * SURF_STRIDE, wp + V_XF * TILE, TILE, sx, xb, ga, gb);
+        else gap_vjp<FK>(a, sm + prev * SURF_STRIDE, sm + s * SURF_STRIDE, a.seed + t, N, sx, xb, ga, gb);
         {
             double c[6];
             load_rows(a.contrib + o + k, a.n_items, c);
@@ -379,9 +395,9 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
             aab[i] = ga[i];
             xfb[i] = xb[i];
         }
-        ld(w, V_CP, Cfb);
-        ld(w, V_XF, xs);
-        ld(w, V_U, xsb);
+        ldl(sx, SX_CB, Cfb);
+        ldl(sx, SX_XS, xs);
+        ldl(sx, SX_AV, xsb);
         phase_boundary();
     }
     if (a.g_seed) {
@@ -398,14 +414,19 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
 // the registers) its spills made the C2 adjoint 1.8x slower (measured), so the
 // kernels are built for one wave per SIMD only.
 template <int FK>
-__device__ __attribute__((noinline)) void vjp_one(const VjpArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
+__device__ __attribute__((noinline)) void vjp_one(const VjpArgs& ag, const ldouble* sml, ldouble* sx, int64_t slot,
+                                                  int t) {
+    const VjpArgs& a = ag;
+    // the surface table is in LDS; a generic pointer derived from an LDS one
+    // keeps its reads LDS instructions in the inlined body
+    const double* __restrict__ sm = (const double*)sml;
     const int64_t H = a.n_hits, N = a.n_tracks;
     int o, n;
     int status = check_track(a.off, a.sid, a.loc, a.cov, a.seed, a.seed_cov, H, N, a.n_surf, a.max_hits, t, o, n);
     double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
     if (status == ST_OK) status = vjp_fwd<FK>(a, sm, wl, t, o, n);
     if (status == ST_OK) {
-        vjp_bwd<FK>(a, sm, wl, t, o, n);
+        vjp_bwd<FK>(a, sm, wl, sx, t, o, n);
     } else {
         const double nan = __longlong_as_double(0x7ff8000000000000LL);
         for (int k = 0; k < n; ++k) fill_rows<2>(a.g_meas + o + k, H, nan);
@@ -414,17 +435,20 @@ __device__ __attribute__((noinline)) void vjp_one(const VjpArgs& a, const double
     gbl(a.status)[t] = (uint8_t)status;
 }
 
+// Dynamic LDS: the surface table, then per wave the backward sweep's stash
+// [SX_N][64] doubles.
 template <int FK, bool SORTED>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) k_vjp(VjpArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_vjp(VjpArgs a) {
     extern __shared__ double sm[];
     stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, sm);
     const int lane = threadIdx.x & (TILE - 1);
+    ldouble* sx = (ldouble*)(sm + a.n_surf * SURF_STRIDE + (threadIdx.x / TILE) * (SX_N * TILE)) + lane;
     int iter = 0;
     for (;;) {
         const int tile = next_tile<SORTED>(a.tile_counter, iter);
         if (tile >= a.n_tiles) break;
         const int64_t i = (int64_t)tile * TILE + lane;
-        if (i < a.n_tracks) vjp_one<FK>(a, sm, i, SORTED ? a.order[i] : (int)i);
+        if (i < a.n_tracks) vjp_one<FK>(a, (const ldouble*)sm, sx, i, SORTED ? a.order[i] : (int)i);
     }
 }
 
@@ -604,15 +628,24 @@ VjpLayout vjp_layout(int64_t n_tracks, int64_t n_hits, int max_hits, int n_surf)
     return L;
 }
 
+// Four waves per workgroup share one surface table while it and their four
+// stashes fit the LDS (up to ~240 surfaces); wider detectors run one wave
+// per workgroup (fewer resident waves when the table is large).
 template <int FK, bool SORTED>
 hipError_t launch_vjp(const VjpArgs& a, hipStream_t stream) {
-    const size_t shm = (size_t)a.n_surf * SURF_STRIDE * sizeof(double);
-    int grid = a.n_tiles;
+    const size_t stash = (size_t)SX_N * TILE * sizeof(double);
+    const size_t table = (size_t)a.n_surf * SURF_STRIDE * sizeof(double);
+    const int block = table + 4 * stash <= lds_cap() ? 4 * TILE : TILE;
+    const size_t shm = table + (size_t)(block / TILE) * stash;
+    hipError_t e = allow_lds(k_vjp<FK, SORTED>, shm);
+    if (e != hipSuccess) return e;
+    const int need = (int)(((int64_t)a.n_tiles * TILE + block - 1) / block);
+    int grid = need;
     if (SORTED) {
-        const int persistent = num_cu() * 4;          // one wave per SIMD
+        const int persistent = num_cu() * 4 * TILE / block;    // one wave per SIMD
         grid = grid < persistent ? grid : persistent;
     }
-    hipLaunchKernelGGL((k_vjp<FK, SORTED>), dim3(grid), dim3(TILE), shm, stream, a);
+    hipLaunchKernelGGL((k_vjp<FK, SORTED>), dim3(grid), dim3(block), shm, stream, a);
     return hipGetLastError();
 }
 
