@@ -45,8 +45,10 @@ constexpr int V_XF = 0, V_CF = 6, V_XP = 27, V_CP = 33, V_F = 54, V_Q = 79, V_U 
 // loads and stores), LDS reads do not.
 //   SX_XS: xs_{k-1}, SX_XPB: adjoint of xp_k, SX_CB: adjoint of C_{k-1},
 //   SX_FB: adjoint of F_k, SX_QB: adjoints of the two noise terms,
-//   SX_AV: xsb_{k-1}.
-constexpr int SX_XS = 0, SX_XPB = 6, SX_CB = 12, SX_FB = 33, SX_QB = 58, SX_AV = 60, SX_N = 66;
+//   SX_AV: xsb_{k-1}, SX_X0: the start state of gap k, SX_AA: the alignment
+//   contribution of hit k's surface from gap k+1.
+constexpr int SX_XS = 0, SX_XPB = 6, SX_CB = 12, SX_FB = 33, SX_QB = 58, SX_AV = 60, SX_X0 = 66, SX_AA = 72,
+              SX_N = 78;
 typedef __attribute__((address_space(3))) double ldouble;
 
 struct VjpArgs {
@@ -237,16 +239,15 @@ __device__ inline void noise_vjp(const double* sa, const double x[6], double mas
 
 // Reverse of one gap (start state x on surface sa -> predicted state on sb):
 // adds d(contracted outputs)/d(x) to xb and the derivatives with respect to
-// the alignment of sa and sb to ga and gb.  sx (LDS) holds the adjoints
-// (SX_XPB, SX_FB, SX_QB); the start state is read from xsrc (stride xs).  The
-// propagation is reversed by hand (kf_gap_reverse.hpp; it reads the adjoint
-// of F column by column), the noise by its closed-form derivative.
+// the alignment of sa and sb to ga and gb.  sx (LDS) holds the start state
+// (SX_X0) and the adjoints (SX_XPB, SX_FB, SX_QB).  The propagation is
+// reversed by hand (kf_gap_reverse.hpp; it reads the adjoint of F column by
+// column), the noise by its closed-form derivative.
 template <int FK>
 __device__ __attribute__((always_inline)) void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const double* __restrict__ sb,
-                        const double* xsrc, int64_t xs, const ldouble* sx, double xb[6], double ga[6],
-                        double gb[6]) {
+                        const ldouble* sx, double xb[6], double ga[6], double gb[6]) {
     double x[6], xpb[6];
-    load_rows(xsrc, xs, x);
+    ldl(sx, SX_X0, x);
     ldl(sx, SX_XPB, xpb);
     double sab[13], sbb[13];
 #pragma unroll
@@ -350,6 +351,7 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
             gain_vjp_rank1(av, wv, z, y, u, Cb, Fb, Cpb);
             if (k > 0) ld(wp, V_XF, xprev);
             else load_rows(a.seed + t, N, xprev);
+            stl(sx, SX_X0, xprev);                    // start state of gap k
             symv(C, z, xn);
 #pragma unroll
             for (int i = 0; i < 6; ++i) xn[i] += xprev[i];
@@ -374,18 +376,17 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
         stl(sx, SX_CB, Cb);
         stl(sx, SX_AV, av);
         // hit k's surface receives aab (from gap k+1, where it was the start)
-        // now and gb (gap k, where it is the target) below
-        store_rows(a.contrib + o + k, a.n_items, aab);
+        // and gb (gap k, where it is the target)
+        stl(sx, SX_AA, aab);
         phase_boundary();
-        // ---- propagation adjoint (dual-number recompute) ----
+        // ---- propagation adjoint (reverse mode) ----
         double xb[6], ga[6], gb[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) { xb[i] = 0.0; ga[i] = 0.0; gb[i] = 0.0; }
-        if (k > 0) gap_vjp<FK>(a, sm + prev * SURF_STRIDE, sm + s * SURF_STRIDE, wp + V_XF * TILE, TILE, sx, xb, ga, gb);
-        else gap_vjp<FK>(a, sm + prev * SURF_STRIDE, sm + s * SURF_STRIDE, a.seed + t, N, sx, xb, ga, gb);
+        gap_vjp<FK>(a, sm + prev * SURF_STRIDE, sm + s * SURF_STRIDE, sx, xb, ga, gb);
         {
             double c[6];
-            load_rows(a.contrib + o + k, a.n_items, c);
+            ldl(sx, SX_AA, c);
 #pragma unroll
             for (int i = 0; i < 6; ++i) c[i] += gb[i];
             store_rows(a.contrib + o + k, a.n_items, c);
@@ -629,8 +630,8 @@ VjpLayout vjp_layout(int64_t n_tracks, int64_t n_hits, int max_hits, int n_surf)
 }
 
 // Four waves per workgroup share one surface table while it and their four
-// stashes fit the LDS (up to ~240 surfaces); wider detectors run one wave
-// per workgroup (fewer resident waves when the table is large).
+// stashes fit the LDS (up to 39 surfaces on gfx950); wider detectors run one
+// wave per workgroup (fewer resident waves as the table grows).
 template <int FK, bool SORTED>
 hipError_t launch_vjp(const VjpArgs& a, hipStream_t stream) {
     const size_t stash = (size_t)SX_N * TILE * sizeof(double);
