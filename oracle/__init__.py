@@ -50,7 +50,7 @@ def lib():
         P = C.c_void_p
         i, d = C.c_int, C.c_double
         fit_args = [i, P, P, P, P, i, P, P, P, P, i, P, d, P, P, i, i, d, d, d, i]
-        L.kfo_fit.argtypes = fit_args + [P] * 12 + [i]
+        L.kfo_fit.argtypes = fit_args + [P] * 12 + [i, i, d]
         L.kfo_fit.restype = i
         L.kfo_fit_vjp.argtypes = fit_args + [P] * 6 + [i]
         L.kfo_fit_vjp.restype = i
@@ -62,6 +62,8 @@ def lib():
         L.kfo_rkn_step.restype = d
         L.kfo_linear_smoother.argtypes = [i] + [P] * 11
         L.kfo_linear_smoother.restype = i
+        L.kfo_linear_two_filter.argtypes = [i] + [P] * 7 + [d, P, P]
+        L.kfo_linear_two_filter.restype = i
         L.kfo_ms_noise.argtypes = [i, P, P, P, i, P, d, P]
         L.kfo_ms_noise.restype = i
         L.kfo_version.restype = C.c_char_p
@@ -121,8 +123,17 @@ class _Args:
                      float(tol), float(land_tol), int(max_steps)]
 
 
-def fit(ev, n_threads: int = 0, extras: bool = False, **kw) -> FitResult:
-    """Filter + RTS smoother for every track of `ev` (FP64)."""
+SMOOTHERS = {"rts": 0, "two_filter": 1}
+DEFAULT_BWD_SCALE = 1e3
+
+
+def fit(ev, n_threads: int = 0, extras: bool = False, smoother: str = "rts", bwd_scale: float = DEFAULT_BWD_SCALE,
+        **kw) -> FitResult:
+    """Filter + smoother for every track of `ev` (FP64).
+
+    smoother: "rts" (stored Jacobians) or "two_filter" (a backward filter
+    started from the last filtered covariance times `bwd_scale`, combined with
+    the forward filter)."""
     a = _Args(ev, **kw)
     N, H = a.N, a.H
     out = FitResult(np.empty((6, H)), np.empty((21, H)), np.empty((6, N)), np.empty((21, N)),
@@ -133,7 +144,7 @@ def fit(ev, n_threads: int = 0, extras: bool = False, **kw) -> FitResult:
         out.trials = np.empty(H, np.int32)
     lib().kfo_fit(*a.args, _p(out.par), _p(out.cov), _p(out.tgt_par), _p(out.tgt_cov), _p(out.chi2),
                   _p(out.ndf), _p(out.status), _p(out.filt_par), _p(out.filt_cov), _p(out.pred_par),
-                  _p(out.pred_cov), _p(out.trials), int(n_threads))
+                  _p(out.pred_cov), _p(out.trials), int(n_threads), SMOOTHERS[smoother], float(bwd_scale))
     return out
 
 
@@ -202,6 +213,22 @@ def linear_smoother(F, Q, m, V, x0, C0):
     if st:
         raise RuntimeError(f"linear smoother status {st}")
     return xs, Cs, xf, Cf, chi2
+
+
+def linear_two_filter(F, G, Q, m, V, x0, C0, scale):
+    """Linear-Gaussian filter + two-filter smoother with the oracle's routines.
+
+    G: (n,6,6) backward transports (the inverses of F); the backward filter
+    starts from the last filtered state with its covariance times `scale`.
+    Returns xs (n+1,6), Cs (n+1,6,6)."""
+    n = F.shape[0]
+    F, G, Q, m, V, x0, C0 = map(_f64, (F, G, Q, m, V, x0, C0))
+    xs = np.empty((n + 1, 6)); Cs = np.empty((n + 1, 6, 6))
+    st = lib().kfo_linear_two_filter(n, _p(F), _p(G), _p(Q), _p(m), _p(V), _p(x0), _p(C0), float(scale), _p(xs),
+                                     _p(Cs))
+    if st:
+        raise RuntimeError(f"linear two-filter status {st}")
+    return xs, Cs
 
 
 def ms_noise(det, s, x, mass=0.1056583755):

@@ -19,6 +19,10 @@
 //   * after the last surface a Rauch-Tung-Striebel smoother runs backwards
 //     with the Jacobians stored during the forward pass (Sect. 2, smoother
 //     paragraph); the inverse it needs is done in FP64 (Sect. 4.2.4);
+//   * as the alternative smoother of Sect. 2 (Fig. 2), a second Kalman filter
+//     runs from the last hit back to the seed surface, propagating against the
+//     direction of flight, and its predictions are combined with the forward
+//     filtered states;
 //   * the chi2 is built from measurement residuals (Sect. 2).
 // The paper defers the formulas to the works it cites (Kalman filter for
 // track fitting, RTS smoother, Runge-Kutta-Nystrom of Myrheim and Bugge);
@@ -140,6 +144,9 @@ struct Cfg {
     double tol;        // RKN local error tolerance on h^2 |k1-k2-k3+k4|_1 [mm]
     double land_tol;   // landing tolerance on the distance to the plane [mm]
     int max_steps;     // maximum RKN trials per surface-to-surface gap
+    int smoother = 0;          // 0: RTS with the stored Jacobians; 1: forward + backward filter combined
+    double bwd_scale = 1e3;    // two-filter: the backward filter starts from the last filtered
+                               // covariance multiplied by this factor
 };
 
 template <class S>
@@ -541,6 +548,58 @@ int rts_step(const S xf[6], const S (&Cf)[6][6], const S (&F)[6][6], const S xp1
 }
 
 // ---------------------------------------------------------------------------
+// Two-filter smoother (Sect. 2, Fig. 2: the smoother run as a second filter
+// from the last hit back to the first, whose predictions are combined with
+// the forward filter's estimates).  Two independent estimates (xf, Cf) and
+// (xb, Cb) of one state combine with the gain K = Cf (Cf + Cb)^{-1}:
+//   xs = xf + K (xb - xf)                                  (phi difference wrapped)
+//   Cs = (I - K) Cf (I - K)^T + K Cb K^T                   (covariance of that sum)
+// Cholesky of Cf + Cb: K^T = (Cf + Cb)^{-1} Cf.
+// ---------------------------------------------------------------------------
+template <class S>
+int two_filter_combine(const S xf[6], const S (&Cf)[6][6], const S xb[6], const S (&Cb)[6][6],
+                       S xs[6], S (&Cs)[6][6]) {
+    S Sm[6][6], L[6][6], Kt[6][6], K[6][6];
+    for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) Sm[i][j] = Cf[i][j] + Cb[i][j];
+    if (!cholesky6(Sm, L)) return ST_NOT_SPD;
+    chol_solve6(L, Cf, Kt);
+    transpose(Kt, K);
+    S dx[6];
+    for (int i = 0; i < 6; ++i) dx[i] = xb[i] - xf[i];
+    dx[2] = wrap_phi(dx[2]);
+    for (int i = 0; i < 6; ++i) {
+        S acc = xf[i];
+        for (int k = 0; k < 6; ++k) acc = acc + K[i][k] * dx[k];
+        xs[i] = acc;
+    }
+    xs[2] = wrap_phi(xs[2]);
+    S IK[6][6], IKt[6][6], T1[6][6], T2[6][6], T3[6][6], T4[6][6];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) IK[i][j] = ((i == j) ? S(1.0) : S(0.0)) - K[i][j];
+    transpose(IK, IKt);
+    matmul(IK, Cf, T1);
+    matmul(T1, IKt, T2);
+    matmul(K, Cb, T3);
+    matmul(T3, Kt, T4);
+    for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) Cs[i][j] = T2[i][j] + T4[i][j];
+    return ST_OK;
+}
+
+// Backward prediction: a state estimate (x, C) carried against the direction
+// of flight by the transport G, then the thin scatterer of the surface it
+// reaches (the forward model scatters after each measurement, so going back
+// the scattering angle's variance is added after the transport):
+//   C <- G C G^T + Q
+template <class S>
+void backward_predict(const S (&G)[6][6], const S (&Q)[6][6], const S (&C)[6][6], S (&Cq)[6][6]) {
+    S T1[6][6], Gt[6][6], T2[6][6];
+    matmul(G, C, T1);
+    transpose(G, Gt);
+    matmul(T1, Gt, T2);
+    for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) Cq[i][j] = T2[i][j] + Q[i][j];
+}
+
+// ---------------------------------------------------------------------------
 // one track: filter + smoother
 // ---------------------------------------------------------------------------
 template <class S>
@@ -625,9 +684,69 @@ int fit_track(const FieldDef& f, const Cfg& cfg, const Surf<S>* surf, int n_surf
         }
         prev = sid[k];
     }
-    // RTS smoother, k = n-1 .. 0 over hits, then the seed state
+    // the last hit's smoothed state is its filtered state (both smoothers)
     for (int i = 0; i < 6; ++i) out.xs[6 * (n - 1) + i] = out.xf[6 * (n - 1) + i];
     for (int i = 0; i < 36; ++i) out.Cs[36 * (n - 1) + i] = out.Cf[36 * (n - 1) + i];
+    if (cfg.smoother == 1) {
+        // Two-filter smoother.  The backward filter starts at the last hit from
+        // the forward estimate there with its covariance inflated by bwd_scale
+        // (a weak prior, so that the backward estimates rest on the hits behind
+        // them), takes in that hit, and then for k = n-2 .. 0 and finally the
+        // seed surface: propagate back to surface k, add the scatterer of
+        // surface k, combine this prediction (hits k+1 .. n-1) with the forward
+        // filtered state of hit k (hits 0 .. k) into the smoothed state, and
+        // take in hit k.
+        S xb[6], Cb[6][6];
+        {
+            S xl[6], Cl[6][6], ck;
+            for (int i = 0; i < 6; ++i) {
+                xl[i] = out.xf[6 * (n - 1) + i];
+                for (int j = 0; j < 6; ++j) Cl[i][j] = cfg.bwd_scale * out.Cf[36 * (n - 1) + 6 * i + j];
+            }
+            S mk[2] = {m[2 * (n - 1)], m[2 * (n - 1) + 1]};
+            const double* v = V3 + 3 * (n - 1);
+            S V[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
+            int st = kalman_update(xl, Cl, mk, V, xb, Cb, &ck);
+            if (st != ST_OK) return out.status = st;
+        }
+        for (int k = n - 2; k >= -1; --k) {
+            const Surf<S>& sa = surf[sid[k + 1]];
+            const Surf<S>& sb = surf[k >= 0 ? sid[k] : seed_sid];
+            S xf[6], Cf[6][6], xs[6], Cs[6][6];
+            for (int i = 0; i < 6; ++i) {
+                xf[i] = (k >= 0) ? out.xf[6 * k + i] : seed[i];
+                for (int j = 0; j < 6; ++j) Cf[i][j] = (k >= 0) ? out.Cf[36 * k + 6 * i + j] : C0[i][j];
+            }
+            S xq[6], G[6][6], Q[6][6], Cq[6][6];
+            int trials = 0;
+            int st = transport(f, cfg, sa, sb, xb, xq, G, &trials);
+            if (st != ST_OK) return out.status = st;
+            // the scatterer's variance as the forward filter took it: at the
+            // forward filtered state of surface k (the seed on the seed surface)
+            if (cfg.ms) ms_noise(sb, xf, cfg.mass, Q);
+            else for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) Q[i][j] = 0.0;
+            backward_predict(G, Q, Cb, Cq);
+            st = two_filter_combine(xf, Cf, xq, Cq, xs, Cs);
+            if (st != ST_OK) return out.status = st;
+            for (int i = 0; i < 6; ++i) {
+                if (k >= 0) out.xs[6 * k + i] = xs[i]; else out.tgt[i] = xs[i];
+                for (int j = 0; j < 6; ++j) {
+                    if (k >= 0) out.Cs[36 * k + 6 * i + j] = Cs[i][j]; else out.tgt_cov[i][j] = Cs[i][j];
+                }
+            }
+            if (k >= 0) {
+                S mk[2] = {m[2 * k], m[2 * k + 1]};
+                const double* v = V3 + 3 * k;
+                S V[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
+                S ck;
+                st = kalman_update(xq, Cq, mk, V, xb, Cb, &ck);
+                if (st != ST_OK) return out.status = st;
+            }
+        }
+        out.chi2 = chi2;
+        return out.status = ST_OK;
+    }
+    // RTS smoother, k = n-2 .. 0 over hits, then the seed state
     for (int k = n - 2; k >= -1; --k) {
         S xf[6], Cf[6][6], F[6][6], xp1[6], Cp1[6][6], xs1[6], Cs1[6][6], xs[6], Cs[6][6];
         for (int i = 0; i < 6; ++i) {
@@ -741,7 +860,8 @@ extern "C" {
 const char* kfo_version() { return "kf-oracle fp64 1"; }
 
 // Full fit of every track.  Arrays are component-major ([component][item]).
-// Optional outputs may be NULL.  Returns 0.
+// Optional outputs may be NULL.  smoother: 0 RTS, 1 two-filter (bwd_scale:
+// inflation of the backward filter's starting covariance).  Returns 0.
 int kfo_fit(int n_tracks, const int32_t* off, const int32_t* sid, const double* loc, const double* cov,
             int n_surf, const double* center, const double* rot, const double* x0, const double* align,
             int field_kind, const double* b0, double field_a,
@@ -749,9 +869,11 @@ int kfo_fit(int n_tracks, const int32_t* off, const int32_t* sid, const double* 
             int ms, double mass, double tol, double land_tol, int max_steps,
             double* par, double* pcov, double* tgt_par, double* tgt_cov, double* chi2, int32_t* ndf,
             uint8_t* status, double* filt_par, double* filt_cov, double* pred_par, double* pred_cov,
-            int32_t* trials, int n_threads) {
+            int32_t* trials, int n_threads, int smoother, double bwd_scale) {
     Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, align, field_kind, b0, field_a,
                             seed, seed_cov, seed_sid, ms, mass, tol, land_tol, max_steps);
+    in.cfg.smoother = smoother;
+    in.cfg.bwd_scale = bwd_scale;
     std::vector<Surf<double>> surf(n_surf);
     for (int s = 0; s < n_surf; ++s) surf[s] = surf_d(in, s);
     const int64_t H = in.H;
@@ -874,6 +996,59 @@ int kfo_linear_smoother(int n, const double* Fin, const double* Qin, const doubl
     for (int k = 0; k < n; ++k) {
         for (int i = 0; i < 6; ++i) xf_out[6 * k + i] = xf[6 * (k + 1) + i];
         for (int i = 0; i < 36; ++i) Cf_out[36 * k + i] = Cf[36 * (k + 1) + i];
+    }
+    return 0;
+}
+
+// The same linear model smoothed by the two-filter routines of the track fit:
+// forward filter as above; backward filter started from (xf_n, scale Cf_n),
+// backward prediction x_{k|k+1} = G_k x_{k+1}, C = G_k C G_k^T + Q_k (G_k is
+// the inverse of F_k, given), combined with x_{k|k} by two_filter_combine.
+// G: [n][6][6]; outputs xs: [n+1][6], Cs: [n+1][6][6].
+int kfo_linear_two_filter(int n, const double* Fin, const double* Gin, const double* Qin, const double* m,
+                          const double* V3, const double* x0, const double* C0, double scale, double* xs_out,
+                          double* Cs_out) {
+    std::vector<double> xs_r(6 * (n + 1)), Cs_r(36 * (n + 1)), xf(6 * n), Cf(36 * n), chi2(n);
+    int st = kfo_linear_smoother(n, Fin, Qin, m, V3, x0, C0, xs_r.data(), Cs_r.data(), xf.data(), Cf.data(),
+                                 chi2.data());
+    if (st) return st;
+    // state n: the filtered state
+    for (int i = 0; i < 6; ++i) xs_out[6 * n + i] = xf[6 * (n - 1) + i];
+    for (int i = 0; i < 36; ++i) Cs_out[36 * n + i] = Cf[36 * (n - 1) + i];
+    double xb[6], Cb[6][6];
+    {
+        double xl[6], Cl[6][6], c2;
+        for (int i = 0; i < 6; ++i) {
+            xl[i] = xf[6 * (n - 1) + i];
+            for (int j = 0; j < 6; ++j) Cl[i][j] = scale * Cf[36 * (n - 1) + 6 * i + j];
+        }
+        double mk[2] = {m[2 * (n - 1)], m[2 * (n - 1) + 1]};
+        const double* v = V3 + 3 * (n - 1);
+        double V[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
+        st = kalman_update(xl, Cl, mk, V, xb, Cb, &c2);
+        if (st) return st;
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double G[6][6], Q[6][6], Cq[6][6], xq[6], a[6], A[6][6], o[6], O[6][6];
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) { G[i][j] = Gin[36 * k + 6 * i + j]; Q[i][j] = Qin[36 * k + 6 * i + j]; }
+        for (int i = 0; i < 6; ++i) { double acc = 0; for (int j = 0; j < 6; ++j) acc += G[i][j] * xb[j]; xq[i] = acc; }
+        backward_predict(G, Q, Cb, Cq);
+        for (int i = 0; i < 6; ++i) {
+            a[i] = k > 0 ? xf[6 * (k - 1) + i] : x0[i];
+            for (int j = 0; j < 6; ++j) A[i][j] = k > 0 ? Cf[36 * (k - 1) + 6 * i + j] : C0[6 * i + j];
+        }
+        st = two_filter_combine(a, A, xq, Cq, o, O);
+        if (st) return st;
+        for (int i = 0; i < 6; ++i) { xs_out[6 * k + i] = o[i]; for (int j = 0; j < 6; ++j) Cs_out[36 * k + 6 * i + j] = O[i][j]; }
+        if (k > 0) {
+            double mk[2] = {m[2 * (k - 1)], m[2 * (k - 1) + 1]};
+            const double* v = V3 + 3 * (k - 1);
+            double V[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
+            double c2;
+            st = kalman_update(xq, Cq, mk, V, xb, Cb, &c2);
+            if (st) return st;
+        }
     }
     return 0;
 }

@@ -111,3 +111,62 @@ def test_smoother_gain_is_inverse_jacobian_without_noise(oracle_lib):
         assert _close(xs[k], back, sd, 1e-9)
         Cb = np.linalg.solve(F[k], np.linalg.solve(F[k], Cs[k + 1]).T)
         assert _close(Cs[k], Cb, np.outer(sd, sd), 1e-9)
+
+
+def _condition_rows(mu, Sig, rows, R, y):
+    """Condition N(mu, Sig) on y = Hs x + e, e ~ N(0, R) (Hs = stacked rows)."""
+    Hs = np.vstack(rows)
+    Sy = Hs @ Sig @ Hs.T + R
+    G = np.linalg.solve(Sy, Hs @ Sig).T
+    return mu + G @ (y - Hs @ mu), Sig - G @ Hs @ Sig
+
+
+@pytest.mark.parametrize("seed,n,with_noise,scale", [(4, 3, False, 1e3), (5, 8, True, 1e2), (6, 12, True, 1e4)])
+def test_linear_two_filter_is_conditioning_with_a_weak_prior(oracle_lib, seed, n, with_noise, scale):
+    """Two-filter smoother (Sect. 2, Fig. 2) on a linear-Gaussian model.
+
+    Its backward filter starts from the last filtered state x_{n|n} with
+    covariance scale * C_{n|n}.  With a backward model x_k = G_k x_{k+1} - w_k
+    (G_k = F_k^{-1}) the backward transition density equals the forward one,
+    so the combined estimate of state k < n is the joint Gaussian conditioned
+    on every measurement plus one extra observation y = x_{n|n} of state n with
+    covariance scale * C_{n|n}; state n itself is the filtered state.  Because
+    y equals the posterior mean of state n, the extra observation moves no
+    mean: the means are the RTS means, and only the covariances shrink, by a
+    part of order 1/scale."""
+    rng = np.random.default_rng(seed)
+    F, Q, m, V, x0, C0 = _model(rng, n, with_noise)
+    # component 2 is the azimuth, which the update and the combination wrap
+    # into (-pi, pi]: scale the means down so that the weakly constrained
+    # backward predictions stay far inside that range (the model is linear,
+    # so this changes nothing else)
+    m, x0 = 0.05 * m, 0.05 * x0
+    G = np.linalg.inv(F)
+    xs2, Cs2 = oracle_lib.linear_two_filter(F, G, Q, m, V, x0, C0, scale)
+    xs, Cs, _, _, _ = oracle_lib.linear_smoother(F, Q, m, V, x0, C0)
+    mu, Sig = _joint(F, Q, x0, C0)
+    pm, pS, _ = _condition(mu, Sig, m, V, n)
+    last = slice(6 * n, 6 * n + 6)
+    rows, R = [], np.zeros((2 * n + 6, 2 * n + 6))
+    for k in range(1, n + 1):
+        Hk = np.zeros((2, mu.size))
+        Hk[:, 6 * k: 6 * k + 6] = H2
+        rows.append(Hk)
+        R[2 * k - 2: 2 * k, 2 * k - 2: 2 * k] = [[V[k - 1, 0], V[k - 1, 1]], [V[k - 1, 1], V[k - 1, 2]]]
+    Hy = np.zeros((6, mu.size))
+    Hy[:, last] = np.eye(6)
+    rows.append(Hy)
+    R[2 * n:, 2 * n:] = scale * pS[last, last]
+    y = np.concatenate([m.reshape(-1), pm[last]])
+    am, aS = _condition_rows(mu, Sig, rows, R, y)
+    for k in range(n + 1):
+        blk = slice(6 * k, 6 * k + 6)
+        ref_m, ref_S = (pm[blk], pS[blk, blk]) if k == n else (am[blk], aS[blk, blk])
+        sd = np.sqrt(np.diag(ref_S))
+        assert _close(xs2[k], ref_m, sd, 1e-9), k
+        assert _close(Cs2[k], ref_S, np.outer(sd, sd), 1e-9), k
+        assert _close(xs2[k], xs[k], sd, 1e-9), k
+    # the covariance difference to RTS is the weak prior's share, of order 1/scale
+    d = max(np.max(np.abs(Cs2[k] - Cs[k]) / np.outer(np.sqrt(np.diag(Cs[k])), np.sqrt(np.diag(Cs[k]))))
+            for k in range(n))
+    assert 1e-3 / scale < d < 10.0 / scale

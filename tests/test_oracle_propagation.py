@@ -167,6 +167,40 @@ def test_transport_jacobian_matches_finite_differences(oracle_lib, field, x, sb)
     assert np.max(np.abs(J - F) / scale) < 3e-5
 
 
+@pytest.mark.parametrize("field,x", [
+    (synth.Field(0, (0.0, 0.0, 2.0), 0.0), [0.1, -0.2, 0.1, 1.4, 1.0, 0.0]),
+    (synth.Field(0, (0.3, -0.5, 1.7), 0.0), [-1.0, 2.0, -0.12, 1.7, -0.8, 0.3]),
+    (synth.Field(1, (0.0, 0.0, 2.0), 1e-7), [0.0, 150.0, 0.05, 0.9, 0.7, 0.0]),
+])
+def test_backward_transport_retraces_the_trajectory(oracle_lib, field, x):
+    """Transport against the direction of flight (the two-filter smoother's
+    backward filter, Sect. 2 / Fig. 2): from the state reached on plane 30
+    back to plane 0 returns the starting state (the forward leg is pinned to
+    the exact helix and to DOP853 above, so this ties the backward leg to the
+    true trajectory), time runs backwards, and the backward Jacobian is the
+    inverse of the forward one; it also matches central differences."""
+    det = synth.telescope(30)
+    x = np.array(x)
+    st, xo, F, _ = oracle_lib.transport(det, field, 0, 30, x, tol=1e-7)
+    assert st == 0
+    st, xb, G, tr = oracle_lib.transport(det, field, 30, 0, xo, tol=1e-7)
+    assert st == 0 and tr > 1
+    assert np.abs(xb[:2] - x[:2]).max() < 1e-6
+    assert np.abs(xb[2:4] - x[2:4]).max() < 1e-9
+    assert xb[4] == x[4] and abs(xb[5] - x[5]) < 1e-9 and xo[5] > x[5]
+    assert np.abs(G @ F - np.eye(6)).max() < 1e-6
+    J = np.zeros((6, 6))
+    for j in range(6):
+        e = 1e-6 if j != 4 else 1e-7
+        a, b = xo.copy(), xo.copy()
+        a[j] += e
+        b[j] -= e
+        J[:, j] = (oracle_lib.transport(det, field, 30, 0, a)[1] - oracle_lib.transport(det, field, 30, 0, b)[1]) / (2 * e)
+    st, _, G4, _ = oracle_lib.transport(det, field, 30, 0, xo)
+    scale = np.maximum(np.abs(G4), np.abs(G4).max(axis=0, keepdims=True) * 1e-3)
+    assert np.max(np.abs(J - G4) / scale) < 3e-5
+
+
 def test_misaligned_plane_transport_lands_on_plane(oracle_lib):
     det = synth.misalign(synth.telescope(10), np.array([[0, 0.1, -0.2, 0.05, 0.0, 0.3, 0, 0, 0, 0, 0]] * 3 +
                                                         [[0, 0.01, 0.02, -0.03, 0.01, 0, 0, 0, 0, 0, 0]] * 3))
