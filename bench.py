@@ -9,8 +9,10 @@ in HBM), launched as the product runs it: the launch shape is picked by the
 library's autotuner (kf_autotune, untimed) and the whole launch sequence is
 captured once in a HIP graph (kf_plan_create) that every step replays.
 Prints one JSON line.  Besides the FP64 headline it times the
-mixed-precision fit and a fit + adjoint step (kf_fit_tracks then
-kf_fit_tracks_vjp with chi2, smoothed-parameter and target cotangents).
+mixed-precision fit, the same fit with the two-filter smoother (a backward
+Kalman filter, i.e. a second propagation, instead of RTS), a fit + adjoint
+step (kf_fit_tracks then kf_fit_tracks_vjp with chi2, smoothed-parameter and
+target cotangents) and the fit from pinned host buffers (PCIe included).
 
 The roofline entry uses the oracle's count of non-trivial floating-point
 operations per track (add/sub, mul, div, sqrt) times the tracks in a launch,
@@ -123,6 +125,7 @@ def main():
                     help="without --autotune: transport Jacobians stored for the smoother or recomputed by it")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the fit + adjoint leg")
+    ap.add_argument("--no-two-filter", action="store_true", help="skip the two-filter smoother leg")
     ap.add_argument("--no-staged", action="store_true",
                     help="skip the host-buffer leg (copies in, fit, copies out, chunked over streams)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -162,9 +165,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def prepared_plan(precision):
+    def prepared_plan(precision, **extra):
         """Plan with autotuned launch settings, captured in a HIP graph."""
-        plan = kfmi.Plan(batch, kfmi.Options(precision=precision, **base_opt))
+        plan = kfmi.Plan(batch, kfmi.Options(precision=precision, **base_opt, **extra))
         tuned = None
         if not args.no_autotune:
             opt, tune_ms = plan.autotune()
@@ -188,6 +191,19 @@ def main():
         msm, kmsm, _ = time_plan(planm, args.steps, args.warmup)
         mixed = {"value": N / (msm * 1e-3), "ms_per_step": msm, "launch_ms": kmsm,
                  "speedup_vs_fp64": ms64 / msm, "launch": tunedm}
+
+    two_filter = None
+    if not args.no_two_filter:
+        # the other smoother of Sect. 2: a backward Kalman filter (second
+        # propagation) combined with the forward filter, same workload
+        plant, tunedt = prepared_plan(kfmi.KF_PREC_FP64, smoother=kfmi.KF_SMOOTHER_TWO_FILTER)
+        mst, kmst, _ = time_plan(plant, args.steps, args.warmup)
+        two_filter = {"value": N / (mst * 1e-3), "unit": "tracks/s", "ms_per_step": mst, "launch_ms": kmst,
+                      "rts_speedup": mst / ms64, "launch": tunedt,
+                      "tracks_ok": int((plant.out.status.cpu().numpy() == 0).sum()),
+                      "what": "filter + two-filter smoother (backward filter from the last hit, "
+                              "combined with the forward filter), FP64"}
+        del plant
 
     staged = None
     if not args.no_staged:
@@ -289,6 +305,7 @@ def main():
                    "gen_seconds": round(t_gen, 2)},
         "mixed": mixed,
         "adjoint": adjoint,
+        "two_filter": two_filter,
         "staged": staged,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -86,6 +86,11 @@ extern "C" {
 #define KF_JAC_STORE 0         /* transport Jacobians stored by the filter, read by the smoother */
 #define KF_JAC_RECOMPUTE 1     /* smoother re-propagates the filtered state (less memory traffic) */
 
+#define KF_SMOOTHER_RTS 0         /* Rauch-Tung-Striebel with the forward pass's transport Jacobians */
+#define KF_SMOOTHER_TWO_FILTER 1  /* a second Kalman filter from the last hit back to the seed surface,
+                                     propagating against the direction of flight, combined with the
+                                     forward filter (Sect. 2, Fig. 2) */
+
 #define KF_MAX_SURFACES 512     /* the surface table is staged in LDS (13 doubles each) */
 #define KF_MAX_HITS 64         /* per track */
 
@@ -140,6 +145,20 @@ typedef struct {
                                     smoother (52 workspace doubles per hit); KF_JAC_RECOMPUTE: the
                                     smoother propagates each filtered state again instead (27 doubles
                                     per hit; fused smoother only) */
+    int32_t smoother;            /* KF_SMOOTHER_*.  TWO_FILTER: the backward filter starts at the last
+                                    hit from the forward filtered state there with its covariance times
+                                    bwd_scale, and takes in every hit on its way back; at each surface
+                                    it adds the scatterer's variance as the forward filter evaluated it
+                                    (at the forward filtered state) after propagating back, and its
+                                    prediction (hits after k) combines with the forward filtered state
+                                    (hits up to k): K = Cf (Cf + Cb)^-1, xs = xf + K (xb - xf),
+                                    Cs = (I - K) Cf (I - K)^T + K Cb K^T.  The last hit keeps its
+                                    filtered state; the seed surface gets the combination with the
+                                    seed.  Fused smoother only (split_smoother 0; jacobians ignored);
+                                    kf_fit_tracks_vjp supports RTS only */
+    double bwd_scale;            /* TWO_FILTER: inflation of the backward filter's starting covariance
+                                    (> 1; 0 = 1e3).  Its information, 1/bwd_scale of the last
+                                    filtered state's, counts twice in the combination */
 } kf_config;
 
 typedef struct {
@@ -166,7 +185,8 @@ const char *kf_status_string(int code);
  * transport Jacobian per hit) plus small per-track and per-tile tables. */
 size_t kf_workspace_bytes(const kf_config *cfg, const kf_measurements *meas, int32_t n_surfaces);
 
-/* Filter + RTS smoother for every track (Sect. 2; Sect. 4.1; Sect. 4.3).
+/* Filter + smoother (RTS or two-filter, cfg->smoother) for every track
+ * (Sect. 2; Sect. 4.1; Sect. 4.3).
  * All pointers inside the structs are device pointers except where stated.
  * Returns KF_OK or a negative KF_E_* code; per-track results in out->status. */
 int kf_fit_tracks(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
@@ -190,12 +210,13 @@ void kf_plan_destroy(kf_plan *plan);
 /* Launch-shape autotuner (the paper's grid/block/register studies, Sect. 5.3,
  * made automatic): times every candidate schedule (direct / length-sorted
  * persistent), workgroup size, register budget (waves per SIMD), fused or
- * separate smoother kernel, stored or recomputed transport Jacobians and
+ * separate smoother kernel, stored or recomputed transport Jacobians (RTS
+ * only: a two-filter fit tries the fused kernel alone) and
  * persistent waves per CU on these very buffers
  * (outputs are overwritten), synchronising `stream`.  Writes the fastest
  * setting to *best (and its time per fit to *best_ms if not NULL) and
  * remembers it: later calls with AUTO (0) settings and the same precision,
- * field kind, max_hits and track count (to a power of two) use it. */
+ * field kind, smoother, max_hits and track count (to a power of two) use it. */
 int kf_autotune(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
                 const kf_measurements *meas, const kf_seeds *seeds, const kf_outputs *out,
                 void *workspace, size_t workspace_bytes, void *stream, kf_config *best, float *best_ms);

@@ -645,4 +645,66 @@ __device__ inline void rts_cov(const double A[36], const double D[21], double R[
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-filter smoother step (Sect. 2, Fig. 2): the forward estimate (xf, Cf)
+// and the backward filter's prediction (xb, Cb) of the same state are
+// independent; their combination with K = Cf (Cf + Cb)^{-1} is
+//   xs = xf + K (xb - xf)                          (phi difference wrapped)
+//   Cs = (I - K) Cf (I - K)^T + K Cb K^T           (covariance of that sum)
+// Column c of K^T is (Cf + Cb)^{-1} Cf[:, c] (FP64 Cholesky).  Returns false
+// if Cf + Cb is not positive definite.
+// ---------------------------------------------------------------------------
+__device__ inline bool two_filter_combine(const double xf[6], const double Cf[21], const double xb[6],
+                                          const double Cb[21], double xs[6], double Cs[21]) {
+    double L[21], id[6], S[21];
+#pragma unroll
+    for (int q = 0; q < 21; ++q) S[q] = Cf[q] + Cb[q];
+    const bool ok = chol6(S, L, id);
+    double K[36];                                    // K[6 * i + c]
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double g[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) g[i] = Cf[sy(i, c)];
+        chol_solve6(L, id, g);                       // column c of K^T = row c of K
+#pragma unroll
+        for (int i = 0; i < 6; ++i) K[6 * c + i] = g[i];
+    }
+    double dx[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) dx[i] = xb[i] - xf[i];
+    dx[2] = wrap_phi(dx[2]);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double acc = xf[i];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc += K[6 * i + k] * dx[k];
+        xs[i] = acc;
+    }
+    xs[2] = wrap_phi(xs[2]);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double e[6], f[6];                           // row i of (I - K) Cf and of K Cb
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+            double a = Cf[sy(i, m)], b = 0.0;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                a -= K[6 * i + k] * Cf[sy(k, m)];
+                b += K[6 * i + k] * Cb[sy(k, m)];
+            }
+            e[m] = a;
+            f[m] = b;
+        }
+#pragma unroll
+        for (int j = i; j < 6; ++j) {
+            double acc = e[j];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) acc += f[m] * K[6 * j + m] - e[m] * K[6 * j + m];
+            Cs[sy(i, j)] = acc;
+        }
+    }
+    return ok;
+}
+
 }  // namespace kfm

@@ -17,6 +17,11 @@
 //     gain in FP64 (Cholesky of the predicted covariance, Sect. 4.2.4),
 //     applies the smoother and writes the smoothed states to the caller's CSR
 //     outputs, and the seed-surface result to tgt_*.
+// The two-filter smoother (KF_SMOOTHER_TWO_FILTER; Sect. 2, Fig. 2) replaces
+// the RTS pass by a second Kalman filter run from the last hit back to the
+// seed surface, propagating against the direction of flight, whose
+// predictions combine with the forward filtered states (fused kernel, 27
+// doubles per hit in the workspace).
 // Schedules: DIRECT (track i on lane i) and SORTED (tracks ordered by hit
 // count, longest first; persistent waves pull 64-track tiles from a queue so
 // that waves carry tracks of equal length).
@@ -82,6 +87,7 @@ struct FitArgs {
     const int32_t* order;       // slot -> track (SORTED) or NULL
     int32_t* tile_counter;      // SORTED queue heads: [0] forward pass, [1] backward pass
     int n_tiles;
+    double bwd_scale;           // two-filter smoother: inflation of the backward filter's start
 };
 
 // Forward filter of the track held by workspace slot `slot` (track index t):
@@ -324,6 +330,111 @@ __device__ bool bwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t
     return false;
 }
 
+// Two-filter smoother of one track (Sect. 2, Fig. 2), fused after the forward
+// pass (which kept only the predictions: 27 doubles per hit).  The backward
+// filter starts at the last hit from the forward filtered state with its
+// covariance times bwd_scale and takes in that hit; then for k = n-2 .. 0 and
+// finally the seed surface it propagates back to surface k (against the
+// direction of flight, the forward pass's transport routine), adds the
+// scatterer of surface k as the forward filter evaluated it (at the forward
+// filtered state of hit k, or the seed), combines that prediction with the
+// forward filtered state of hit k (recomputed from the stored prediction and
+// the hit, bit for bit as in the forward pass) into the smoothed state, which
+// replaces slot k, and takes in hit k.  The last hit keeps its filtered
+// state.  Returns true if the track's smoothed states are in its slots.
+template <class P, int FK>
+__device__ bool bwd_two_filter(const FitArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
+    constexpr int NW = NC_RECOMPUTE;
+    if (a.status[t] != ST_OK) return false;
+    const int o = a.off[t];
+    const int n = a.off[t + 1] - o;
+    const int64_t H = a.n_hits;
+    const int64_t N = a.n_tracks;
+    double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
+    Field<P, FK> fl;
+    fl.init(a.field);
+    int fail = ST_OK;
+    double xb[6], Cb[21];
+    {
+        double* w = wl + (n - 1) * (NW * TILE);
+        double xp[6], Cp[21], m[2], V[3], x[6], C[21], ck;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) xp[i] = w[(OFF_XP + i) * TILE];
+#pragma unroll
+        for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
+        load_rows(a.loc + o + n - 1, H, m);
+        load_rows(a.cov + o + n - 1, H, V);
+        kalman_update(xp, Cp, m, V, x, C, &ck);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) w[(OFF_XP + i) * TILE] = x[i];
+#pragma unroll
+        for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = C[q];
+#pragma unroll
+        for (int q = 0; q < 21; ++q) C[q] *= a.bwd_scale;
+        if (kalman_update(x, C, m, V, xb, Cb, &ck) != ST_OK) fail = ST_NOT_SPD;
+    }
+    int s1 = a.sid[o + n - 1];
+    double xs[6], Cs[21];
+    for (int k = n - 2; k >= -1 && fail == ST_OK; --k) {
+        double xf[6], Cf[21], m[2], V[3];
+        int s0 = a.seed_sid;
+        double* w = wl + (k >= 0 ? k : 0) * (NW * TILE);
+        if (k >= 0) {
+            double xp[6], Cp[21], ck;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) xp[i] = w[(OFF_XP + i) * TILE];
+#pragma unroll
+            for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
+            load_rows(a.loc + o + k, H, m);
+            load_rows(a.cov + o + k, H, V);
+            s0 = a.sid[o + k];
+            kalman_update(xp, Cp, m, V, xf, Cf, &ck);
+        } else {
+            load_rows(a.seed + t, N, xf);
+            load_rows(a.seed_cov + t, N, Cf);
+        }
+        double q22 = 0.0, q33 = 0.0;
+        if (a.cfg.ms) highland(sm + s0 * SURF_STRIDE, xf, a.cfg.mass, &q22, &q33);
+        phase_boundary();
+        double xq[6], G[25];
+        int tr = 0;
+        fail = transport<P, FK>(fl, a.field, a.cfg, sm + s1 * SURF_STRIDE, sm + s0 * SURF_STRIDE, xb, xq, G, &tr);
+        if (fail != ST_OK) break;
+        phase_boundary();
+        double Cq[21];
+        transport_cov(G, Cb, Cq);
+        Cq[sy(2, 2)] += q22;
+        Cq[sy(3, 3)] += q33;
+        phase_boundary();
+        if (!two_filter_combine(xf, Cf, xq, Cq, xs, Cs)) { fail = ST_NOT_SPD; break; }
+        phase_boundary();
+        if (k >= 0) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) w[(OFF_XP + i) * TILE] = xs[i];
+#pragma unroll
+            for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = Cs[q];
+            double ck;
+            if (kalman_update(xq, Cq, m, V, xb, Cb, &ck) != ST_OK) { fail = ST_NOT_SPD; break; }
+        }
+        s1 = s0;
+    }
+    if (fail == ST_OK) {
+        store_rows(a.tgt_par + t, N, xs);
+        store_rows(a.tgt_cov + t, N, Cs);
+        return true;
+    }
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    for (int k = 0; k < n; ++k) {
+        fill_rows<6>(a.par + o + k, H, nan);
+        fill_rows<21>(a.pcov + o + k, H, nan);
+    }
+    fill_rows<6>(a.tgt_par + t, N, nan);
+    fill_rows<21>(a.tgt_cov + t, N, nan);
+    a.chi2[t] = nan;
+    a.status[t] = (uint8_t)fail;
+    return false;
+}
+
 // All lanes of the wave, in step: LDS written by one lane is then visible to
 // the others (the waves of a workgroup run different tiles, so no workgroup
 // barrier may be used here).
@@ -411,12 +522,14 @@ __device__ void flush_tile(const FitArgs& a, double* lw, const double* wtile, bo
 // FUSED runs the smoother for a track right after its forward pass, while
 // its workspace column is still cache-hot (otherwise k_bwd does it); STOREF
 // (always with a split smoother) stores the transport Jacobians, otherwise the
-// fused smoother recomputes them.
+// fused smoother recomputes them; TWOF (fused, no stored Jacobians) runs the
+// two-filter smoother instead of RTS.
 // Dynamic LDS: the surface table, then per wave the carried covariances.
-template <class P, int FK, int OCC, bool SORTED, bool FUSED, bool STOREF>
+template <class P, int FK, int OCC, bool SORTED, bool FUSED, bool STOREF, bool TWOF>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
 k_fwd(FitArgs a) {
     static_assert(FUSED || STOREF, "the split smoother reads stored Jacobians");
+    static_assert(!TWOF || (FUSED && !STOREF), "the two-filter smoother is fused and stores no Jacobians");
     extern __shared__ double sm[];
     stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, sm);
     const int lane = threadIdx.x & (TILE - 1);
@@ -431,7 +544,11 @@ k_fwd(FitArgs a) {
         if (i < a.n_tracks) {
             const int t = SORTED ? a.order[i] : (int)i;
             fwd_one<P, FK, STOREF>(a, sm, cl, i, t);
-            if (FUSED) {
+            if constexpr (TWOF) {
+                done = bwd_two_filter<P, FK>(a, sm, i, t);
+                o = a.off[t];
+                n = a.off[t + 1] - o;
+            } else if constexpr (FUSED) {
                 done = bwd_one<P, FK, STOREF>(a, sm, i, t);
                 o = a.off[t];
                 n = a.off[t + 1] - o;
@@ -503,7 +620,7 @@ int validate(const kf_config* cfg, const kf_surfaces* surf, const kf_field* fiel
     return KF_OK;
 }
 
-template <class P, int FK, int OCC, bool STOREF>
+template <class P, int FK, int OCC, bool STOREF, bool TWOF>
 hipError_t launch_fit_fused(const FitArgs& a, int sched, int block, int waves_per_cu, size_t shm,
                             hipStream_t stream) {
     const int need = (a.n_tiles * TILE + block - 1) / block;
@@ -511,38 +628,40 @@ hipError_t launch_fit_fused(const FitArgs& a, int sched, int block, int waves_pe
     if (sched == KF_SCHED_SORTED) {
         int grid = num_cu() * waves_per_cu * TILE / block;
         grid = grid > need ? need : (grid < 1 ? 1 : grid);
-        if ((e = allow_lds(k_fwd<P, FK, OCC, true, true, STOREF>, shm)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, true, STOREF>), dim3(grid), dim3(block), shm, stream, a);
+        if ((e = allow_lds(k_fwd<P, FK, OCC, true, true, STOREF, TWOF>, shm)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, true, STOREF, TWOF>), dim3(grid), dim3(block), shm, stream, a);
     } else {
-        if ((e = allow_lds(k_fwd<P, FK, OCC, false, true, STOREF>, shm)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, true, STOREF>), dim3(need), dim3(block), shm, stream, a);
+        if ((e = allow_lds(k_fwd<P, FK, OCC, false, true, STOREF, TWOF>, shm)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, true, STOREF, TWOF>), dim3(need), dim3(block), shm, stream,
+                           a);
     }
     return hipGetLastError();
 }
 
 template <class P, int FK, int OCC>
 hipError_t launch_fit_occ(const FitArgs& a, int sched, int block, int waves_per_cu, bool split, bool storef,
-                          hipStream_t stream) {
+                          bool twof, hipStream_t stream) {
     const size_t shm = ((size_t)a.n_surf * SURF_STRIDE + (size_t)(block / TILE) * WAVE_LDS_DOUBLES) * sizeof(double);
     const size_t shm_b = (size_t)(block / TILE) * WAVE_LDS_DOUBLES * sizeof(double);
     const int need = (a.n_tiles * TILE + block - 1) / block;
     hipError_t e = hipSuccess;
+    if (twof) return launch_fit_fused<P, FK, OCC, false, true>(a, sched, block, waves_per_cu, shm, stream);
     if (!split)
-        return storef ? launch_fit_fused<P, FK, OCC, true>(a, sched, block, waves_per_cu, shm, stream)
-                      : launch_fit_fused<P, FK, OCC, false>(a, sched, block, waves_per_cu, shm, stream);
+        return storef ? launch_fit_fused<P, FK, OCC, true, false>(a, sched, block, waves_per_cu, shm, stream)
+                      : launch_fit_fused<P, FK, OCC, false, false>(a, sched, block, waves_per_cu, shm, stream);
     if (sched == KF_SCHED_SORTED) {
         int grid = num_cu() * waves_per_cu * TILE / block;
         grid = grid > need ? need : (grid < 1 ? 1 : grid);
         int gridb = num_cu() * 8 * TILE / block;
         gridb = gridb > need ? need : (gridb < 1 ? 1 : gridb);
-        if ((e = allow_lds(k_fwd<P, FK, OCC, true, false, true>, shm)) != hipSuccess) return e;
+        if ((e = allow_lds(k_fwd<P, FK, OCC, true, false, true, false>, shm)) != hipSuccess) return e;
         if ((e = allow_lds(k_bwd<true>, shm_b)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, false, true>), dim3(grid), dim3(block), shm, stream, a);
+        hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, false, true, false>), dim3(grid), dim3(block), shm, stream, a);
         hipLaunchKernelGGL((k_bwd<true>), dim3(gridb), dim3(block), shm_b, stream, a);
     } else {
-        if ((e = allow_lds(k_fwd<P, FK, OCC, false, false, true>, shm)) != hipSuccess) return e;
+        if ((e = allow_lds(k_fwd<P, FK, OCC, false, false, true, false>, shm)) != hipSuccess) return e;
         if ((e = allow_lds(k_bwd<false>, shm_b)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, false, true>), dim3(need), dim3(block), shm, stream, a);
+        hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, false, true, false>), dim3(need), dim3(block), shm, stream, a);
         hipLaunchKernelGGL((k_bwd<false>), dim3(need), dim3(block), shm_b, stream, a);
     }
     return hipGetLastError();
@@ -550,11 +669,11 @@ hipError_t launch_fit_occ(const FitArgs& a, int sched, int block, int waves_per_
 
 template <class P, int FK>
 hipError_t launch_fit(const FitArgs& a, int sched, int block, int waves_per_cu, int occ, bool split, bool storef,
-                      hipStream_t stream) {
+                      bool twof, hipStream_t stream) {
     switch (occ) {
-        case 1: return launch_fit_occ<P, FK, 1>(a, sched, block, waves_per_cu, split, storef, stream);
-        case 3: return launch_fit_occ<P, FK, 3>(a, sched, block, waves_per_cu, split, storef, stream);
-        default: return launch_fit_occ<P, FK, 2>(a, sched, block, waves_per_cu, split, storef, stream);
+        case 1: return launch_fit_occ<P, FK, 1>(a, sched, block, waves_per_cu, split, storef, twof, stream);
+        case 3: return launch_fit_occ<P, FK, 3>(a, sched, block, waves_per_cu, split, storef, twof, stream);
+        default: return launch_fit_occ<P, FK, 2>(a, sched, block, waves_per_cu, split, storef, twof, stream);
     }
 }
 
@@ -572,8 +691,10 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     a.max_hits = meas->max_hits;
     a.n_hits = meas->n_hits;
     // the workspace is sized for stored Jacobians; without them a tile packs tighter
-    a.tile_doubles = cfg->jacobians == KF_JAC_RECOMPUTE ? (int64_t)meas->max_hits * NC_RECOMPUTE * TILE
-                                                         : L.tile_doubles;
+    const bool twof = cfg->smoother == KF_SMOOTHER_TWO_FILTER;
+    a.tile_doubles = (cfg->jacobians == KF_JAC_RECOMPUTE || twof) ? (int64_t)meas->max_hits * NC_RECOMPUTE * TILE
+                                                                  : L.tile_doubles;
+    a.bwd_scale = cfg->bwd_scale > 0.0 ? cfg->bwd_scale : 1e3;
     a.off = meas->hit_offsets;
     a.sid = meas->surface_id;
     a.loc = meas->loc;
@@ -615,14 +736,14 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     const bool mixed = cfg->precision == KF_PREC_MIXED;
     const int occ = cfg->occupancy;
     const bool split = cfg->split_smoother != 0;
-    const bool storef = cfg->jacobians != KF_JAC_RECOMPUTE;
-    if (!storef && split) return KF_E_VALUE;
+    const bool storef = cfg->jacobians != KF_JAC_RECOMPUTE && !twof;
+    if ((!storef || twof) && split) return KF_E_VALUE;
     if (field->kind == KF_FIELD_UNIFORM)
-        e = mixed ? launch_fit<float, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, storef, stream)
-                  : launch_fit<double, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, storef, stream);
+        e = mixed ? launch_fit<float, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, storef, twof, stream)
+                  : launch_fit<double, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, storef, twof, stream);
     else
-        e = mixed ? launch_fit<float, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, stream)
-                  : launch_fit<double, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, stream);
+        e = mixed ? launch_fit<float, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, twof, stream)
+                  : launch_fit<double, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, twof, stream);
     if (e == hipErrorInvalidValue) return KF_E_VALUE;     // workgroup needs more LDS than the device has
     return e == hipSuccess ? KF_OK : KF_E_HIP;
 }
@@ -632,10 +753,11 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
 // Key: precision, field kind, max hits per track, track count rounded to a
 // power of two.  Filled by kf_autotune, read when a setting is AUTO (0).
 struct TuneKey {
-    int precision, field_kind, max_hits, log2n;
+    int precision, field_kind, smoother, max_hits, log2n;
     bool operator<(const TuneKey& o) const {
         if (precision != o.precision) return precision < o.precision;
         if (field_kind != o.field_kind) return field_kind < o.field_kind;
+        if (smoother != o.smoother) return smoother < o.smoother;
         if (max_hits != o.max_hits) return max_hits < o.max_hits;
         return log2n < o.log2n;
     }
@@ -646,7 +768,7 @@ std::map<TuneKey, kf_config> g_tune;
 TuneKey tune_key(const kf_config* cfg, const kf_field* field, const kf_measurements* meas) {
     int l = 0;
     while ((1LL << (l + 1)) <= (long long)meas->n_tracks) ++l;
-    return TuneKey{cfg->precision, field->kind, meas->max_hits, l};
+    return TuneKey{cfg->precision, field->kind, cfg->smoother, meas->max_hits, l};
 }
 
 // Fill AUTO (0) launch settings from the tuning table, else the defaults
@@ -666,7 +788,7 @@ kf_config resolve(const kf_config* cfg, const kf_field* field, const kf_measurem
     }
     if (r.schedule == KF_SCHED_AUTO) {
         r.schedule = d.schedule;
-        r.split_smoother = d.split_smoother;
+        r.split_smoother = r.smoother == KF_SMOOTHER_TWO_FILTER ? 0 : d.split_smoother;
         r.jacobians = d.jacobians;
     }
     if (r.block == 0) r.block = d.block;
@@ -876,6 +998,7 @@ int kf_autotune(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
                 for (int sp : splits)
                     for (int wp : wpcs) {
                         if (sc == KF_SCHED_DIRECT && wp != wpcs[0]) continue;   // unused by DIRECT
+                        if (cfg->smoother == KF_SMOOTHER_TWO_FILTER && sp != 0) continue;   // fused only
                         kf_config c = *cfg;
                         c.schedule = sc;
                         c.block = bl;

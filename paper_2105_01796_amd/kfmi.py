@@ -26,6 +26,7 @@ KF_FIELD_UNIFORM, KF_FIELD_SOLENOID = 0, 1
 KF_PREC_FP64, KF_PREC_MIXED = 0, 1
 KF_SCHED_AUTO, KF_SCHED_DIRECT, KF_SCHED_SORTED = 0, 1, 2
 KF_JAC_STORE, KF_JAC_RECOMPUTE = 0, 1
+KF_SMOOTHER_RTS, KF_SMOOTHER_TWO_FILTER = 0, 1
 KF_MAX_SURFACES = 512
 KF_MAX_HITS = 64
 
@@ -53,7 +54,8 @@ class kf_config(C.Structure):
     _fields_ = [("precision", C.c_int32), ("multiple_scattering", C.c_int32), ("mass", C.c_double),
                 ("rk_tol", C.c_double), ("land_tol", C.c_double), ("max_steps", C.c_int32),
                 ("schedule", C.c_int32), ("block", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("occupancy", C.c_int32), ("split_smoother", C.c_int32), ("jacobians", C.c_int32)]
+                ("occupancy", C.c_int32), ("split_smoother", C.c_int32), ("jacobians", C.c_int32),
+                ("smoother", C.c_int32), ("bwd_scale", C.c_double)]
 
 
 class kf_outputs(C.Structure):
@@ -217,6 +219,8 @@ class Options:
     occupancy: int = 0
     split_smoother: int = 0
     jacobians: int = 0          # KF_JAC_STORE / KF_JAC_RECOMPUTE
+    smoother: int = 0           # KF_SMOOTHER_RTS / KF_SMOOTHER_TWO_FILTER
+    bwd_scale: float = 0.0      # two-filter: backward start covariance inflation (0 = 1e3)
 
 
 def _max_hits(b: Batch) -> int:
@@ -229,7 +233,8 @@ def _max_hits(b: Batch) -> int:
 def _structs(b: Batch, opt: Options):
     """kf_config, kf_surfaces, kf_field, kf_measurements, kf_seeds for a batch."""
     cfg = kf_config(opt.precision, int(b.multiple_scattering), b.mass, opt.rk_tol, opt.land_tol, opt.max_steps,
-                    opt.schedule, opt.block, opt.waves_per_cu, opt.occupancy, opt.split_smoother, opt.jacobians)
+                    opt.schedule, opt.block, opt.waves_per_cu, opt.occupancy, opt.split_smoother, opt.jacobians,
+                    opt.smoother, opt.bwd_scale)
     if b.align is not None and tuple(b.align.shape) != (6, b.center.shape[1]):
         raise ValueError("align must have shape (6, S)")
     surf = kf_surfaces(b.center.shape[1], _ptr(b.center), _ptr(b.rot), _ptr(b.x_over_X0), _ptr(b.align))
@@ -300,7 +305,8 @@ class Plan:
         self.cfg = best
         self.release()
         o = Options(best.precision, best.rk_tol, best.land_tol, best.max_steps, best.schedule, best.block,
-                    best.waves_per_cu, best.occupancy, best.split_smoother, best.jacobians)
+                    best.waves_per_cu, best.occupancy, best.split_smoother, best.jacobians, best.smoother,
+                    best.bwd_scale)
         return o, ms.value
 
     def release(self):

@@ -95,6 +95,17 @@ def test_argument_validation(kf):
     assert _call(kf, *a) == kf.KF_E_VALUE
     cfg.split_smoother = 0
     cfg.jacobians = kf.KF_JAC_STORE
+    cfg.smoother = 2
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.smoother = kf.KF_SMOOTHER_TWO_FILTER
+    cfg.split_smoother = 1                     # the two-filter smoother is fused only
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.split_smoother = 0
+    for bad in (0.5, 1.0, -3.0, float("nan"), float("inf")):
+        cfg.bwd_scale = bad
+        assert _call(kf, *a) == kf.KF_E_VALUE, bad
+    cfg.bwd_scale = 0.0
+    cfg.smoother = kf.KF_SMOOTHER_RTS
     fld.b0[2] = float("nan")
     assert _call(kf, *a) == kf.KF_E_VALUE
     fld.b0[2] = 2.0
@@ -170,6 +181,9 @@ def test_vjp_argument_validation(kf):
     cfg.land_tol = -1.0
     assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_VALUE
     cfg.land_tol = 1e-6
+    cfg.smoother = kf.KF_SMOOTHER_TWO_FILTER    # the adjoint is that of the RTS fit
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_VALUE
+    cfg.smoother = kf.KF_SMOOTHER_RTS
     surf.n = kf.KF_MAX_SURFACES + 1
     assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad, nbytes=1 << 40) == kf.KF_E_SIZE
     surf.n = 11
