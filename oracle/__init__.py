@@ -50,7 +50,7 @@ def lib():
         P = C.c_void_p
         i, d = C.c_int, C.c_double
         fit_args = [i, P, P, P, P, i, P, P, P, P, i, P, d, P, P, i, i, d, d, d, i]
-        L.kfo_fit.argtypes = fit_args + [P] * 12 + [i, i, d]
+        L.kfo_fit.argtypes = fit_args + [P] * 12 + [i, i, d, i, P]
         L.kfo_fit.restype = i
         L.kfo_fit_vjp.argtypes = fit_args + [P] * 6 + [i]
         L.kfo_fit_vjp.restype = i
@@ -58,6 +58,8 @@ def lib():
         L.kfo_count_ops.restype = i
         L.kfo_transport.argtypes = [i, P, P, P, i, P, d, d, d, d, i, i, i, P, P, P, P]
         L.kfo_transport.restype = i
+        L.kfo_transport_perigee.argtypes = [i, P, P, P, i, P, d, d, d, d, i, i, P, P, P, P, P]
+        L.kfo_transport_perigee.restype = i
         L.kfo_rkn_step.argtypes = [i, P, d, d, P, d, P, P]
         L.kfo_rkn_step.restype = d
         L.kfo_linear_smoother.argtypes = [i] + [P] * 11
@@ -128,12 +130,14 @@ DEFAULT_BWD_SCALE = 1e3
 
 
 def fit(ev, n_threads: int = 0, extras: bool = False, smoother: str = "rts", bwd_scale: float = DEFAULT_BWD_SCALE,
-        **kw) -> FitResult:
+        perigee=None, **kw) -> FitResult:
     """Filter + smoother for every track of `ev` (FP64).
 
     smoother: "rts" (stored Jacobians) or "two_filter" (a backward filter
     started from the last filtered covariance times `bwd_scale`, combined with
-    the forward filter)."""
+    the forward filter).  perigee: None (target = the seed surface) or a
+    reference point (3,): the target result is given at the perigee of the
+    line through it parallel to z, (d0, z0, phi, theta, q/p, t)."""
     a = _Args(ev, **kw)
     N, H = a.N, a.H
     out = FitResult(np.empty((6, H)), np.empty((21, H)), np.empty((6, N)), np.empty((21, N)),
@@ -144,7 +148,8 @@ def fit(ev, n_threads: int = 0, extras: bool = False, smoother: str = "rts", bwd
         out.trials = np.empty(H, np.int32)
     lib().kfo_fit(*a.args, _p(out.par), _p(out.cov), _p(out.tgt_par), _p(out.tgt_cov), _p(out.chi2),
                   _p(out.ndf), _p(out.status), _p(out.filt_par), _p(out.filt_cov), _p(out.pred_par),
-                  _p(out.pred_cov), _p(out.trials), int(n_threads), SMOOTHERS[smoother], float(bwd_scale))
+                  _p(out.pred_cov), _p(out.trials), int(n_threads), SMOOTHERS[smoother], float(bwd_scale),
+                  0 if perigee is None else 1, _p(None if perigee is None else _f64(perigee)))
     return out
 
 
@@ -186,6 +191,21 @@ def transport(det, field, sa, sb, x, mass=0.1056583755, tol=DEFAULT_TOL, land_to
     st = lib().kfo_transport(center.shape[1], _p(center), _p(rot), _p(x0), int(field.kind), _p(b0),
                              float(field.a), float(mass), float(tol), float(land_tol), int(max_steps),
                              int(sa), int(sb), _p(xi), _p(xo), _p(F), _p(tr))
+    return st, xo, F, int(tr[0])
+
+
+def transport_perigee(det, field, sa, c, x, mass=0.1056583755, tol=DEFAULT_TOL, land_tol=DEFAULT_LAND_TOL,
+                      max_steps=DEFAULT_MAX_STEPS):
+    """Bound state x on plane sa -> (status, perigee parameters (d0, z0, phi,
+    theta, q/p, t) w.r.t. the line through c parallel to z, F (6,6), trials)."""
+    center, rot, x0 = _f64(det.center), _f64(det.rot), _f64(det.x_over_X0)
+    b0, cc, xi = _f64(field.b0), _f64(c), _f64(x)
+    xo = np.empty(6)
+    F = np.empty((6, 6))
+    tr = np.zeros(1, np.int32)
+    st = lib().kfo_transport_perigee(center.shape[1], _p(center), _p(rot), _p(x0), int(field.kind), _p(b0),
+                                     float(field.a), float(mass), float(tol), float(land_tol), int(max_steps),
+                                     int(sa), _p(cc), _p(xi), _p(xo), _p(F), _p(tr))
     return st, xo, F, int(tr[0])
 
 

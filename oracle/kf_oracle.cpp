@@ -147,6 +147,8 @@ struct Cfg {
     int smoother = 0;          // 0: RTS with the stored Jacobians; 1: forward + backward filter combined
     double bwd_scale = 1e3;    // two-filter: the backward filter starts from the last filtered
                                // covariance multiplied by this factor
+    int target = 0;            // 0: the fitted state on the seed surface; 1: at the perigee
+    double perigee[3] = {0.0, 0.0, 0.0};   // perigee line: through this point, parallel to z
 };
 
 template <class S>
@@ -467,6 +469,127 @@ int transport(const FieldDef& f, const Cfg& cfg, const Surf<S>& sa, const Surf<S
 }
 
 // ---------------------------------------------------------------------------
+// Perigee (Sect. 2; Sect. 5.2 quotes the fitted parameters there): the line
+// through the reference point c parallel to z.  At the point of closest
+// approach (r - c)_perp is orthogonal to T_perp; the bound parameters are
+// (d0, z0, phi, theta, q/p, t) with d0 = (r - c) . u, u = (-T_y, T_x, 0)/|T_perp|
+// (z cross the transverse direction), and z0 = r_z - c_z.
+// ---------------------------------------------------------------------------
+// constraint g = (r - c)_perp . T_perp, zero at the closest approach; its rate
+// along the trajectory g' = |T_perp|^2 + (r - c)_perp . T'_perp; its gradient
+// in the free state; dF/ds.
+template <class S>
+void perigee_g(const FieldDef& f, double mass, const double c[3], const S F[8], S* g, S* gp, S dg[8],
+               S dFds[8]) {
+    S r[3] = {F[0], F[1], F[2]}, T[3] = {F[4], F[5], F[6]};
+    S B[3], dB[3][3], TxB[3];
+    field_at(f, r, B, dB);
+    cross(T, B, TxB);
+    S lam = F[7];
+    for (int i = 0; i < 3; ++i) { dFds[i] = T[i]; dFds[4 + i] = lam * kB * TxB[i]; }
+    dFds[3] = sqrt(1.0 + mass * mass * lam * lam) / kC;
+    dFds[7] = 0.0;
+    S dx = r[0] - c[0], dy = r[1] - c[1];
+    *g = dx * T[0] + dy * T[1];
+    *gp = T[0] * T[0] + T[1] * T[1] + dx * dFds[4] + dy * dFds[5];
+    for (int i = 0; i < 8; ++i) dg[i] = 0.0;
+    dg[0] = T[0]; dg[1] = T[1]; dg[4] = dx; dg[5] = dy;
+}
+
+// Adaptive propagation of the free state F to the perigee, with the plane
+// propagation's step control; the distance to go is the Newton step
+// d = -g/g'; land when |d| < land_tol, then move d to second order.  g' must
+// stay positive (a closest approach, not a farthest point).
+template <class S>
+int propagate_perigee(const FieldDef& f, const Cfg& cfg, const double c[3], S F[8], S (&D)[8][8], int* n_trials) {
+    for (int i = 0; i < 8; ++i) for (int j = 0; j < 8; ++j) D[i][j] = (i == j) ? 1.0 : 0.0;
+    double hmag = -1.0;
+    int trials = 0;
+    for (;;) {
+        S g, gp, dg[8], dFds[8];
+        perigee_g(f, cfg.mass, c, F, &g, &gp, dg, dFds);
+        if (!(val(gp) > 1e-6)) { *n_trials = trials; return ST_NO_INTERSECT; }
+        S d = -g / gp;
+        if (std::fabs(val(d)) < cfg.land_tol) break;
+        if (trials >= cfg.max_steps) { *n_trials = trials; return ST_STEP_CAP; }
+        if (hmag < 0.0) hmag = std::fabs(val(d));
+        S h = (std::fabs(val(d)) <= hmag) ? d : S(std::copysign(hmag, val(d)));
+        S Fn[8], Ds[8][8];
+        double err = rkn_step(f, cfg.mass, F, h, Fn, Ds);
+        ++trials;
+        double fac = 0.9 * std::pow(cfg.tol / std::max(err, 1e-300), 0.25);
+        fac = std::min(4.0, std::max(0.25, fac));
+        if (err <= cfg.tol) {
+            for (int i = 0; i < 8; ++i) F[i] = Fn[i];
+            S Dn[8][8];
+            matmul(Ds, D, Dn);
+            for (int i = 0; i < 8; ++i) for (int j = 0; j < 8; ++j) D[i][j] = Dn[i][j];
+        }
+        hmag = std::fabs(val(h)) * fac;
+    }
+    {
+        S g, gp, dg[8], dFds[8];
+        perigee_g(f, cfg.mass, c, F, &g, &gp, dg, dFds);
+        S d = -g / gp;
+        for (int i = 0; i < 3; ++i) {
+            F[i] = F[i] + d * dFds[i] + 0.5 * d * d * dFds[4 + i];
+            F[4 + i] = F[4 + i] + d * dFds[4 + i];
+        }
+        F[3] = F[3] + d * dFds[3];
+    }
+    *n_trials = trials;
+    return ST_OK;
+}
+
+template <class S>
+void free_to_perigee(const double c[3], const S F[8], S P[6], S J[6][8]) {
+    S tx = F[4], ty = F[5], tz = F[6];
+    S rho2 = tx * tx + ty * ty;
+    S rho = sqrt(rho2);
+    S n2 = rho2 + tz * tz;
+    S ux = -ty / rho, uy = tx / rho;
+    S dx = F[0] - c[0], dy = F[1] - c[1];
+    P[0] = dx * ux + dy * uy;
+    P[1] = F[2] - c[2];
+    P[2] = atan2(ty, tx);
+    P[3] = atan2(rho, tz);
+    P[4] = F[7];
+    P[5] = F[3];
+    for (int i = 0; i < 6; ++i) for (int j = 0; j < 8; ++j) J[i][j] = 0.0;
+    S rho3 = rho2 * rho;
+    S gperp = dx * tx + dy * ty;
+    J[0][0] = ux; J[0][1] = uy;
+    J[0][4] = ty * gperp / rho3;
+    J[0][5] = -(tx * gperp) / rho3;
+    J[1][2] = 1.0;
+    J[2][4] = -ty / rho2;  J[2][5] = tx / rho2;
+    J[3][4] = tx * tz / (rho * n2); J[3][5] = ty * tz / (rho * n2); J[3][6] = -rho / n2;
+    J[4][7] = 1.0;
+    J[5][3] = 1.0;
+}
+
+// x on plane surface a -> perigee parameters, with F = dx'/dx.  The path
+// correction moves a variation back onto the constraint g = 0 along dF/ds.
+template <class S>
+int transport_perigee(const FieldDef& f, const Cfg& cfg, const Surf<S>& sa, const double c[3], const S x[6],
+                      S xo[6], S (&Fk)[6][6], int* n_trials) {
+    S F[8], Jbf[8][6], D[8][8], Pc[8][8], Jfb[6][8];
+    bound_to_free(sa, x, F, Jbf);
+    int st = propagate_perigee(f, cfg, c, F, D, n_trials);
+    if (st != ST_OK) return st;
+    S g, gp, dg[8], dFds[8];
+    perigee_g(f, cfg.mass, c, F, &g, &gp, dg, dFds);
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 8; ++j) Pc[i][j] = ((i == j) ? S(1.0) : S(0.0)) - dFds[i] * dg[j] / gp;
+    free_to_perigee(c, F, xo, Jfb);
+    S A[6][8], Bm[6][8];
+    matmul(Jfb, Pc, A);
+    matmul(A, D, Bm);
+    matmul(Bm, Jbf, Fk);
+    return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
 // multiple scattering (thin scatterer after the update, PDG Highland width)
 // ---------------------------------------------------------------------------
 template <class S>
@@ -618,9 +741,9 @@ inline void unpack21(const double* c21, double (&C)[6][6]) {
 }
 
 template <class S>
-int fit_track(const FieldDef& f, const Cfg& cfg, const Surf<S>* surf, int n_surf,
-              int n, const int* sid, const S* m /*[n][2]*/, const double* V3 /*[n][3]*/,
-              const S* seed /*6*/, const double* seed_cov21, int seed_sid, TrackOut<S>& out) {
+int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* surf, int n_surf,
+                           int n, const int* sid, const S* m /*[n][2]*/, const double* V3 /*[n][3]*/,
+                           const S* seed /*6*/, const double* seed_cov21, int seed_sid, TrackOut<S>& out) {
     out.xs.assign(6 * n, S(NAN)); out.Cs.assign(36 * n, S(NAN));
     out.xf.assign(6 * n, S(NAN)); out.Cf.assign(36 * n, S(NAN));
     out.xp.assign(6 * n, S(NAN)); out.Cp.assign(36 * n, S(NAN));
@@ -773,6 +896,35 @@ int fit_track(const FieldDef& f, const Cfg& cfg, const Surf<S>* surf, int n_surf
     return out.status = ST_OK;
 }
 
+// Filter + smoother; with a perigee target the fitted state on the seed
+// surface is then propagated to the perigee, its covariance with that
+// transport's Jacobian.  A failure there fails the track (NaN outputs).
+template <class S>
+int fit_track(const FieldDef& f, const Cfg& cfg, const Surf<S>* surf, int n_surf,
+              int n, const int* sid, const S* m /*[n][2]*/, const double* V3 /*[n][3]*/,
+              const S* seed /*6*/, const double* seed_cov21, int seed_sid, TrackOut<S>& out) {
+    int st = fit_track_seed_surface(f, cfg, surf, n_surf, n, sid, m, V3, seed, seed_cov21, seed_sid, out);
+    if (st != ST_OK || cfg.target != 1) return st;
+    S xo[6], Fp[6][6], T1[6][6], Ft[6][6], Cp[6][6];
+    int trials = 0;
+    st = transport_perigee(f, cfg, surf[seed_sid], cfg.perigee, out.tgt, xo, Fp, &trials);
+    if (st != ST_OK) {
+        for (auto& v : out.xs) v = S(NAN);
+        for (auto& v : out.Cs) v = S(NAN);
+        for (int i = 0; i < 6; ++i) { out.tgt[i] = NAN; for (int j = 0; j < 6; ++j) out.tgt_cov[i][j] = NAN; }
+        out.chi2 = NAN;
+        return out.status = st;
+    }
+    matmul(Fp, out.tgt_cov, T1);
+    transpose(Fp, Ft);
+    matmul(T1, Ft, Cp);
+    for (int i = 0; i < 6; ++i) {
+        out.tgt[i] = xo[i];
+        for (int j = 0; j < 6; ++j) out.tgt_cov[i][j] = Cp[i][j];
+    }
+    return ST_OK;
+}
+
 // alignment a = (dx, dy, dz, alpha, beta, gamma): c <- c + d, R <- R Rx(alpha) Ry(beta) Rz(gamma)
 template <class S>
 void aligned_surface(const Surf<double>& s0, const S a[6], Surf<S>& o) {
@@ -861,7 +1013,9 @@ const char* kfo_version() { return "kf-oracle fp64 1"; }
 
 // Full fit of every track.  Arrays are component-major ([component][item]).
 // Optional outputs may be NULL.  smoother: 0 RTS, 1 two-filter (bwd_scale:
-// inflation of the backward filter's starting covariance).  Returns 0.
+// inflation of the backward filter's starting covariance).  target: 0 seed
+// surface, 1 perigee line through `perigee` (3 values) parallel to z.
+// Returns 0.
 int kfo_fit(int n_tracks, const int32_t* off, const int32_t* sid, const double* loc, const double* cov,
             int n_surf, const double* center, const double* rot, const double* x0, const double* align,
             int field_kind, const double* b0, double field_a,
@@ -869,11 +1023,13 @@ int kfo_fit(int n_tracks, const int32_t* off, const int32_t* sid, const double* 
             int ms, double mass, double tol, double land_tol, int max_steps,
             double* par, double* pcov, double* tgt_par, double* tgt_cov, double* chi2, int32_t* ndf,
             uint8_t* status, double* filt_par, double* filt_cov, double* pred_par, double* pred_cov,
-            int32_t* trials, int n_threads, int smoother, double bwd_scale) {
+            int32_t* trials, int n_threads, int smoother, double bwd_scale, int target, const double* perigee) {
     Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, align, field_kind, b0, field_a,
                             seed, seed_cov, seed_sid, ms, mass, tol, land_tol, max_steps);
     in.cfg.smoother = smoother;
     in.cfg.bwd_scale = bwd_scale;
+    in.cfg.target = target;
+    for (int i = 0; i < 3; ++i) in.cfg.perigee[i] = perigee ? perigee[i] : 0.0;
     std::vector<Surf<double>> surf(n_surf);
     for (int s = 0; s < n_surf; ++s) surf[s] = surf_d(in, s);
     const int64_t H = in.H;
@@ -931,6 +1087,23 @@ int kfo_transport(int n_surf, const double* center, const double* rot, const dou
     for (int i = 0; i < 6; ++i) xi[i] = x[i];
     int tr = 0;
     int st = transport(in.field, in.cfg, A, B, xi, xr, Fk, &tr);
+    for (int i = 0; i < 6; ++i) { xo[i] = xr[i]; for (int j = 0; j < 6; ++j) F[6 * i + j] = Fk[i][j]; }
+    *trials = tr;
+    return st;
+}
+
+// Plane surface sa -> perigee line through c parallel to z; F = dxo/dx.
+int kfo_transport_perigee(int n_surf, const double* center, const double* rot, const double* x0,
+                          int field_kind, const double* b0, double field_a, double mass, double tol,
+                          double land_tol, int max_steps, int sa, const double* c, const double* x, double* xo,
+                          double* F, int32_t* trials) {
+    Inputs in = make_inputs(0, nullptr, nullptr, nullptr, nullptr, n_surf, center, rot, x0, nullptr, field_kind, b0,
+                            field_a, nullptr, nullptr, 0, 0, mass, tol, land_tol, max_steps);
+    Surf<double> A = surf_d(in, sa);
+    double xi[6], xr[6], Fk[6][6], cc[3] = {c[0], c[1], c[2]};
+    for (int i = 0; i < 6; ++i) xi[i] = x[i];
+    int tr = 0;
+    int st = transport_perigee(in.field, in.cfg, A, cc, xi, xr, Fk, &tr);
     for (int i = 0; i < 6; ++i) { xo[i] = xr[i]; for (int j = 0; j < 6; ++j) F[6 * i + j] = Fk[i][j]; }
     *trials = tr;
     return st;
