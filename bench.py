@@ -10,7 +10,8 @@ library's autotuner (kf_autotune, untimed) and the whole launch sequence is
 captured once in a HIP graph (kf_plan_create) that every step replays.
 Prints one JSON line.  Besides the FP64 headline it times the
 mixed-precision fit, the same fit with the two-filter smoother (a backward
-Kalman filter, i.e. a second propagation, instead of RTS), a fit + adjoint
+Kalman filter, i.e. a second propagation, instead of RTS), the fit with the
+fitted parameters given at the perigee, a fit + adjoint
 step (kf_fit_tracks then kf_fit_tracks_vjp with chi2, smoothed-parameter and
 target cotangents) and the fit from pinned host buffers (PCIe included).
 
@@ -126,6 +127,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the fit + adjoint leg")
     ap.add_argument("--no-two-filter", action="store_true", help="skip the two-filter smoother leg")
+    ap.add_argument("--no-perigee", action="store_true", help="skip the perigee-target leg")
     ap.add_argument("--no-staged", action="store_true",
                     help="skip the host-buffer leg (copies in, fit, copies out, chunked over streams)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -204,6 +206,19 @@ def main():
                       "what": "filter + two-filter smoother (backward filter from the last hit, "
                               "combined with the forward filter), FP64"}
         del plant
+
+    perigee = None
+    if not args.no_perigee:
+        # fitted parameters at the perigee of the z axis instead of the seed
+        # plane: one more FP64 propagation per track after the smoother
+        planp, _ = prepared_plan(kfmi.KF_PREC_FP64, target=kfmi.KF_TARGET_PERIGEE, perigee=(0.0, 0.0, 0.0))
+        msp, kmsp, _ = time_plan(planp, args.steps, args.warmup)
+        perigee = {"value": N / (msp * 1e-3), "unit": "tracks/s", "ms_per_step": msp, "launch_ms": kmsp,
+                   "extra_ms": msp - ms64,
+                   "tracks_ok": int((planp.out.status.cpu().numpy() == 0).sum()),
+                   "what": "filter + RTS smoother + propagation of the fitted state to the perigee of the "
+                           "z axis, FP64"}
+        del planp
 
     staged = None
     if not args.no_staged:
@@ -306,6 +321,7 @@ def main():
         "mixed": mixed,
         "adjoint": adjoint,
         "two_filter": two_filter,
+        "perigee": perigee,
         "staged": staged,
         "roofline": roofline,
         "cpu_baseline": cpu,

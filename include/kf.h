@@ -91,6 +91,9 @@ extern "C" {
                                      propagating against the direction of flight, combined with the
                                      forward filter (Sect. 2, Fig. 2) */
 
+#define KF_TARGET_SEED_SURFACE 0  /* tgt_par / tgt_cov on the seed surface */
+#define KF_TARGET_PERIGEE 1       /* tgt_par / tgt_cov at the perigee of a line parallel to z */
+
 #define KF_MAX_SURFACES 512     /* the surface table is staged in LDS (13 doubles each) */
 #define KF_MAX_HITS 64         /* per track */
 
@@ -159,6 +162,16 @@ typedef struct {
     double bwd_scale;            /* TWO_FILTER: inflation of the backward filter's starting covariance
                                     (> 1; 0 = 1e3).  Its information, 1/bwd_scale of the last
                                     filtered state's, counts twice in the combination */
+    int32_t target;              /* KF_TARGET_*.  PERIGEE (Sect. 2; Sect. 5.2): the fitted state on
+                                    the seed surface is propagated (FP64, whatever the precision) to
+                                    the closest approach to the line through `perigee` parallel to
+                                    z and given as (d0, z0, phi, theta, q/p, t): d0 = (r - c) . u with
+                                    u = (-sin phi, cos phi, 0), z0 = r_z - c_z; the covariance goes
+                                    with that transport's Jacobian.  A track whose perigee is not
+                                    reached (|T_perp| too small, or more than max_steps trials) gets
+                                    KF_ST_NO_INTERSECT / KF_ST_STEP_CAP and NaN outputs.
+                                    kf_fit_tracks_vjp supports the seed surface only */
+    double perigee[3];           /* PERIGEE: a point c of the line (mm) */
 } kf_config;
 
 typedef struct {

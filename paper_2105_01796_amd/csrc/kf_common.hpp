@@ -386,6 +386,10 @@ inline int validate_inputs(const kf_config* cfg, const kf_surfaces* surf, const 
     if (cfg->smoother == KF_SMOOTHER_TWO_FILTER &&
         (cfg->split_smoother || !(cfg->bwd_scale == 0.0 || (cfg->bwd_scale > 1.0 && isfinite(cfg->bwd_scale)))))
         return KF_E_VALUE;
+    if (cfg->target != KF_TARGET_SEED_SURFACE && cfg->target != KF_TARGET_PERIGEE) return KF_E_VALUE;
+    if (cfg->target == KF_TARGET_PERIGEE &&
+        !(isfinite(cfg->perigee[0]) && isfinite(cfg->perigee[1]) && isfinite(cfg->perigee[2])))
+        return KF_E_VALUE;
     if (!(cfg->rk_tol > 0.0) || !(cfg->land_tol > 0.0) || !(cfg->mass >= 0.0) || cfg->max_steps < 1)
         return KF_E_VALUE;
     if (!isfinite(field->b0[0]) || !isfinite(field->b0[1]) || !isfinite(field->b0[2]) || !isfinite(field->a))

@@ -443,6 +443,140 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
 }
 
 // ---------------------------------------------------------------------------
+// bound state on plane a -> perigee of the line through c parallel to z
+// (Sect. 2; Sect. 5.2 quotes the fitted parameters there), in FP64.  The
+// distance to go is the Newton step d = -g/g' of the constraint
+// g = (r - c)_perp . T_perp, g' = |T_perp|^2 + (r - c)_perp . T'_perp (a
+// closest approach needs g' > 0), with the plane transport's step control;
+// land when |d| < land_tol, then move d to second order.  Bound parameters
+// (d0, z0, phi, theta, q/p, t): d0 = (r - c) . u, u = (-T_y, T_x, 0)/|T_perp|,
+// z0 = r_z - c_z.  F (25 stored entries) carries the path correction that
+// moves a variation back onto g = 0 along dF/ds.
+// ---------------------------------------------------------------------------
+template <int FK>
+__device__ inline int transport_perigee(const FieldDef& fd, const Cfg& cfg, const double* __restrict__ sa,
+                                        const double c[3], const double x[6], double xp[6], double F[25],
+                                        int* trials_out) {
+    using R = double;
+    Field<R, FK> fl;
+    fl.init(fd);
+    R sp, cp, st, ct;
+    angle_sincos(x[2], &sp, &cp);
+    angle_sincos(x[3], &st, &ct);
+    R r[3], T[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r[i] = sa[i] + x[0] * sa[3 + 3 * i + 0] + x[1] * sa[3 + 3 * i + 1];
+    T[0] = cp * st; T[1] = sp * st; T[2] = ct;
+    const R lam = x[4];
+    const R lk = lam * kKappa;
+    const R gd = sqrt(1.0 + cfg.mass * cfg.mass * lam * lam) / kC;
+    const R gpd = cfg.mass * cfg.mass * lam / (kC * kC * gd);
+    R Mr[3][5], MT[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) { Mr[i][j] = 0.0; MT[i][j] = 0.0; }
+        if (TangentCols<FK>::J0 == 0) {
+            Mr[i][0] = sa[3 + 3 * i + 0];
+            Mr[i][1] = sa[3 + 3 * i + 1];
+        }
+    }
+    MT[0][2] = -(sp * st); MT[1][2] = cp * st; MT[2][2] = 0.0;
+    MT[0][3] = cp * ct;    MT[1][3] = sp * ct; MT[2][3] = -st;
+    R Mtl = 0.0, t = x[5], hmag = -1.0;
+    int trials = 0, status = ST_OK;
+    Stages<R, FK> S;
+    for (;;) {
+        R B[3], TB[3];
+        fl.eval(r, B);
+        cross(T, B, TB);
+        const R dx = r[0] - c[0], dy = r[1] - c[1];
+        const R g = dx * T[0] + dy * T[1];
+        const R gp = T[0] * T[0] + T[1] * T[1] + lk * (dx * TB[0] + dy * TB[1]);
+        if (!(gp > 1e-6)) { status = ST_NO_INTERSECT; break; }
+        const R d = -g / gp;
+        if (::fabs(d) < cfg.land_tol) break;
+        if (trials >= cfg.max_steps) { status = ST_STEP_CAP; break; }
+        if (hmag < 0.0) hmag = ::fabs(d);
+        const R h = (::fabs(d) <= hmag) ? d : ::copysign(hmag, d);
+        R k[4][3];
+        const R err = rkn_trial<R, FK>(fl, r, T, lam, h, S, k);
+        ++trials;
+        phase_boundary();
+        R fac = 0.9 * sqrt(sqrt(cfg.tol / (err > 1e-300 ? err : 1e-300)));
+        fac = fac < 0.25 ? 0.25 : (fac > 4.0 ? 4.0 : fac);
+        if (err <= cfg.tol) {
+            rkn_tangent<R, FK>(fl, S, k, lam, h, Mr, MT);
+            phase_boundary();
+            Mtl = Mtl + h * gpd;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                r[i] = r[i] + h * T[i] + h * h * (1.0 / 6.0) * (k[0][i] + k[1][i] + k[2][i]);
+                T[i] = T[i] + h * (1.0 / 6.0) * (k[0][i] + 2.0 * k[1][i] + 2.0 * k[2][i] + k[3][i]);
+            }
+            t = t + h * gd;
+        }
+        hmag = ::fabs(h) * fac;
+    }
+    *trials_out = trials;
+    if (status != ST_OK) return status;
+    {
+        R B[3], TB[3];
+        fl.eval(r, B);
+        cross(T, B, TB);
+        const R dx = r[0] - c[0], dy = r[1] - c[1];
+        const R gp = T[0] * T[0] + T[1] * T[1] + lk * (dx * TB[0] + dy * TB[1]);
+        const R d = -(dx * T[0] + dy * T[1]) / gp;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            r[i] = r[i] + d * T[i] + 0.5 * d * d * lk * TB[i];
+            T[i] = T[i] + d * lk * TB[i];
+        }
+        t = t + d * gd;
+    }
+    R B[3], TB[3];
+    fl.eval(r, B);
+    cross(T, B, TB);
+    const R Tp[3] = {lk * TB[0], lk * TB[1], lk * TB[2]};
+    const R dx = r[0] - c[0], dy = r[1] - c[1];
+    const R gp = T[0] * T[0] + T[1] * T[1] + dx * Tp[0] + dy * Tp[1];
+    const R rho2 = T[0] * T[0] + T[1] * T[1];
+    const R rho = sqrt(rho2);
+    const R n2 = rho2 + T[2] * T[2];
+    const R ux = -T[1] / rho, uy = T[0] / rho;
+    const R gperp = dx * T[0] + dy * T[1];
+    xp[0] = dx * ux + dy * uy;
+    xp[1] = r[2] - c[2];
+    xp[2] = atan2(T[1], T[0]);
+    xp[3] = atan2(rho, T[2]);
+    xp[4] = lam;
+    xp[5] = t;
+    const R igp = 1.0 / gp, ip = 1.0 / rho2, ith = 1.0 / (rho * n2), in2 = 1.0 / n2, ir3 = gperp / (rho2 * rho);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const bool fixed = j < TangentCols<FK>::J0;
+        R mr[3], mt[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            mr[i] = fixed ? R(sa[3 + 3 * i + j]) : Mr[i][j];
+            mt[i] = fixed ? R(0.0) : MT[i][j];
+        }
+        const R sc = (T[0] * mr[0] + T[1] * mr[1] + dx * mt[0] + dy * mt[1]) * igp;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            mr[i] = mr[i] - T[i] * sc;
+            mt[i] = mt[i] - Tp[i] * sc;
+        }
+        F[0 * 5 + j] = ux * mr[0] + uy * mr[1] + (T[1] * mt[0] - T[0] * mt[1]) * ir3;
+        F[1 * 5 + j] = mr[2];
+        F[2 * 5 + j] = (T[0] * mt[1] - T[1] * mt[0]) * ip;
+        F[3 * 5 + j] = T[2] * (T[0] * mt[0] + T[1] * mt[1]) * ith - rho * mt[2] * in2;
+        F[4 * 5 + j] = (j == 4 ? Mtl : R(0.0)) - gd * sc;
+    }
+    return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
 // thin-scatterer noise on surface s for the filtered state x (PDG Highland)
 // Q = diag(0, 0, theta0^2 / sin^2(theta), theta0^2, 0, 0)
 // ---------------------------------------------------------------------------

@@ -88,6 +88,7 @@ struct FitArgs {
     int32_t* tile_counter;      // SORTED queue heads: [0] forward pass, [1] backward pass
     int n_tiles;
     double bwd_scale;           // two-filter smoother: inflation of the backward filter's start
+    double perigee[3];          // perigee target: a point of the line (parallel to z)
 };
 
 // Forward filter of the track held by workspace slot `slot` (track index t):
@@ -583,6 +584,52 @@ k_bwd(FitArgs a) {
     }
 }
 
+// Perigee target: one lane per track carries the fitted state on the seed
+// surface (tgt_*) to the perigee of the line through a.perigee parallel to z
+// and replaces it there, covariance C <- F C F^T.  A track that does not
+// reach it fails: status and NaN outputs.
+template <int FK>
+__global__ void __launch_bounds__(256) k_perigee(FitArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n_tracks || a.status[t] != ST_OK) return;
+    const int64_t N = a.n_tracks;
+    const int S = a.n_surf, s0 = a.seed_sid;
+    double sv[SURF_STRIDE];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) sv[f] = a.center[f * S + s0];
+#pragma unroll
+    for (int f = 0; f < 9; ++f) sv[3 + f] = a.rot[f * S + s0];
+    sv[12] = a.x0[s0];
+    if (a.align) {
+        double al[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) al[c] = a.align[c * S + s0];
+        apply_alignment(al, sv);
+    }
+    double x[6], C[21], xp[6], F[25], Cp[21];
+    load_rows(a.tgt_par + t, N, x);
+    load_rows(a.tgt_cov + t, N, C);
+    int tr = 0;
+    const int st = transport_perigee<FK>(a.field, a.cfg, sv, a.perigee, x, xp, F, &tr);
+    if (st == ST_OK) {
+        transport_cov(F, C, Cp);
+        store_rows(a.tgt_par + t, N, xp);
+        store_rows(a.tgt_cov + t, N, Cp);
+        return;
+    }
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    const int64_t H = a.n_hits;
+    const int o = a.off[t], n = a.off[t + 1] - o;
+    for (int k = 0; k < n; ++k) {
+        fill_rows<6>(a.par + o + k, H, nan);
+        fill_rows<21>(a.pcov + o + k, H, nan);
+    }
+    fill_rows<6>(a.tgt_par + t, N, nan);
+    fill_rows<21>(a.tgt_cov + t, N, nan);
+    a.chi2[t] = nan;
+    a.status[t] = (uint8_t)st;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -695,6 +742,7 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     a.tile_doubles = (cfg->jacobians == KF_JAC_RECOMPUTE || twof) ? (int64_t)meas->max_hits * NC_RECOMPUTE * TILE
                                                                   : L.tile_doubles;
     a.bwd_scale = cfg->bwd_scale > 0.0 ? cfg->bwd_scale : 1e3;
+    for (int i = 0; i < 3; ++i) a.perigee[i] = cfg->perigee[i];
     a.off = meas->hit_offsets;
     a.sid = meas->surface_id;
     a.loc = meas->loc;
@@ -745,6 +793,14 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
         e = mixed ? launch_fit<float, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, twof, stream)
                   : launch_fit<double, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, twof, stream);
     if (e == hipErrorInvalidValue) return KF_E_VALUE;     // workgroup needs more LDS than the device has
+    if (e == hipSuccess && cfg->target == KF_TARGET_PERIGEE) {
+        const dim3 grid((unsigned)((a.n_tracks + 255) / 256));
+        if (field->kind == KF_FIELD_UNIFORM)
+            hipLaunchKernelGGL(k_perigee<FIELD_UNIFORM>, grid, dim3(256), 0, stream, a);
+        else
+            hipLaunchKernelGGL(k_perigee<FIELD_SOLENOID>, grid, dim3(256), 0, stream, a);
+        e = hipGetLastError();
+    }
     return e == hipSuccess ? KF_OK : KF_E_HIP;
 }
 

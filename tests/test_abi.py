@@ -106,6 +106,13 @@ def test_argument_validation(kf):
         assert _call(kf, *a) == kf.KF_E_VALUE, bad
     cfg.bwd_scale = 0.0
     cfg.smoother = kf.KF_SMOOTHER_RTS
+    cfg.target = 2
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.target = kf.KF_TARGET_PERIGEE
+    cfg.perigee[1] = float("nan")
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.perigee[1] = 0.0
+    cfg.target = kf.KF_TARGET_SEED_SURFACE
     fld.b0[2] = float("nan")
     assert _call(kf, *a) == kf.KF_E_VALUE
     fld.b0[2] = 2.0
@@ -184,6 +191,9 @@ def test_vjp_argument_validation(kf):
     cfg.smoother = kf.KF_SMOOTHER_TWO_FILTER    # the adjoint is that of the RTS fit
     assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_VALUE
     cfg.smoother = kf.KF_SMOOTHER_RTS
+    cfg.target = kf.KF_TARGET_PERIGEE           # ... ending on the seed surface
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_VALUE
+    cfg.target = kf.KF_TARGET_SEED_SURFACE
     surf.n = kf.KF_MAX_SURFACES + 1
     assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad, nbytes=1 << 40) == kf.KF_E_SIZE
     surf.n = 11
