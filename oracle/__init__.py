@@ -68,6 +68,10 @@ def lib():
         L.kfo_linear_two_filter.restype = i
         L.kfo_ms_noise.argtypes = [i, P, P, P, i, P, d, P]
         L.kfo_ms_noise.restype = i
+        L.kfo_field_at.argtypes = [i, P, d, P, P, P]
+        L.kfo_field_at.restype = None
+        L.kfo_set_field_map.argtypes = [P, P, P, P]
+        L.kfo_set_field_map.restype = i
         L.kfo_version.restype = C.c_char_p
         _lib = L
     return _lib
@@ -75,6 +79,24 @@ def lib():
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+_map_keep = []
+
+
+def _use_field(field):
+    """Hand a tabulated field (kind 2) to the library before a call."""
+    if int(field.kind) != 2:
+        return
+    vals = np.ascontiguousarray(field.map_values, dtype=np.float64)
+    nz, ny, nx, three = vals.shape
+    assert three == 3
+    n = np.array([nx, ny, nz], dtype=np.int32)
+    o = np.asarray(field.map_origin, dtype=np.float64)
+    h = np.asarray(field.map_spacing, dtype=np.float64)
+    _map_keep[:] = [vals, n, o, h]
+    if lib().kfo_set_field_map(_p(n), _p(o), _p(h), _p(vals)):
+        raise ValueError("bad field map")
 
 
 def _f64(a):
@@ -107,6 +129,7 @@ class _Args:
     def __init__(self, ev, detector=None, ms=None, mass=None, tol=DEFAULT_TOL, land_tol=DEFAULT_LAND_TOL,
                  max_steps=DEFAULT_MAX_STEPS, loc=None, seed_par=None, align=None):
         det = detector if detector is not None else ev.detector
+        _use_field(ev.field)
         self.keep = dict(
             off=_i32(ev.hit_offsets), sid=_i32(ev.surface_id), loc=_f64(ev.loc if loc is None else loc),
             cov=_f64(ev.cov), center=_f64(det.center), rot=_f64(det.rot), x0=_f64(det.x_over_X0),
@@ -182,6 +205,7 @@ def count_ops(ev, **kw) -> np.ndarray:
 def transport(det, field, sa, sb, x, mass=0.1056583755, tol=DEFAULT_TOL, land_tol=DEFAULT_LAND_TOL,
               max_steps=DEFAULT_MAX_STEPS):
     """Bound state x on surface sa -> (status, x' on sb, F = dx'/dx (6,6), trials)."""
+    _use_field(field)
     center, rot, x0 = _f64(det.center), _f64(det.rot), _f64(det.x_over_X0)
     b0 = _f64(field.b0)
     xi = _f64(x)
@@ -198,6 +222,7 @@ def transport_perigee(det, field, sa, c, x, mass=0.1056583755, tol=DEFAULT_TOL, 
                       max_steps=DEFAULT_MAX_STEPS):
     """Bound state x on plane sa -> (status, perigee parameters (d0, z0, phi,
     theta, q/p, t) w.r.t. the line through c parallel to z, F (6,6), trials)."""
+    _use_field(field)
     center, rot, x0 = _f64(det.center), _f64(det.rot), _f64(det.x_over_X0)
     b0, cc, xi = _f64(field.b0), _f64(c), _f64(x)
     xo = np.empty(6)
@@ -211,12 +236,22 @@ def transport_perigee(det, field, sa, c, x, mass=0.1056583755, tol=DEFAULT_TOL, 
 
 def rkn_step(field, F, h, mass=0.1056583755):
     """One RKN step of the free state (x,y,z,t,Tx,Ty,Tz,q/p) -> (F', D (8,8), err)."""
+    _use_field(field)
     b0 = _f64(field.b0)
     Fi = _f64(F)
     Fn = np.empty(8)
     D = np.empty((8, 8))
     e = lib().kfo_rkn_step(int(field.kind), _p(b0), float(field.a), float(mass), _p(Fi), float(h), _p(Fn), _p(D))
     return Fn, D, e
+
+
+def field_at(field, r):
+    """(B (3,), dB/dr (3,3)) of the oracle's field at r."""
+    _use_field(field)
+    b0, rr = _f64(field.b0), _f64(r)
+    B, dB = np.empty(3), np.empty((3, 3))
+    lib().kfo_field_at(int(field.kind), _p(b0), float(field.a), _p(rr), _p(B), _p(dB))
+    return B, dB
 
 
 def linear_smoother(F, Q, m, V, x0, C0):

@@ -136,7 +136,10 @@ using std::sin; using std::cos; using std::sqrt; using std::log; using std::fabs
 // ---------------------------------------------------------------------------
 // problem description
 // ---------------------------------------------------------------------------
-struct FieldDef { int kind; double b0[3]; double a; };   // kind 0 uniform b0; 1: Bz=b0z(1-a z^2), Bx=a b0z x z, By=a b0z y z
+// tabulated field: values at origin + (i, j, k) * spacing, stored [k][j][i][3]
+struct FieldMap { int n[3]; double origin[3]; double spacing[3]; const double* values; };
+// kind 0 uniform b0; 1: Bz=b0z(1-a z^2), Bx=a b0z x z, By=a b0z y z; 2: the tabulated map
+struct FieldDef { int kind; double b0[3]; double a; const FieldMap* map = nullptr; };
 
 struct Cfg {
     int ms;            // apply multiple-scattering process noise
@@ -224,8 +227,50 @@ void chol_solve6(const S (&L)[6][6], const S (&B)[6][6], S (&X)[6][6]) {
 // ---------------------------------------------------------------------------
 // magnetic field and its gradient dB[a][b] = dB_a / dr_b
 // ---------------------------------------------------------------------------
+// Tabulated field (kind 2, the position-dependent field information of
+// Sect. 4.1 stored as a map): trilinear interpolation in the grid cell that
+// holds the point.  A coordinate outside the grid is clamped to the grid's
+// boundary, where the field is the boundary's and its derivative along that
+// axis is zero.
+template <class S>
+void map_field(const FieldMap& m, const S r[3], S B[3], S dB[3][3]) {
+    int idx[3];
+    S w1[3];
+    double dudx[3];
+    for (int a = 0; a < 3; ++a) {
+        S u = (r[a] - m.origin[a]) / m.spacing[a];
+        dudx[a] = 1.0 / m.spacing[a];
+        if (val(u) <= 0.0) { u = S(0.0); dudx[a] = 0.0; }
+        if (val(u) >= double(m.n[a] - 1)) { u = S(double(m.n[a] - 1)); dudx[a] = 0.0; }
+        int i = (int)std::floor(val(u));
+        if (i > m.n[a] - 2) i = m.n[a] - 2;
+        idx[a] = i;
+        w1[a] = u - double(i);
+    }
+    for (int c = 0; c < 3; ++c) { B[c] = 0.0; for (int a = 0; a < 3; ++a) dB[c][a] = 0.0; }
+    for (int dk = 0; dk < 2; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) {
+                const double* v = m.values + 3 * (((size_t)(idx[2] + dk) * m.n[1] + (idx[1] + dj)) * m.n[0]
+                                                   + (idx[0] + di));
+                S wx = di ? w1[0] : S(1.0) - w1[0];
+                S wy = dj ? w1[1] : S(1.0) - w1[1];
+                S wz = dk ? w1[2] : S(1.0) - w1[2];
+                double sx = di ? dudx[0] : -dudx[0];
+                double sy = dj ? dudx[1] : -dudx[1];
+                double sz = dk ? dudx[2] : -dudx[2];
+                for (int c = 0; c < 3; ++c) {
+                    B[c] = B[c] + wx * wy * wz * v[c];
+                    dB[c][0] = dB[c][0] + sx * wy * wz * v[c];
+                    dB[c][1] = dB[c][1] + wx * sy * wz * v[c];
+                    dB[c][2] = dB[c][2] + wx * wy * sz * v[c];
+                }
+            }
+}
+
 template <class S>
 void field_at(const FieldDef& f, const S r[3], S B[3], S dB[3][3]) {
+    if (f.kind == 2) { map_field(*f.map, r, B, dB); return; }
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) dB[i][j] = 0.0;
     if (f.kind == 0) {
         for (int i = 0; i < 3; ++i) B[i] = f.b0[i];
@@ -987,6 +1032,10 @@ inline bool field_nonzero(const FieldDef& f) {
 
 using namespace kfo;
 
+// The tabulated field that field kind 2 refers to (set by kfo_set_field_map;
+// the caller keeps the array alive while it is in use).
+static FieldMap g_map = {{0, 0, 0}, {0.0, 0.0, 0.0}, {1.0, 1.0, 1.0}, nullptr};
+
 static Inputs make_inputs(int n_tracks, const int32_t* off, const int32_t* sid, const double* loc,
                           const double* cov, int n_surf, const double* center, const double* rot,
                           const double* x0, const double* align, int field_kind, const double* b0,
@@ -997,6 +1046,7 @@ static Inputs make_inputs(int n_tracks, const int32_t* off, const int32_t* sid, 
     in.H = off ? off[n_tracks] : 0;
     in.n_surf = n_surf; in.center = center; in.rot = rot; in.x0 = x0; in.align = align;
     in.field.kind = field_kind;
+    in.field.map = &g_map;
     for (int i = 0; i < 3; ++i) in.field.b0[i] = b0[i];
     in.field.a = field_a;
     in.seed = seed; in.seed_cov = seed_cov; in.seed_sid = seed_sid;
@@ -1010,6 +1060,17 @@ static const int PACK_J[21] = {0,1,2,3,4,5,1,2,3,4,5,2,3,4,5,3,4,5,4,5,5};
 extern "C" {
 
 const char* kfo_version() { return "kf-oracle fp64 1"; }
+
+// The map of field kind 2: n[3] grid points per axis (>= 2), origin[3],
+// spacing[3] (mm), values [n2][n1][n0][3] (T), kept alive by the caller.
+int kfo_set_field_map(const int32_t* n, const double* origin, const double* spacing, const double* values) {
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] < 2 || !(spacing[a] > 0.0)) return 1;
+        g_map.n[a] = n[a]; g_map.origin[a] = origin[a]; g_map.spacing[a] = spacing[a];
+    }
+    g_map.values = values;
+    return 0;
+}
 
 // Full fit of every track.  Arrays are component-major ([component][item]).
 // Optional outputs may be NULL.  smoother: 0 RTS, 1 two-filter (bwd_scale:
@@ -1109,10 +1170,19 @@ int kfo_transport_perigee(int n_surf, const double* center, const double* rot, c
     return st;
 }
 
+// The field and its gradient dB[a][b] = dB_a/dr_b at r (kind 2: the map set
+// by kfo_set_field_map).
+void kfo_field_at(int field_kind, const double* b0, double field_a, const double* r, double* B, double* dB) {
+    FieldDef f; f.kind = field_kind; for (int i = 0; i < 3; ++i) f.b0[i] = b0[i]; f.a = field_a; f.map = &g_map;
+    double rr[3] = {r[0], r[1], r[2]}, Bo[3], dBo[3][3];
+    field_at(f, rr, Bo, dBo);
+    for (int i = 0; i < 3; ++i) { B[i] = Bo[i]; for (int j = 0; j < 3; ++j) dB[3 * i + j] = dBo[i][j]; }
+}
+
 // One RKN step of the free state at fixed h; D = d(step map)/dF.  Returns err.
 double kfo_rkn_step(int field_kind, const double* b0, double field_a, double mass, const double* F,
                     double h, double* Fn, double* D) {
-    FieldDef f; f.kind = field_kind; for (int i = 0; i < 3; ++i) f.b0[i] = b0[i]; f.a = field_a;
+    FieldDef f; f.kind = field_kind; for (int i = 0; i < 3; ++i) f.b0[i] = b0[i]; f.a = field_a; f.map = &g_map;
     double Fi[8], Fo[8], Dm[8][8];
     for (int i = 0; i < 8; ++i) Fi[i] = F[i];
     double e = rkn_step(f, mass, Fi, h, Fo, Dm);

@@ -37,6 +37,7 @@ SEED_SIGMA = (0.1, 0.1, 2e-3, 2e-3, 0.05, 1.0)   # l0, l1 [mm], phi, theta, rel 
 
 FIELD_UNIFORM = 0
 FIELD_SOLENOID = 1
+FIELD_MAP = 2
 
 PACK_IDX = [(i, j) for i in range(6) for j in range(i, 6)]   # 21 packed entries
 
@@ -60,9 +61,33 @@ class Field:
     kind: int = FIELD_UNIFORM
     b0: tuple = (0.0, 0.0, 2.0)   # T
     a: float = 0.0                # 1/mm^2, solenoid shape parameter
+    # FIELD_MAP: values at origin + (i, j, k) * spacing, array [nz][ny][nx][3] (T)
+    map_values: np.ndarray | None = None
+    map_origin: tuple = (0.0, 0.0, 0.0)
+    map_spacing: tuple = (1.0, 1.0, 1.0)
 
     def is_zero(self) -> bool:
         return self.kind == FIELD_UNIFORM and not any(self.b0)
+
+
+def analytic_field(field: Field, x, y, z):
+    """B of a uniform or solenoid-like field at arrays x, y, z -> (Bx, By, Bz)."""
+    if field.kind == FIELD_UNIFORM:
+        return tuple(np.full(np.shape(x), float(b)) for b in field.b0)
+    g = field.a * field.b0[2]
+    return g * x * z, g * y * z, field.b0[2] * (1.0 - field.a * z * z)
+
+
+def sample_field_map(field: Field, lo, hi, spacing) -> Field:
+    """A tabulated field (FIELD_MAP) holding `field` sampled on the grid from
+    lo to (at least) hi with the given spacing per axis."""
+    lo = np.asarray(lo, float)
+    sp = np.asarray(spacing, float)
+    n = np.ceil((np.asarray(hi, float) - lo) / sp).astype(int) + 1
+    ax = [lo[a] + sp[a] * np.arange(n[a]) for a in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    B = np.stack(analytic_field(field, X, Y, Z), axis=-1)
+    return Field(FIELD_MAP, tuple(field.b0), float(field.a), np.ascontiguousarray(B), tuple(lo), tuple(sp))
 
 
 @dataclass
@@ -416,7 +441,7 @@ def solenoid_event(n_tracks, seed, n_planes=30, b0z=2.0, a=1e-7, nmin=8, p_hole=
 # ----------------------------------------------------------------------------
 # named workloads
 # ----------------------------------------------------------------------------
-CONFIG_SEEDS = {1: 1001, 2: 1002, 3: 1003, 4: 1004, 5: 1005}
+CONFIG_SEEDS = {1: 1001, 2: 1002, 3: 1003, 4: 1004, 5: 1005, 6: 1005}
 
 
 def make_config(cfg: int, n_tracks: int | None = None, seed: int | None = None, **kw) -> Event:
@@ -427,6 +452,9 @@ def make_config(cfg: int, n_tracks: int | None = None, seed: int | None = None, 
     4: 1e5 tracks, 10 planes, 2 T, misaligned truth (10 um, 0.1 mrad).
     5: 1e6 tracks, 30 planes, solenoid field, pT log-uniform 0.5-100 GeV,
        |eta| < 2.5, ragged 8-30 hits over reachable planes.
+    6: the tracks of 5, fitted with the field given as a map: the solenoid
+       sampled every 25 mm over x -50..950, y -1000..1000, z -6000..6000 mm
+       (41 x 81 x 481 points, 38 MB).
     """
     seed = CONFIG_SEEDS[cfg] if seed is None else seed
     if cfg == 1:
@@ -439,4 +467,8 @@ def make_config(cfg: int, n_tracks: int | None = None, seed: int | None = None, 
         return telescope_event(n_tracks or 100_000, seed, misalign_sigma=(0.01, 1e-4), name="C4", **kw)
     if cfg == 5:
         return solenoid_event(n_tracks or 1_000_000, seed, name="C5", **kw)
+    if cfg == 6:
+        ev = solenoid_event(n_tracks or 1_000_000, seed, name="C6", **kw)
+        ev.field = sample_field_map(ev.field, (-50.0, -1000.0, -6000.0), (950.0, 1000.0, 6000.0), (25.0, 25.0, 25.0))
+        return ev
     raise ValueError(f"unknown config {cfg}")
