@@ -46,6 +46,8 @@ WORKLOADS = {
     3: "1e5 tracks, 30 planes x=30..900 mm, Bz=2 T, ragged 5-30 hits (holes p=0.1)",
     4: "1e5 tracks, 10 planes, Bz=2 T, misaligned truth",
     5: "solenoid B=2T(1-0.1(z/1m)^2), 30 planes, pT log-uniform 0.5-100 GeV, |eta|<2.5, ragged 8-30 hits",
+    6: "the tracks of C5 with the field as a map: the solenoid sampled every 25 mm (41x81x481 points, "
+       "38 MB), trilinear",
 }
 
 
@@ -245,7 +247,7 @@ def main():
                           "(PCIe-inclusive; not the headline value)"}
 
     adjoint = None
-    if not args.no_adjoint:
+    if not args.no_adjoint and int(ev.field.kind) != kfmi.KF_FIELD_MAP:   # the adjoint needs an analytic field
         rng_g = np.random.default_rng(1)
         g_chi2 = torch.ones(N, dtype=torch.float64, device=dev)
         g_par = torch.as_tensor(rng_g.standard_normal((6, ev.n_hits)), device=dev)

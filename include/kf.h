@@ -73,6 +73,7 @@ extern "C" {
 /* ---- enums ---- */
 #define KF_FIELD_UNIFORM 0     /* B = b0 everywhere */
 #define KF_FIELD_SOLENOID 1    /* Bz = b0[2] (1 - a z^2), Bx = a b0[2] x z, By = a b0[2] y z */
+#define KF_FIELD_MAP 2         /* tabulated: trilinear interpolation in kf_field.map */
 
 #define KF_PREC_FP64 0         /* every step in FP64 */
 #define KF_PREC_MIXED 1        /* RKN stepping and transport Jacobian in FP32 on increments
@@ -110,8 +111,20 @@ typedef struct {
 
 typedef struct {
     int32_t kind;              /* KF_FIELD_* */
-    double b0[3];              /* T */
+    double b0[3];              /* T (UNIFORM, SOLENOID) */
     double a;                  /* 1/mm^2, KF_FIELD_SOLENOID only */
+    /* KF_FIELD_MAP (Sect. 4.1: position-dependent field information kept in
+     * memory): B at the grid points map_origin + (i, j, k) * map_spacing,
+     * 0 <= i < map_n[0] etc. (each >= 2, spacing > 0), interpolated
+     * trilinearly in the cell that holds the point, with the interpolant's
+     * gradient for the transport Jacobian.  A coordinate outside the grid is
+     * clamped to its boundary (the field there is the boundary's; no
+     * gradient along that axis). */
+    int32_t map_n[3];
+    double map_origin[3];      /* mm */
+    double map_spacing[3];     /* mm */
+    const double *map;         /* device pointer, [map_n[2]][map_n[1]][map_n[0]][3] (Bx, By, Bz in T);
+                                  read by the kernels, owned by the caller */
 } kf_field;
 
 typedef struct {

@@ -375,7 +375,16 @@ inline int validate_inputs(const kf_config* cfg, const kf_surfaces* surf, const 
     if (cfg->precision != KF_PREC_FP64 && cfg->precision != KF_PREC_MIXED) return KF_E_ENUM;
     if (cfg->schedule != KF_SCHED_AUTO && cfg->schedule != KF_SCHED_DIRECT && cfg->schedule != KF_SCHED_SORTED)
         return KF_E_ENUM;
-    if (field->kind != KF_FIELD_UNIFORM && field->kind != KF_FIELD_SOLENOID) return KF_E_ENUM;
+    if (field->kind != KF_FIELD_UNIFORM && field->kind != KF_FIELD_SOLENOID && field->kind != KF_FIELD_MAP)
+        return KF_E_ENUM;
+    if (field->kind == KF_FIELD_MAP) {
+        if (!field->map) return KF_E_NULL;
+        for (int i = 0; i < 3; ++i)
+            if (field->map_n[i] < 2 || !(field->map_spacing[i] > 0.0) || !isfinite(field->map_spacing[i]) ||
+                !isfinite(field->map_origin[i]))
+                return KF_E_VALUE;
+        if ((double)field->map_n[0] * field->map_n[1] * field->map_n[2] > 2.0e9) return KF_E_SIZE;
+    }
     if (cfg->block != 0 && cfg->block != 64 && cfg->block != 128 && cfg->block != 256) return KF_E_VALUE;
     if (cfg->waves_per_cu < 0 || cfg->waves_per_cu > 32) return KF_E_VALUE;
     if (cfg->occupancy < 0 || cfg->occupancy > 3) return KF_E_VALUE;
@@ -410,6 +419,12 @@ inline FieldDef field_def(const kf_field* field) {
     f.kind = field->kind;
     for (int i = 0; i < 3; ++i) f.b0[i] = field->b0[i];
     f.a = field->a;
+    f.map = field->kind == KF_FIELD_MAP ? field->map : nullptr;
+    for (int i = 0; i < 3; ++i) {
+        f.mo[i] = field->map_origin[i];
+        f.mih[i] = field->kind == KF_FIELD_MAP ? 1.0 / field->map_spacing[i] : 0.0;
+        f.mn[i] = field->map_n[i];
+    }
     return f;
 }
 

@@ -21,7 +21,7 @@ constexpr double kKappa = 0.299792458e-3; // curvature per (q/p) per tesla, 1/mm
 constexpr double kPi = 3.141592653589793238462643383279502884;
 
 enum : int { ST_OK = 0, ST_NO_INTERSECT = 1, ST_STEP_CAP = 2, ST_NOT_SPD = 3, ST_BAD_INPUT = 4, ST_TOO_FEW = 5 };
-enum : int { FIELD_UNIFORM = 0, FIELD_SOLENOID = 1 };
+enum : int { FIELD_UNIFORM = 0, FIELD_SOLENOID = 1, FIELD_MAP = 2 };
 
 // packed index of symmetric 6x6 element (i, j): upper triangle, row-major
 __host__ __device__ constexpr int sy(int i, int j) {
@@ -38,6 +38,11 @@ struct FieldDef {
     int kind;
     double b0[3];
     double a;
+    // FIELD_MAP: grid points mo + (i, j, k) / mih, mn per axis, values [k][j][i][3]
+    const double* map;
+    double mo[3];
+    double mih[3];    // 1 / spacing
+    int mn[3];
 };
 
 struct Cfg {
@@ -156,6 +161,72 @@ struct Field {
     }
 };
 
+// Tabulated field: trilinear interpolation in the grid cell holding r; a
+// coordinate outside the grid is clamped to the boundary (no gradient along
+// that axis).  The cell index and weights are formed in FP64 from the
+// position, the corner values are read from global memory (the map is shared
+// by every lane and stays in the caches).
+template <class P>
+struct Field<P, FIELD_MAP> {
+    const double* m;
+    double mo[3], mih[3];
+    int mn[3];
+    __device__ void init(const FieldDef& f) {
+        m = f.map;
+        for (int i = 0; i < 3; ++i) { mo[i] = f.mo[i]; mih[i] = f.mih[i]; mn[i] = f.mn[i]; }
+    }
+    // the cell (base index of its low corner) and the weights w1 (fraction
+    // across the cell) and dw (d w1 / dr, zero where clamped) along each axis
+    __device__ inline int64_t cell(const P r[3], P w1[3], P dw[3]) const {
+        int idx[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double u = (double(r[a]) - mo[a]) * mih[a];
+            double du = mih[a];
+            const double top = double(mn[a] - 1);
+            if (u <= 0.0) { u = 0.0; du = 0.0; }
+            if (u >= top) { u = top; du = 0.0; }
+            int i = (int)floor(u);
+            i = i > mn[a] - 2 ? mn[a] - 2 : i;
+            idx[a] = i;
+            w1[a] = P(u - double(i));
+            dw[a] = P(du);
+        }
+        return 3 * (((int64_t)idx[2] * mn[1] + idx[1]) * mn[0] + idx[0]);
+    }
+    __device__ inline void eval(const P r[3], P B[3]) const {
+        P w1[3], dw[3];
+        const auto c = gbl(m) + cell(r, w1, dw);
+        const int64_t sy = 3 * (int64_t)mn[0], sz = sy * mn[1];
+        B[0] = B[1] = B[2] = P(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int di = k & 1, dj = (k >> 1) & 1, dk = k >> 2;
+            const P w = (di ? w1[0] : P(1) - w1[0]) * (dj ? w1[1] : P(1) - w1[1]) * (dk ? w1[2] : P(1) - w1[2]);
+            const auto v = c + dk * sz + dj * sy + 3 * di;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) B[q] += w * P(v[q]);
+        }
+    }
+    __device__ inline void grad_apply(const P r[3], const P v3[3], P o[3]) const {
+        P w1[3], dw[3];
+        const auto c = gbl(m) + cell(r, w1, dw);
+        const int64_t sy = 3 * (int64_t)mn[0], sz = sy * mn[1];
+        o[0] = o[1] = o[2] = P(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int di = k & 1, dj = (k >> 1) & 1, dk = k >> 2;
+            const P wx = di ? w1[0] : P(1) - w1[0], wy = dj ? w1[1] : P(1) - w1[1], wz = dk ? w1[2] : P(1) - w1[2];
+            const P sx = di ? dw[0] : -dw[0], sy_ = dj ? dw[1] : -dw[1], sz_ = dk ? dw[2] : -dw[2];
+            // d(weight)/dr . v
+            const P dwv = sx * wy * wz * v3[0] + wx * sy_ * wz * v3[1] + wx * wy * sz_ * v3[2];
+            const auto v = c + dk * sz + dj * sy + 3 * di;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) o[q] += dwv * P(v[q]);
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // one Runge-Kutta-Nystrom trial step (Sect. 4.1), state on an FP64 anchor:
 //   position r = r0 + dr, direction T = T0 + dT, time t = t0 + dt
@@ -217,7 +288,7 @@ __device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& 
                                    P Mr[3][5], P MT[3][5]) {
     const P h2 = h * P(0.5), hh = h * h, lk = lam * P(kKappa), ilam = P(1) / lam;
     P LB[3];
-    if (FK == FIELD_UNIFORM) {
+    if constexpr (FK == FIELD_UNIFORM) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) LB[i] = lk * fl.b[i];
     }

@@ -789,16 +789,21 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     if (field->kind == KF_FIELD_UNIFORM)
         e = mixed ? launch_fit<float, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, storef, twof, stream)
                   : launch_fit<double, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, storef, twof, stream);
-    else
+    else if (field->kind == KF_FIELD_SOLENOID)
         e = mixed ? launch_fit<float, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, twof, stream)
                   : launch_fit<double, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, twof, stream);
+    else
+        e = mixed ? launch_fit<float, FIELD_MAP>(a, sched, block, wpc, occ, split, storef, twof, stream)
+                  : launch_fit<double, FIELD_MAP>(a, sched, block, wpc, occ, split, storef, twof, stream);
     if (e == hipErrorInvalidValue) return KF_E_VALUE;     // workgroup needs more LDS than the device has
     if (e == hipSuccess && cfg->target == KF_TARGET_PERIGEE) {
         const dim3 grid((unsigned)((a.n_tracks + 255) / 256));
         if (field->kind == KF_FIELD_UNIFORM)
             hipLaunchKernelGGL(k_perigee<FIELD_UNIFORM>, grid, dim3(256), 0, stream, a);
-        else
+        else if (field->kind == KF_FIELD_SOLENOID)
             hipLaunchKernelGGL(k_perigee<FIELD_SOLENOID>, grid, dim3(256), 0, stream, a);
+        else
+            hipLaunchKernelGGL(k_perigee<FIELD_MAP>, grid, dim3(256), 0, stream, a);
         e = hipGetLastError();
     }
     return e == hipSuccess ? KF_OK : KF_E_HIP;

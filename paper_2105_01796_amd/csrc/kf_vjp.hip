@@ -670,6 +670,7 @@ int kf_fit_tracks_vjp(const kf_config* cfg, const kf_surfaces* surf, const kf_fi
     if (rc != KF_OK) return rc;
     if (cfg->smoother != KF_SMOOTHER_RTS) return KF_E_VALUE;     // the reverse pass is that of RTS
     if (cfg->target != KF_TARGET_SEED_SURFACE) return KF_E_VALUE;  // ... ending on the seed surface
+    if (field->kind == KF_FIELD_MAP) return KF_E_VALUE;            // analytic fields only
     if (meas->n_hits > 0 && !grad->meas) return KF_E_NULL;
     const VjpLayout L = vjp_layout(meas->n_tracks, meas->n_hits, meas->max_hits, surf->n);
     if (!workspace) return KF_E_WS;

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_PKG, "libkfmi.so")
 # ---- constants (include/kf.h) ----
 KF_OK, KF_E_NULL, KF_E_SIZE, KF_E_ENUM, KF_E_WS, KF_E_HIP, KF_E_VALUE = 0, -1, -2, -3, -4, -5, -6
 KF_ST_OK, KF_ST_NO_INTERSECT, KF_ST_STEP_CAP, KF_ST_NOT_SPD, KF_ST_BAD_INPUT, KF_ST_TOO_FEW = range(6)
-KF_FIELD_UNIFORM, KF_FIELD_SOLENOID = 0, 1
+KF_FIELD_UNIFORM, KF_FIELD_SOLENOID, KF_FIELD_MAP = 0, 1, 2
 KF_PREC_FP64, KF_PREC_MIXED = 0, 1
 KF_SCHED_AUTO, KF_SCHED_DIRECT, KF_SCHED_SORTED = 0, 1, 2
 KF_JAC_STORE, KF_JAC_RECOMPUTE = 0, 1
@@ -38,7 +38,8 @@ class kf_surfaces(C.Structure):
 
 
 class kf_field(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("b0", C.c_double * 3), ("a", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("b0", C.c_double * 3), ("a", C.c_double), ("map_n", C.c_int32 * 3),
+                ("map_origin", C.c_double * 3), ("map_spacing", C.c_double * 3), ("map", C.c_void_p)]
 
 
 class kf_measurements(C.Structure):
@@ -161,6 +162,9 @@ class Batch:
     mass: float = 0.1056583755
     max_hits: int = 0             # 0: computed from hit_offsets
     align: torch.Tensor | None = None   # (6, S) f64 alignment corrections, or None
+    field_map: torch.Tensor | None = None   # KF_FIELD_MAP: (nz, ny, nx, 3) f64 on the device
+    map_origin: tuple = (0.0, 0.0, 0.0)
+    map_spacing: tuple = (1.0, 1.0, 1.0)
 
     @property
     def n_tracks(self) -> int:
@@ -192,7 +196,10 @@ class Batch:
                    field_kind=int(ev.field.kind), b0=tuple(float(b) for b in ev.field.b0),
                    field_a=float(ev.field.a), multiple_scattering=bool(ev.multiple_scattering),
                    mass=float(ev.mass), max_hits=int(max(counts)) if len(counts) else 1,
-                   align=None if align is None else _dev(align, f64, device))
+                   align=None if align is None else _dev(align, f64, device),
+                   field_map=None if int(ev.field.kind) != KF_FIELD_MAP else _dev(ev.field.map_values, f64, device),
+                   map_origin=tuple(float(v) for v in getattr(ev.field, "map_origin", (0.0, 0.0, 0.0))),
+                   map_spacing=tuple(float(v) for v in getattr(ev.field, "map_spacing", (1.0, 1.0, 1.0))))
 
 
 @dataclass
@@ -242,7 +249,14 @@ def _structs(b: Batch, opt: Options):
     if b.align is not None and tuple(b.align.shape) != (6, b.center.shape[1]):
         raise ValueError("align must have shape (6, S)")
     surf = kf_surfaces(b.center.shape[1], _ptr(b.center), _ptr(b.rot), _ptr(b.x_over_X0), _ptr(b.align))
-    field = kf_field(b.field_kind, (C.c_double * 3)(*b.b0), b.field_a)
+    if b.field_kind == KF_FIELD_MAP:
+        if b.field_map is None or b.field_map.dim() != 4 or b.field_map.shape[3] != 3:
+            raise ValueError("field_map must have shape (nz, ny, nx, 3)")
+        nz, ny, nx, _ = b.field_map.shape
+        field = kf_field(b.field_kind, (C.c_double * 3)(*b.b0), b.field_a, (C.c_int32 * 3)(nx, ny, nz),
+                         (C.c_double * 3)(*b.map_origin), (C.c_double * 3)(*b.map_spacing), _ptr(b.field_map))
+    else:
+        field = kf_field(b.field_kind, (C.c_double * 3)(*b.b0), b.field_a)
     meas = kf_measurements(b.n_tracks, _max_hits(b), b.n_hits, _ptr(b.hit_offsets), _ptr(b.surface_id),
                            _ptr(b.loc), _ptr(b.cov))
     seeds = kf_seeds(_ptr(b.seed_par), _ptr(b.seed_cov), b.seed_surface)

@@ -113,6 +113,19 @@ def test_argument_validation(kf):
     assert _call(kf, *a) == kf.KF_E_VALUE
     cfg.perigee[1] = 0.0
     cfg.target = kf.KF_TARGET_SEED_SURFACE
+    # tabulated field: pointer, grid size and spacing are checked
+    fld.kind = kf.KF_FIELD_MAP
+    assert _call(kf, *a) == kf.KF_E_NULL
+    fld.map = C.c_void_p(0x3000)
+    assert _call(kf, *a) == kf.KF_E_VALUE           # map_n = 0
+    fld.map_n[0], fld.map_n[1], fld.map_n[2] = 4, 4, 1
+    fld.map_spacing[0] = fld.map_spacing[1] = fld.map_spacing[2] = 10.0
+    assert _call(kf, *a) == kf.KF_E_VALUE           # fewer than 2 points along z
+    fld.map_n[2] = 4
+    fld.map_spacing[1] = -1.0
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    fld.map_spacing[1] = 10.0
+    fld.kind = 0
     fld.b0[2] = float("nan")
     assert _call(kf, *a) == kf.KF_E_VALUE
     fld.b0[2] = 2.0
@@ -194,6 +207,12 @@ def test_vjp_argument_validation(kf):
     cfg.target = kf.KF_TARGET_PERIGEE           # ... ending on the seed surface
     assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_VALUE
     cfg.target = kf.KF_TARGET_SEED_SURFACE
+    fld.kind = kf.KF_FIELD_MAP                  # ... in an analytic field
+    fld.map = C.c_void_p(0x3000)
+    fld.map_n[0] = fld.map_n[1] = fld.map_n[2] = 4
+    fld.map_spacing[0] = fld.map_spacing[1] = fld.map_spacing[2] = 10.0
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_VALUE
+    fld.kind = 0
     surf.n = kf.KF_MAX_SURFACES + 1
     assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad, nbytes=1 << 40) == kf.KF_E_SIZE
     surf.n = 11
