@@ -208,6 +208,31 @@ struct Field<P, FIELD_MAP> {
             for (int q = 0; q < 3; ++q) B[q] += w * P(v[q]);
         }
     }
+    // the field and its gradient G[3 q + a] = dB_q/dr_a in one pass over the corners
+    __device__ inline void eval_grad(const P r[3], P B[3], P G[9]) const {
+        P w1[3], dw[3];
+        const auto c = gbl(m) + cell(r, w1, dw);
+        const int64_t sy = 3 * (int64_t)mn[0], sz = sy * mn[1];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) B[q] = P(0);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) G[q] = P(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int di = k & 1, dj = (k >> 1) & 1, dk = k >> 2;
+            const P wx = di ? w1[0] : P(1) - w1[0], wy = dj ? w1[1] : P(1) - w1[1], wz = dk ? w1[2] : P(1) - w1[2];
+            const P sx = di ? dw[0] : -dw[0], sy_ = dj ? dw[1] : -dw[1], sz_ = dk ? dw[2] : -dw[2];
+            const auto v = c + dk * sz + dj * sy + 3 * di;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const P vq = P(v[q]);
+                B[q] += wx * wy * wz * vq;
+                G[3 * q + 0] += sx * wy * wz * vq;
+                G[3 * q + 1] += wx * sy_ * wz * vq;
+                G[3 * q + 2] += wx * wy * sz_ * vq;
+            }
+        }
+    }
     __device__ inline void grad_apply(const P r[3], const P v3[3], P o[3]) const {
         P w1[3], dw[3];
         const auto c = gbl(m) + cell(r, w1, dw);
@@ -240,6 +265,18 @@ struct Stages {
     P r2[3];      // uniform: midpoint position (unused by the field)
 };
 
+// Map: the field gradient is kept per stage point instead of the position
+// (stages 2 and 3 share the midpoint, so three gradients), so the tangent
+// update does not read the map again.
+template <class P>
+struct Stages<P, FIELD_MAP> {
+    P T[4][3];
+    P B[4][3];
+    P G[3][9];    // dB_q/dr_a at the start, the midpoint and the end point
+    P r2[3];      // midpoint position
+};
+__host__ __device__ constexpr int stage_point(int st) { return st == 0 ? 0 : (st == 3 ? 2 : 1); }
+
 // Returns the error estimate h^2 |k1 - k2 - k3 + k4|_1; k receives the stage
 // accelerations k_i = (q/p) kappa T_i x B(r_i).
 template <class P, int FK>
@@ -254,11 +291,17 @@ __device__ inline P rkn_trial(const Field<P, FK>& fl, const P rabs[3], const P T
         for (int i = 0; i < 3; ++i) {
             if (st == 0) { rs[i] = rabs[i]; Ts[i] = T[i]; }
             else if (st == 1) { rs[i] = rabs[i] + h2 * T[i] + hh * P(0.125) * k[0][i]; Ts[i] = T[i] + h2 * k[0][i]; }
-            else if (st == 2) { rs[i] = (FK == FIELD_UNIFORM) ? S.r2[i] : S.r[1][i]; Ts[i] = T[i] + h2 * k[1][i]; }
+            else if (st == 2) {
+                if constexpr (FK == FIELD_SOLENOID) rs[i] = S.r[1][i]; else rs[i] = S.r2[i];
+                Ts[i] = T[i] + h2 * k[1][i];
+            }
             else { rs[i] = rabs[i] + h * T[i] + hh * P(0.5) * k[2][i]; Ts[i] = T[i] + h * k[2][i]; }
         }
-        if (FK == FIELD_UNIFORM) {
+        if constexpr (FK == FIELD_UNIFORM) {
             if (st == 0) fl.eval(rs, B);
+        } else if constexpr (FK == FIELD_MAP) {
+            // the third stage sits at the second one's point: same field and gradient
+            if (st != 2) fl.eval_grad(rs, B, S.G[stage_point(st)]);
         } else {
             fl.eval(rs, B);
         }
@@ -267,7 +310,8 @@ __device__ inline P rkn_trial(const Field<P, FK>& fl, const P rabs[3], const P T
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             k[st][i] = lk * c[i];
-            if (FK != FIELD_UNIFORM) { S.T[st][i] = Ts[i]; S.B[st][i] = B[i]; S.r[st][i] = rs[i]; }
+            if constexpr (FK == FIELD_SOLENOID) { S.T[st][i] = Ts[i]; S.B[st][i] = B[i]; S.r[st][i] = rs[i]; }
+            else if constexpr (FK == FIELD_MAP) { S.T[st][i] = Ts[i]; S.B[st][i] = B[i]; if (st == 1) S.r2[i] = rs[i]; }
             else if (st == 1) S.r2[i] = rs[i];
         }
     }
@@ -311,7 +355,13 @@ __device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& 
             } else {
                 P g[3], c2[3];
                 cross(dT, S.B[st], c);
-                fl.grad_apply(S.r[st], dr, g);
+                if constexpr (FK == FIELD_MAP) {
+                    const P* G = S.G[stage_point(st)];
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) g[q] = G[3 * q] * dr[0] + G[3 * q + 1] * dr[1] + G[3 * q + 2] * dr[2];
+                } else {
+                    fl.grad_apply(S.r[st], dr, g);
+                }
                 cross(S.T[st], g, c2);
 #pragma unroll
                 for (int i = 0; i < 3; ++i) c[i] = lk * (c[i] + c2[i]);
