@@ -242,7 +242,7 @@ void map_field(const FieldMap& m, const S r[3], S B[3], S dB[3][3]) {
         dudx[a] = 1.0 / m.spacing[a];
         if (val(u) <= 0.0) { u = S(0.0); dudx[a] = 0.0; }
         if (val(u) >= double(m.n[a] - 1)) { u = S(double(m.n[a] - 1)); dudx[a] = 0.0; }
-        int i = (int)std::floor(val(u));
+        int i = val(u) >= 0.0 ? (int)std::floor(val(u)) : 0;     // a NaN position reads cell 0
         if (i > m.n[a] - 2) i = m.n[a] - 2;
         idx[a] = i;
         w1[a] = u - double(i);

@@ -186,7 +186,7 @@ struct Field<P, FIELD_MAP> {
             const double top = double(mn[a] - 1);
             if (u <= 0.0) { u = 0.0; du = 0.0; }
             if (u >= top) { u = top; du = 0.0; }
-            int i = (int)floor(u);
+            int i = u >= 0.0 ? (int)floor(u) : 0;     // a NaN position reads cell 0 (in bounds)
             i = i > mn[a] - 2 ? mn[a] - 2 : i;
             idx[a] = i;
             w1[a] = P(u - double(i));
