@@ -28,9 +28,9 @@ def test_map_fp64_launch_shapes(kf):
     _announce("C6 (solenoid map) fp64 n=2000")
     ev = synth.make_config(6, 2000)
     ref = _ref(ev)
-    for sched, block, occ in ((1, 256, 1), (2, 64, 1), (2, 128, 2)):
-        out = _fit(kf, ev, schedule=sched, block=block, occupancy=occ)
-        compare(out, ref, tol=TOL[5], label=f"C6 sched {sched} block {block} occ {occ}")
+    for sched, block, occ, split in ((1, 256, 1, 0), (2, 64, 1, 0), (2, 128, 2, 0), (2, 64, 1, 1), (1, 256, 2, 1)):
+        out = _fit(kf, ev, schedule=sched, block=block, occupancy=occ, split_smoother=split)
+        compare(out, ref, tol=TOL[5], label=f"C6 sched {sched} block {block} occ {occ} split {split}")
 
 
 def test_map_with_other_options(kf):
