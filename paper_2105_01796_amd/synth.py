@@ -326,7 +326,7 @@ def _kinematics(rng, N, pt_range=(1.0, 10.0), pt_log=False, phi_max=0.1, eta_max
 
 def telescope_event(n_tracks, seed, n_planes=10, bz=2.0, x_over_X0=0.0, ms=False,
                     ragged=None, p_hole=0.1, f_inf=1.0, misalign_sigma=None,
-                    pt_range=(1.0, 10.0), phi_max=0.1, eta_max=0.2, name="telescope"):
+                    pt_range=(1.0, 10.0), phi_max=0.1, eta_max=0.2, name="telescope", pitch=30.0):
     """Uniform field along z (or no field), planes normal to x, exact helices.
 
     ragged=(nmin, nmax): hit count per track uniform in [nmin, nmax], hole
@@ -336,7 +336,7 @@ def telescope_event(n_tracks, seed, n_planes=10, bz=2.0, x_over_X0=0.0, ms=False
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     N, P = n_tracks, n_planes
-    det = telescope(P, x_over_X0=x_over_X0 if ms else 0.0)
+    det = telescope(P, pitch=pitch, x_over_X0=x_over_X0 if ms else 0.0)
     fld = Field(FIELD_UNIFORM, (0.0, 0.0, float(bz)), 0.0)
     q, p, phi, theta = _kinematics(rng, N, pt_range, False, phi_max, eta_max)
     lam = q / p
