@@ -81,3 +81,30 @@ def test_perigee_full_size_sampled_and_staged(kf):
     torch.cuda.synchronize()
     for name in ("par", "cov", "tgt_par", "tgt_cov", "chi2", "status"):
         assert np.array_equal(getattr(host, name).numpy(), getattr(dev, name).cpu().numpy(), equal_nan=True), name
+
+
+def test_staged_and_captured_variants_equal_device_fit(kf):
+    """The host-staged path and a captured graph give the device fit bit for
+    bit with the perigee target, the two-filter smoother and a field map."""
+    _announce("staged / graph equal device fit: two-filter, perigee, field map")
+    import torch
+    cases = [(synth.make_config(2, 3000), dict(smoother=1)),
+             (synth.make_config(3, 3000), dict(target=PERIGEE, perigee=REFS[1], smoother=1)),
+             (synth.make_config(6, 1500), dict(target=PERIGEE, perigee=REFS[0]))]
+    for ev, opt in cases:
+        dev = _fit(kf, ev, extras=False, schedule=2, **opt)
+        bh = kf.Batch.staged_from_event(ev)
+        host = kf.StagedPlan(bh, kf.Options(schedule=2, **opt), n_chunks=3, n_streams=2).run()
+        torch.cuda.synchronize()
+        g = kf.Plan(kf.Batch.from_event(ev), kf.Options(schedule=2, **opt), extras=False).capture()
+        for rep in range(3):
+            g.out.par.fill_(-1.0)
+            torch.cuda.synchronize()
+            g.run()
+            torch.cuda.synchronize()
+            for name in ("par", "cov", "tgt_par", "tgt_cov", "chi2", "status"):
+                want = getattr(dev, name).cpu().numpy()
+                assert np.array_equal(getattr(g.out, name).cpu().numpy(), want, equal_nan=True), (ev.name, rep, name)
+                if rep == 0:
+                    assert np.array_equal(getattr(host, name).numpy(), want, equal_nan=True), (ev.name, name)
+        g.release()
