@@ -50,13 +50,13 @@ def lib():
         P = C.c_void_p
         i, d = C.c_int, C.c_double
         fit_args = [i, P, P, P, P, i, P, P, P, P, i, P, d, P, P, i, i, d, d, d, i]
-        L.kfo_fit.argtypes = fit_args + [P] * 12 + [i, i, d, i, P]
+        L.kfo_fit.argtypes = fit_args + [P] * 12 + [i, i, d, i, P, P]
         L.kfo_fit.restype = i
         L.kfo_fit_vjp.argtypes = fit_args + [P] * 6 + [i]
         L.kfo_fit_vjp.restype = i
         L.kfo_count_ops.argtypes = fit_args + [P]
         L.kfo_count_ops.restype = i
-        L.kfo_transport.argtypes = [i, P, P, P, i, P, d, d, d, d, i, i, i, P, P, P, P]
+        L.kfo_transport.argtypes = [i, P, P, P, i, P, d, d, d, d, i, i, i, P, P, P, P, P]
         L.kfo_transport.restype = i
         L.kfo_transport_perigee.argtypes = [i, P, P, P, i, P, d, d, d, d, i, i, P, P, P, P, P]
         L.kfo_transport_perigee.restype = i
@@ -134,7 +134,8 @@ class _Args:
             off=_i32(ev.hit_offsets), sid=_i32(ev.surface_id), loc=_f64(ev.loc if loc is None else loc),
             cov=_f64(ev.cov), center=_f64(det.center), rot=_f64(det.rot), x0=_f64(det.x_over_X0),
             b0=_f64(ev.field.b0), seed=_f64(ev.seed_par if seed_par is None else seed_par),
-            seed_cov=_f64(ev.seed_cov), align=None if align is None else _f64(align))
+            seed_cov=_f64(ev.seed_cov), align=None if align is None else _f64(align),
+            stype=None if getattr(det, "stype", None) is None else _i32(det.stype))
         k = self.keep
         self.N = ev.n_tracks
         self.H = ev.n_hits
@@ -172,7 +173,7 @@ def fit(ev, n_threads: int = 0, extras: bool = False, smoother: str = "rts", bwd
     lib().kfo_fit(*a.args, _p(out.par), _p(out.cov), _p(out.tgt_par), _p(out.tgt_cov), _p(out.chi2),
                   _p(out.ndf), _p(out.status), _p(out.filt_par), _p(out.filt_cov), _p(out.pred_par),
                   _p(out.pred_cov), _p(out.trials), int(n_threads), SMOOTHERS[smoother], float(bwd_scale),
-                  0 if perigee is None else 1, _p(None if perigee is None else _f64(perigee)))
+                  0 if perigee is None else 1, _p(None if perigee is None else _f64(perigee)), _p(a.keep["stype"]))
     return out
 
 
@@ -212,9 +213,10 @@ def transport(det, field, sa, sb, x, mass=0.1056583755, tol=DEFAULT_TOL, land_to
     xo = np.empty(6)
     F = np.empty((6, 6))
     tr = np.zeros(1, np.int32)
+    stype = None if getattr(det, "stype", None) is None else _i32(det.stype)
     st = lib().kfo_transport(center.shape[1], _p(center), _p(rot), _p(x0), int(field.kind), _p(b0),
                              float(field.a), float(mass), float(tol), float(land_tol), int(max_steps),
-                             int(sa), int(sb), _p(xi), _p(xo), _p(F), _p(tr))
+                             int(sa), int(sb), _p(xi), _p(xo), _p(F), _p(tr), _p(stype))
     return st, xo, F, int(tr[0])
 
 

@@ -155,7 +155,10 @@ struct Cfg {
 };
 
 template <class S>
-struct Surf { S c[3]; S R[3][3]; double x0; };   // R columns: u, v, n; x0 = thickness in X0
+struct Surf {                 // R columns: u, v, n; x0 = thickness in X0
+    S c[3]; S R[3][3]; double x0;
+    int type = 0;             // 0 plane: local (u.d, v.d); 1 disc: polar (|d_uv|, atan2(v.d, u.d)), d = r - c
+};
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -293,12 +296,23 @@ void field_at(const FieldDef& f, const S r[3], S B[3], S dB[3][3]) {
 template <class S>
 void bound_to_free(const Surf<S>& s, const S P[6], S F[8], S J[8][6]) {
     S sp = sin(P[2]), cp = cos(P[2]), st = sin(P[3]), ct = cos(P[3]);
-    for (int i = 0; i < 3; ++i) F[i] = s.c[i] + P[0] * s.R[i][0] + P[1] * s.R[i][1];
+    for (int i = 0; i < 8; ++i) for (int j = 0; j < 6; ++j) J[i][j] = 0.0;
+    if (s.type == 1) {
+        // disc: r = c + l0 (cos l1 u + sin l1 v)
+        S cl = cos(P[1]), sl = sin(P[1]);
+        for (int i = 0; i < 3; ++i) {
+            S e = cl * s.R[i][0] + sl * s.R[i][1];
+            F[i] = s.c[i] + P[0] * e;
+            J[i][0] = e;
+            J[i][1] = P[0] * (cl * s.R[i][1] - sl * s.R[i][0]);
+        }
+    } else {
+        for (int i = 0; i < 3; ++i) F[i] = s.c[i] + P[0] * s.R[i][0] + P[1] * s.R[i][1];
+        for (int i = 0; i < 3; ++i) { J[i][0] = s.R[i][0]; J[i][1] = s.R[i][1]; }
+    }
     F[3] = P[5];
     F[4] = cp * st; F[5] = sp * st; F[6] = ct;
     F[7] = P[4];
-    for (int i = 0; i < 8; ++i) for (int j = 0; j < 6; ++j) J[i][j] = 0.0;
-    for (int i = 0; i < 3; ++i) { J[i][0] = s.R[i][0]; J[i][1] = s.R[i][1]; }
     J[3][5] = 1.0;
     J[4][2] = -(sp * st); J[5][2] = cp * st;
     J[4][3] = cp * ct;    J[5][3] = sp * ct;  J[6][3] = -st;
@@ -310,8 +324,17 @@ template <class S>
 void free_to_bound(const Surf<S>& s, const S F[8], S P[6], S J[6][8]) {
     S d[3];
     for (int i = 0; i < 3; ++i) d[i] = F[i] - s.c[i];
-    P[0] = s.R[0][0] * d[0] + s.R[1][0] * d[1] + s.R[2][0] * d[2];
-    P[1] = s.R[0][1] * d[0] + s.R[1][1] * d[1] + s.R[2][1] * d[2];
+    S a = s.R[0][0] * d[0] + s.R[1][0] * d[1] + s.R[2][0] * d[2];
+    S b = s.R[0][1] * d[0] + s.R[1][1] * d[1] + s.R[2][1] * d[2];
+    S rr = 0.0;
+    if (s.type == 1) {
+        rr = sqrt(a * a + b * b);
+        P[0] = rr;
+        P[1] = atan2(b, a);
+    } else {
+        P[0] = a;
+        P[1] = b;
+    }
     S tx = F[4], ty = F[5], tz = F[6];
     S rho2 = tx * tx + ty * ty;
     S rho = sqrt(rho2);
@@ -321,7 +344,14 @@ void free_to_bound(const Surf<S>& s, const S F[8], S P[6], S J[6][8]) {
     P[4] = F[7];
     P[5] = F[3];
     for (int i = 0; i < 6; ++i) for (int j = 0; j < 8; ++j) J[i][j] = 0.0;
-    for (int i = 0; i < 3; ++i) { J[0][i] = s.R[i][0]; J[1][i] = s.R[i][1]; }
+    if (s.type == 1) {
+        for (int i = 0; i < 3; ++i) {
+            J[0][i] = (a * s.R[i][0] + b * s.R[i][1]) / rr;
+            J[1][i] = (a * s.R[i][1] - b * s.R[i][0]) / (rr * rr);
+        }
+    } else {
+        for (int i = 0; i < 3; ++i) { J[0][i] = s.R[i][0]; J[1][i] = s.R[i][1]; }
+    }
     J[2][4] = -ty / rho2;  J[2][5] = tx / rho2;
     J[3][4] = tx * tz / (rho * n2); J[3][5] = ty * tz / (rho * n2); J[3][6] = -rho / n2;
     J[4][7] = 1.0;
@@ -655,10 +685,13 @@ void ms_noise(const Surf<S>& s, const S x[6], double mass, S (&Q)[6][6]) {
 // ---------------------------------------------------------------------------
 // gain-matrix update, H = [I2 0] (Sect. 2), Joseph covariance form
 // ---------------------------------------------------------------------------
+// ang1: the second local coordinate is an angle (disc): its residual and
+// its filtered value are taken in (-pi, pi].
 template <class S>
 int kalman_update(const S xp[6], const S (&Cp)[6][6], const S m[2], const S (&V)[2][2],
-                  S xf[6], S (&Cf)[6][6], S* chi2) {
+                  S xf[6], S (&Cf)[6][6], S* chi2, bool ang1 = false) {
     S r[2] = {m[0] - xp[0], m[1] - xp[1]};
+    if (ang1) r[1] = wrap_phi(r[1]);
     S Sm[2][2] = {{V[0][0] + Cp[0][0], V[0][1] + Cp[0][1]}, {V[1][0] + Cp[1][0], V[1][1] + Cp[1][1]}};
     S det = Sm[0][0] * Sm[1][1] - Sm[0][1] * Sm[1][0];
     if (!(val(Sm[0][0]) > 0.0 && val(det) > 0.0)) return ST_NOT_SPD;
@@ -668,6 +701,7 @@ int kalman_update(const S xp[6], const S (&Cp)[6][6], const S m[2], const S (&V)
         for (int a = 0; a < 2; ++a) K[i][a] = Cp[i][0] * Si[0][a] + Cp[i][1] * Si[1][a];
     for (int i = 0; i < 6; ++i) xf[i] = xp[i] + K[i][0] * r[0] + K[i][1] * r[1];
     xf[2] = wrap_phi(xf[2]);
+    if (ang1) xf[1] = wrap_phi(xf[1]);
     S IKH[6][6];
     for (int i = 0; i < 6; ++i)
         for (int j = 0; j < 6; ++j) IKH[i][j] = ((i == j) ? S(1.0) : S(0.0)) - ((j < 2) ? K[i][j] : S(0.0));
@@ -689,9 +723,12 @@ int kalman_update(const S xp[6], const S (&Cp)[6][6], const S m[2], const S (&V)
 // Rauch-Tung-Striebel step with the stored Jacobian F (Sect. 2):
 //   A = Cf F^T Cp1^{-1} (FP64 SPD solve),  xs = xf + A (xs1 - xp1),  Cs = Cf + A (Cs1 - Cp1) A^T
 // ---------------------------------------------------------------------------
+// ang1_next / ang1_here: the second local coordinate of state k+1 / k is an
+// angle (disc) and its differences and values are taken in (-pi, pi].
 template <class S>
 int rts_step(const S xf[6], const S (&Cf)[6][6], const S (&F)[6][6], const S xp1[6], const S (&Cp1)[6][6],
-             const S xs1[6], const S (&Cs1)[6][6], S xs[6], S (&Cs)[6][6]) {
+             const S xs1[6], const S (&Cs1)[6][6], S xs[6], S (&Cs)[6][6], bool ang1_next = false,
+             bool ang1_here = false) {
     S L[6][6];
     if (!cholesky6(Cp1, L)) return ST_NOT_SPD;
     S FC[6][6], At[6][6], A[6][6];
@@ -701,12 +738,14 @@ int rts_step(const S xf[6], const S (&Cf)[6][6], const S (&F)[6][6], const S xp1
     S dx[6];
     for (int i = 0; i < 6; ++i) dx[i] = xs1[i] - xp1[i];
     dx[2] = wrap_phi(dx[2]);
+    if (ang1_next) dx[1] = wrap_phi(dx[1]);
     for (int i = 0; i < 6; ++i) {
         S acc = xf[i];
         for (int k = 0; k < 6; ++k) acc = acc + A[i][k] * dx[k];
         xs[i] = acc;
     }
     xs[2] = wrap_phi(xs[2]);
+    if (ang1_here) xs[1] = wrap_phi(xs[1]);
     S dC[6][6], T1[6][6], T2[6][6];
     for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) dC[i][j] = Cs1[i][j] - Cp1[i][j];
     matmul(A, dC, T1);
@@ -726,7 +765,7 @@ int rts_step(const S xf[6], const S (&Cf)[6][6], const S (&F)[6][6], const S xp1
 // ---------------------------------------------------------------------------
 template <class S>
 int two_filter_combine(const S xf[6], const S (&Cf)[6][6], const S xb[6], const S (&Cb)[6][6],
-                       S xs[6], S (&Cs)[6][6]) {
+                       S xs[6], S (&Cs)[6][6], bool ang1 = false) {
     S Sm[6][6], L[6][6], Kt[6][6], K[6][6];
     for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) Sm[i][j] = Cf[i][j] + Cb[i][j];
     if (!cholesky6(Sm, L)) return ST_NOT_SPD;
@@ -735,12 +774,14 @@ int two_filter_combine(const S xf[6], const S (&Cf)[6][6], const S xb[6], const 
     S dx[6];
     for (int i = 0; i < 6; ++i) dx[i] = xb[i] - xf[i];
     dx[2] = wrap_phi(dx[2]);
+    if (ang1) dx[1] = wrap_phi(dx[1]);
     for (int i = 0; i < 6; ++i) {
         S acc = xf[i];
         for (int k = 0; k < 6; ++k) acc = acc + K[i][k] * dx[k];
         xs[i] = acc;
     }
     xs[2] = wrap_phi(xs[2]);
+    if (ang1) xs[1] = wrap_phi(xs[1]);
     S IK[6][6], IKt[6][6], T1[6][6], T2[6][6], T3[6][6], T4[6][6];
     for (int i = 0; i < 6; ++i)
         for (int j = 0; j < 6; ++j) IK[i][j] = ((i == j) ? S(1.0) : S(0.0)) - K[i][j];
@@ -797,9 +838,11 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
     out.chi2 = NAN;
     // input validation
     if (n < 3) return out.status = ST_TOO_FEW;
-    if (seed_sid < 0 || seed_sid >= n_surf) return out.status = ST_BAD_INPUT;
+    // the seed surface is a plane; hit surfaces are planes or discs
+    if (seed_sid < 0 || seed_sid >= n_surf || surf[seed_sid].type != 0) return out.status = ST_BAD_INPUT;
     for (int k = 0; k < n; ++k) {
         if (sid[k] < 0 || sid[k] >= n_surf) return out.status = ST_BAD_INPUT;
+        if (surf[sid[k]].type != 0 && surf[sid[k]].type != 1) return out.status = ST_BAD_INPUT;
         for (int a = 0; a < 2; ++a) if (!std::isfinite(val(m[2 * k + a]))) return out.status = ST_BAD_INPUT;
         const double* v = V3 + 3 * k;
         if (!(std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]))) return out.status = ST_BAD_INPUT;
@@ -838,7 +881,7 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
         const double* v = V3 + 3 * k;
         S V[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
         S ck;
-        st = kalman_update(xp, Cp, mk, V, x, C, &ck);
+        st = kalman_update(xp, Cp, mk, V, x, C, &ck, surf[sid[k]].type == 1);
         if (st != ST_OK) return out.status = st;
         chi2 = chi2 + ck;
         for (int i = 0; i < 6; ++i) {
@@ -874,7 +917,7 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
             S mk[2] = {m[2 * (n - 1)], m[2 * (n - 1) + 1]};
             const double* v = V3 + 3 * (n - 1);
             S V[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
-            int st = kalman_update(xl, Cl, mk, V, xb, Cb, &ck);
+            int st = kalman_update(xl, Cl, mk, V, xb, Cb, &ck, surf[sid[n - 1]].type == 1);
             if (st != ST_OK) return out.status = st;
         }
         for (int k = n - 2; k >= -1; --k) {
@@ -894,7 +937,8 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
             if (cfg.ms) ms_noise(sb, xf, cfg.mass, Q);
             else for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) Q[i][j] = 0.0;
             backward_predict(G, Q, Cb, Cq);
-            st = two_filter_combine(xf, Cf, xq, Cq, xs, Cs);
+            const bool ang = k >= 0 && surf[sid[k]].type == 1;
+            st = two_filter_combine(xf, Cf, xq, Cq, xs, Cs, ang);
             if (st != ST_OK) return out.status = st;
             for (int i = 0; i < 6; ++i) {
                 if (k >= 0) out.xs[6 * k + i] = xs[i]; else out.tgt[i] = xs[i];
@@ -907,7 +951,7 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
                 const double* v = V3 + 3 * k;
                 S V[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
                 S ck;
-                st = kalman_update(xq, Cq, mk, V, xb, Cb, &ck);
+                st = kalman_update(xq, Cq, mk, V, xb, Cb, &ck, ang);
                 if (st != ST_OK) return out.status = st;
             }
         }
@@ -928,7 +972,8 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
                 Cs1[i][j] = out.Cs[36 * (k + 1) + 6 * i + j];
             }
         }
-        int st = rts_step(xf, Cf, F, xp1, Cp1, xs1, Cs1, xs, Cs);
+        int st = rts_step(xf, Cf, F, xp1, Cp1, xs1, Cs1, xs, Cs, surf[sid[k + 1]].type == 1,
+                          k >= 0 && surf[sid[k]].type == 1);
         if (st != ST_OK) return out.status = st;
         for (int i = 0; i < 6; ++i) {
             if (k >= 0) out.xs[6 * k + i] = xs[i]; else out.tgt[i] = xs[i];
@@ -985,6 +1030,7 @@ void aligned_surface(const Surf<double>& s0, const S a[6], Surf<S>& o) {
     matmul(T2, Rz, R);
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) o.R[i][j] = R[i][j];
     o.x0 = s0.x0;
+    o.type = s0.type;
 }
 
 
@@ -997,6 +1043,7 @@ struct Inputs {
     const double* align;   // [6][S] alignment corrections or NULL
     FieldDef field; const double* seed; const double* seed_cov; int seed_sid;
     Cfg cfg;
+    const int32_t* stype = nullptr;   // [S] surface types (0 plane, 1 disc) or NULL (all planes)
 };
 
 // nominal surface s (before any alignment correction)
@@ -1005,6 +1052,7 @@ inline Surf<double> surf_nominal(const Inputs& in, int s) {
     for (int i = 0; i < 3; ++i) o.c[i] = in.center[i * in.n_surf + s];
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) o.R[i][j] = in.rot[(3 * i + j) * in.n_surf + s];
     o.x0 = in.x0[s];
+    o.type = in.stype ? in.stype[s] : 0;
     return o;
 }
 
@@ -1084,13 +1132,15 @@ int kfo_fit(int n_tracks, const int32_t* off, const int32_t* sid, const double* 
             int ms, double mass, double tol, double land_tol, int max_steps,
             double* par, double* pcov, double* tgt_par, double* tgt_cov, double* chi2, int32_t* ndf,
             uint8_t* status, double* filt_par, double* filt_cov, double* pred_par, double* pred_cov,
-            int32_t* trials, int n_threads, int smoother, double bwd_scale, int target, const double* perigee) {
+            int32_t* trials, int n_threads, int smoother, double bwd_scale, int target, const double* perigee,
+            const int32_t* stype) {
     Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, align, field_kind, b0, field_a,
                             seed, seed_cov, seed_sid, ms, mass, tol, land_tol, max_steps);
     in.cfg.smoother = smoother;
     in.cfg.bwd_scale = bwd_scale;
     in.cfg.target = target;
     for (int i = 0; i < 3; ++i) in.cfg.perigee[i] = perigee ? perigee[i] : 0.0;
+    in.stype = stype;
     std::vector<Surf<double>> surf(n_surf);
     for (int s = 0; s < n_surf; ++s) surf[s] = surf_d(in, s);
     const int64_t H = in.H;
@@ -1138,11 +1188,10 @@ int kfo_fit(int n_tracks, const int32_t* off, const int32_t* sid, const double* 
 int kfo_transport(int n_surf, const double* center, const double* rot, const double* x0,
                   int field_kind, const double* b0, double field_a, double mass, double tol,
                   double land_tol, int max_steps, int sa, int sb, const double* x, double* xo,
-                  double* F, int32_t* trials) {
-    double dummy = 0;
+                  double* F, int32_t* trials, const int32_t* stype) {
     Inputs in = make_inputs(0, nullptr, nullptr, nullptr, nullptr, n_surf, center, rot, x0, nullptr, field_kind, b0,
                             field_a, nullptr, nullptr, 0, 0, mass, tol, land_tol, max_steps);
-    (void)dummy;
+    in.stype = stype;
     Surf<double> A = surf_d(in, sa), B = surf_d(in, sb);
     double xi[6], xr[6], Fk[6][6];
     for (int i = 0; i < 6; ++i) xi[i] = x[i];

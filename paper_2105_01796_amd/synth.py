@@ -50,6 +50,7 @@ class Detector:
     center: np.ndarray      # (3, S) f64
     rot: np.ndarray         # (9, S) f64, row-major 3x3 with columns u, v, n
     x_over_X0: np.ndarray   # (S,) f64
+    stype: np.ndarray | None = None   # (S,) int32 surface types: 0 plane, 1 disc (None: all planes)
 
     @property
     def n(self) -> int:
@@ -172,7 +173,7 @@ def misalign(det: Detector, align: np.ndarray) -> Detector:
     for s in range(det.n):
         R = det.rot[:, s].reshape(3, 3) @ rot_xyz(*align[3:, s])
         rot[:, s] = R.reshape(9)
-    return Detector(center, rot, det.x_over_X0.copy())
+    return Detector(center, rot, det.x_over_X0.copy(), None if det.stype is None else det.stype.copy())
 
 
 # ----------------------------------------------------------------------------
@@ -324,19 +325,43 @@ def _kinematics(rng, N, pt_range=(1.0, 10.0), pt_log=False, phi_max=0.1, eta_max
     return q, p, phi, theta
 
 
+def _to_discs(ev):
+    """Measure every hit surface as a disc: local polar coordinates (r, phi)
+    about the surface centre in its (u, v) plane; r smeared by the hit
+    resolution, phi by resolution / r (the same unit normal draws)."""
+    unit = (ev.loc - ev.truth_hit[:2]) / SIGMA_HIT
+    a, b = ev.truth_hit[0], ev.truth_hit[1]
+    r = np.hypot(a, b)
+    ph = np.arctan2(b, a)
+    s_ph = SIGMA_HIT / r
+    ev.truth_hit[0], ev.truth_hit[1] = r, ph
+    ev.loc = np.ascontiguousarray(np.stack([r + SIGMA_HIT * unit[0],
+                                            np.angle(np.exp(1j * (ph + s_ph * unit[1])))]))
+    ev.cov = np.stack([np.full_like(r, SIGMA_HIT ** 2), np.zeros_like(r), s_ph ** 2])
+    st = np.ones(ev.detector.n, dtype=np.int32)
+    st[ev.seed_surface] = 0
+    ev.detector.stype = st
+    return ev
+
+
 def telescope_event(n_tracks, seed, n_planes=10, bz=2.0, x_over_X0=0.0, ms=False,
                     ragged=None, p_hole=0.1, f_inf=1.0, misalign_sigma=None,
-                    pt_range=(1.0, 10.0), phi_max=0.1, eta_max=0.2, name="telescope", pitch=30.0):
+                    pt_range=(1.0, 10.0), phi_max=0.1, eta_max=0.2, name="telescope", pitch=30.0,
+                    center_offset=None, discs=False):
     """Uniform field along z (or no field), planes normal to x, exact helices.
 
     ragged=(nmin, nmax): hit count per track uniform in [nmin, nmax], hole
     pattern from `choose_planes`; otherwise every plane is hit.
     misalign_sigma=(pos_mm, ang_rad): hits are simulated in a misaligned
     copy of the telescope while the fitter gets the nominal one.
+    center_offset: shift of every measuring surface's centre within its plane;
+    discs: measure in polar coordinates about that centre (`_to_discs`).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     N, P = n_tracks, n_planes
     det = telescope(P, pitch=pitch, x_over_X0=x_over_X0 if ms else 0.0)
+    if center_offset is not None:
+        det.center[:, 1:] += np.asarray(center_offset, float)[:, None]
     fld = Field(FIELD_UNIFORM, (0.0, 0.0, float(bz)), 0.0)
     q, p, phi, theta = _kinematics(rng, N, pt_range, False, phi_max, eta_max)
     lam = q / p
@@ -381,9 +406,10 @@ def telescope_event(n_tracks, seed, n_planes=10, bz=2.0, x_over_X0=0.0, ms=False
             th0 = highland_theta0(p, M_MU, path)
             ph = ph + th0 * kicks[:, j, 0] / np.sin(th)
             th = th + th0 * kicks[:, j, 1]
-    return _assemble(name, det, fld, mask, hit_state, hit_rand, seed_rand, truth0, ms, f_inf,
-                     det_true=det_true, align=align,
-                     meta=dict(seed=seed, n_planes=P, bz=bz, ragged=ragged))
+    ev = _assemble(name, det, fld, mask, hit_state, hit_rand, seed_rand, truth0, ms, f_inf,
+                   det_true=det_true, align=align,
+                   meta=dict(seed=seed, n_planes=P, bz=bz, ragged=ragged))
+    return _to_discs(ev) if discs else ev
 
 
 def solenoid_event(n_tracks, seed, n_planes=30, b0z=2.0, a=1e-7, nmin=8, p_hole=0.1,
@@ -441,7 +467,7 @@ def solenoid_event(n_tracks, seed, n_planes=30, b0z=2.0, a=1e-7, nmin=8, p_hole=
 # ----------------------------------------------------------------------------
 # named workloads
 # ----------------------------------------------------------------------------
-CONFIG_SEEDS = {1: 1001, 2: 1002, 3: 1003, 4: 1004, 5: 1005, 6: 1005}
+CONFIG_SEEDS = {1: 1001, 2: 1002, 3: 1003, 4: 1004, 5: 1005, 6: 1005, 7: 1007}
 
 
 def make_config(cfg: int, n_tracks: int | None = None, seed: int | None = None, **kw) -> Event:
@@ -455,6 +481,9 @@ def make_config(cfg: int, n_tracks: int | None = None, seed: int | None = None, 
     6: the tracks of 5, fitted with the field given as a map: the solenoid
        sampled every 25 mm over x -50..950, y -1000..1000, z -6000..6000 mm
        (41 x 81 x 481 points, 38 MB).
+    7: C2 measured on discs: every plane's centre moved to y = +100 mm and
+       the hits given in polar coordinates (r, phi) about it (phi straddles
+       +-pi), 50 um in r and 50 um / r in phi.
     """
     seed = CONFIG_SEEDS[cfg] if seed is None else seed
     if cfg == 1:
@@ -467,6 +496,9 @@ def make_config(cfg: int, n_tracks: int | None = None, seed: int | None = None, 
         return telescope_event(n_tracks or 100_000, seed, misalign_sigma=(0.01, 1e-4), name="C4", **kw)
     if cfg == 5:
         return solenoid_event(n_tracks or 1_000_000, seed, name="C5", **kw)
+    if cfg == 7:
+        return telescope_event(n_tracks or 100_000, seed, x_over_X0=0.005, ms=True, center_offset=(0.0, 100.0, 0.0),
+                               discs=True, name="C7", **kw)
     if cfg == 6:
         ev = solenoid_event(n_tracks or 1_000_000, seed, name="C6", **kw)
         ev.field = sample_field_map(ev.field, (-50.0, -1000.0, -6000.0), (950.0, 1000.0, 6000.0), (25.0, 25.0, 25.0))
