@@ -95,7 +95,11 @@ extern "C" {
 #define KF_TARGET_SEED_SURFACE 0  /* tgt_par / tgt_cov on the seed surface */
 #define KF_TARGET_PERIGEE 1       /* tgt_par / tgt_cov at the perigee of a line parallel to z */
 
-#define KF_MAX_SURFACES 512     /* the surface table is staged in LDS (13 doubles each) */
+#define KF_SURF_PLANE 0        /* local (u.(r - c), v.(r - c)) */
+#define KF_SURF_DISC 1         /* local polar (|d|, atan2(v.d, u.d)), d = (u.(r - c), v.(r - c)): radius
+                                  and azimuth about the centre in the surface's plane */
+
+#define KF_MAX_SURFACES 512     /* the surface table is staged in LDS (14 doubles each) */
 #define KF_MAX_HITS 64         /* per track */
 
 typedef struct {
@@ -107,6 +111,11 @@ typedef struct {
                                   (dx, dy, dz, alpha, beta, gamma); the fit uses the surface with
                                   centre c + (dx, dy, dz) and rotation R Rx(alpha) Ry(beta) Rz(gamma)
                                   (turned about its own u, v, n axes) */
+    const int32_t *type;       /* [S] optional (NULL = all planes): KF_SURF_* per surface.  The seed
+                                  surface must be a plane and every hit's surface a plane or a disc
+                                  (else that track gets KF_ST_BAD_INPUT).  On a disc the measured
+                                  azimuth, its residual and the filtered and smoothed azimuths are
+                                  taken in (-pi, pi].  kf_fit_tracks_vjp requires NULL */
 } kf_surfaces;
 
 typedef struct {

@@ -59,10 +59,13 @@ __device__ inline void fill_rows(double* p0, int64_t stride, double val) {
     }
 }
 
-// One hit is usable: a known surface, finite coordinates, an SPD covariance.
-__device__ inline bool hit_ok(int s, int n_surf, const double m[2], const double V[3]) {
-    return (s >= 0 && s < n_surf) && finite(m[0]) && finite(m[1]) && finite(V[0]) && finite(V[1]) &&
-           finite(V[2]) && (V[0] > 0.0) && (V[0] * V[2] - V[1] * V[1] > 0.0);
+// One hit is usable: a known surface of a measuring type (plane or disc;
+// stype NULL: all planes), finite coordinates, an SPD covariance.
+__device__ inline bool hit_ok(int s, int n_surf, const double m[2], const double V[3],
+                              const int32_t* stype = nullptr) {
+    return (s >= 0 && s < n_surf) && (!stype || stype[s] == 0 || stype[s] == 1) && finite(m[0]) &&
+           finite(m[1]) && finite(V[0]) && finite(V[1]) && finite(V[2]) && (V[0] > 0.0) &&
+           (V[0] * V[2] - V[1] * V[1] > 0.0);
 }
 
 // The per-track checks that need no hit: CSR range, hit count, a finite seed
@@ -108,12 +111,12 @@ __device__ inline int check_head(const int32_t* off, const double* seed, const d
 
 // Some hit in [k0, n) of the track at CSR offset o is unusable.
 __device__ inline bool any_bad_hit(const int32_t* sid, const double* loc, const double* cov, int64_t H, int n_surf,
-                                   int o, int k0, int n) {
+                                   int o, int k0, int n, const int32_t* stype = nullptr) {
     for (int k = k0; k < n; ++k) {
         double m[2], V[3];
         load_rows(loc + o + k, H, m);
         load_rows(cov + o + k, H, V);
-        if (!hit_ok(sid[o + k], n_surf, m, V)) return true;
+        if (!hit_ok(sid[o + k], n_surf, m, V, stype)) return true;
     }
     return false;
 }
@@ -126,6 +129,11 @@ __device__ inline int check_track(const int32_t* off, const int32_t* sid, const 
     const int st = check_head(off, seed, seed_cov, H, N, max_hits, t, o, n);
     if (st != ST_OK) return st;
     return any_bad_hit(sid, loc, cov, H, n_surf, o, 0, n) ? ST_BAD_INPUT : ST_OK;
+}
+
+// The seed surface is a plane (the transports start from plane coordinates there)
+__device__ inline bool seed_surface_ok(const int32_t* stype, int seed_sid) {
+    return !stype || stype[seed_sid] == 0;
 }
 
 // Surface s with an alignment correction a = (dx, dy, dz, alpha, beta, gamma):
@@ -171,16 +179,18 @@ __device__ inline void apply_alignment(const double al[6], double s[SURF_STRIDE]
     for (int i = 0; i < 3; ++i) s[i] += al[i];
 }
 
-// Surface table in LDS: c[3], R[9] row-major, x/X0 per surface (13 doubles).
+// Surface table in LDS: c[3], R[9] row-major, x/X0, type (1: disc) per
+// surface (14 doubles).
 __device__ inline void stage_surfaces(int S, const double* center, const double* rot, const double* x0,
-                                      const double* align, double* sm) {
+                                      const double* align, const int32_t* stype, double* sm) {
     if (!align) {
         for (int i = threadIdx.x; i < S * SURF_STRIDE; i += blockDim.x) {
             const int s = i / SURF_STRIDE, f = i - s * SURF_STRIDE;
             double v;
             if (f < 3) v = center[f * S + s];
             else if (f < 12) v = rot[(f - 3) * S + s];
-            else v = x0[s];
+            else if (f == 12) v = x0[s];
+            else v = (stype && stype[s] == 1) ? 1.0 : 0.0;
             sm[i] = v;
         }
     } else {
@@ -191,6 +201,7 @@ __device__ inline void stage_surfaces(int S, const double* center, const double*
 #pragma unroll
             for (int f = 0; f < 9; ++f) v[3 + f] = rot[f * S + s];
             v[12] = x0[s];
+            v[13] = (stype && stype[s] == 1) ? 1.0 : 0.0;
 #pragma unroll
             for (int c = 0; c < 6; ++c) al[c] = align[c * S + s];
             apply_alignment(al, v);

@@ -31,8 +31,10 @@ __host__ __device__ constexpr int sy(int i, int j) {
 // (the q/p row is e4 and the t column is e5, both implied); 5 x 5 = 25 entries
 __host__ __device__ constexpr int frow(int i) { return i < 4 ? i : 4; }
 
-// surface table entry in LDS: c[3], R[9] (row-major, columns u v n), x/X0
-constexpr int SURF_STRIDE = 13;
+// surface table entry in LDS: c[3], R[9] (row-major, columns u v n), x/X0,
+// type (0 plane, 1 disc)
+constexpr int SURF_STRIDE = 14;
+__device__ inline bool is_disc(const double* __restrict__ s) { return s[13] != 0.0; }
 
 struct FieldDef {
     int kind;
@@ -400,6 +402,32 @@ __device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& 
 // ---------------------------------------------------------------------------
 // P is the stepping type (double, or float for MIXED); everything else is
 // FP64.  Surfaces a and b are 13 values each (c, R, x/X0).
+// Local -> global on a surface: position r = c + offset(loc), and the
+// columns e0 = dr/dloc0, e1 = dr/dloc1.  Plane: offset l0 u + l1 v; disc:
+// l0 (cos l1 u + sin l1 v).
+__device__ inline void loc_frame(const double* __restrict__ s, const double x[6], double e0[3], double e1[3]) {
+    if (is_disc(s)) {
+        double sl, cl;
+        angle_sincos(x[1], &sl, &cl);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            e0[i] = cl * s[3 + 3 * i + 0] + sl * s[3 + 3 * i + 1];
+            e1[i] = x[0] * (cl * s[3 + 3 * i + 1] - sl * s[3 + 3 * i + 0]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { e0[i] = s[3 + 3 * i + 0]; e1[i] = s[3 + 3 * i + 1]; }
+    }
+}
+__device__ inline double loc_offset(const double* __restrict__ s, const double x[6], int i) {
+    if (is_disc(s)) {
+        double sl, cl;
+        angle_sincos(x[1], &sl, &cl);
+        return x[0] * (cl * s[3 + 3 * i + 0] + sl * s[3 + 3 * i + 1]);
+    }
+    return x[0] * s[3 + 3 * i + 0] + x[1] * s[3 + 3 * i + 1];
+}
+
 template <class P, int FK>
 __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, const Cfg& cfg,
                                 const double* __restrict__ sa, const double* __restrict__ sb,
@@ -412,20 +440,24 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
     angle_sincos(x[3], &st, &ct);
     R r0[3], T0[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) r0[i] = sa[i] + x[0] * sa[3 + 3 * i + 0] + x[1] * sa[3 + 3 * i + 1];
+    for (int i = 0; i < 3; ++i) r0[i] = sa[i] + loc_offset(sa, x, i);
     T0[0] = cp * st; T0[1] = sp * st; T0[2] = ct;
     const R lam_d = x[4];
     const P lam = P(lam_d);
     const R gd = sqrt(1.0 + cfg.mass * cfg.mass * lam_d * lam_d) / kC;     // dt/ds
     const R gpd = cfg.mass * cfg.mass * lam_d / (kC * kC * gd);            // d(dt/ds)/d(q/p)
     P Mr[3][5], MT[3][5];
+    {
+        R e0[3], e1[3];
+        if (TangentCols<FK>::J0 == 0) loc_frame(sa, x, e0, e1);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+        for (int i = 0; i < 3; ++i) {
 #pragma unroll
-        for (int j = 0; j < 5; ++j) { Mr[i][j] = P(0); MT[i][j] = P(0); }
-        if (TangentCols<FK>::J0 == 0) {
-            Mr[i][0] = P(sa[3 + 3 * i + 0]);
-            Mr[i][1] = P(sa[3 + 3 * i + 1]);
+            for (int j = 0; j < 5; ++j) { Mr[i][j] = P(0); MT[i][j] = P(0); }
+            if (TangentCols<FK>::J0 == 0) {
+                Mr[i][0] = P(e0[i]);
+                Mr[i][1] = P(e1[i]);
+            }
         }
     }
     MT[0][2] = P(-(sp * st)); MT[1][2] = P(cp * st); MT[2][2] = P(0);
@@ -517,12 +549,30 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
         t = t + rem * gd;
     }
     const R nTd = nb[0] * T[0] + nb[1] * T[1] + nb[2] * T[2];
-    // free -> bound on surface b
+    // free -> bound on surface b: the local rows g0, g1 are d loc / d r
     const R u[3] = {sb[3 + 0], sb[3 + 3], sb[3 + 6]};
     const R v[3] = {sb[3 + 1], sb[3 + 4], sb[3 + 7]};
     const R dd[3] = {r[0] - sb[0], r[1] - sb[1], r[2] - sb[2]};
-    xp[0] = u[0] * dd[0] + u[1] * dd[1] + u[2] * dd[2];
-    xp[1] = v[0] * dd[0] + v[1] * dd[1] + v[2] * dd[2];
+    R g0[3], g1[3];
+    {
+        const R ca = u[0] * dd[0] + u[1] * dd[1] + u[2] * dd[2];
+        const R cb = v[0] * dd[0] + v[1] * dd[1] + v[2] * dd[2];
+        if (is_disc(sb)) {
+            const R rr = sqrt(ca * ca + cb * cb);
+            xp[0] = rr;
+            xp[1] = atan2(cb, ca);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                g0[i] = (ca * u[i] + cb * v[i]) / rr;
+                g1[i] = (ca * v[i] - cb * u[i]) / (rr * rr);
+            }
+        } else {
+            xp[0] = ca;
+            xp[1] = cb;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) { g0[i] = u[i]; g1[i] = v[i]; }
+        }
+    }
     const R rho2 = T[0] * T[0] + T[1] * T[1];
     const R rho = sqrt(rho2);
     const R n2 = rho2 + T[2] * T[2];
@@ -538,6 +588,9 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
     cross(T, B, TxB);
     const R lk = lam_d * kKappa;
     const R inT = 1.0 / nTd, ip = 1.0 / rho2, ith = 1.0 / (rho * n2), in2 = 1.0 / n2;
+    // the loc0/loc1 columns of a uniform field were never propagated: dr/dloc on surface a
+    R e0[3], e1[3];
+    if (TangentCols<FK>::J0 != 0) loc_frame(sa, x, e0, e1);
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
         // columns below J0 were never propagated: (u, v) of surface a, no direction part
@@ -545,7 +598,7 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
         R mr[3], mt[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            mr[i] = fixed ? R(sa[3 + 3 * i + j]) : R(Mr[i][j]);
+            mr[i] = fixed ? (j == 0 ? e0[i] : e1[i]) : R(Mr[i][j]);
             mt[i] = fixed ? R(0.0) : R(MT[i][j]);
         }
         const R sc = (nb[0] * mr[0] + nb[1] * mr[1] + nb[2] * mr[2]) * inT;
@@ -554,8 +607,8 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
             mr[i] = mr[i] - T[i] * sc;
             mt[i] = mt[i] - lk * TxB[i] * sc;
         }
-        F[0 * 5 + j] = u[0] * mr[0] + u[1] * mr[1] + u[2] * mr[2];
-        F[1 * 5 + j] = v[0] * mr[0] + v[1] * mr[1] + v[2] * mr[2];
+        F[0 * 5 + j] = g0[0] * mr[0] + g0[1] * mr[1] + g0[2] * mr[2];
+        F[1 * 5 + j] = g1[0] * mr[0] + g1[1] * mr[1] + g1[2] * mr[2];
         F[2 * 5 + j] = (T[0] * mt[1] - T[1] * mt[0]) * ip;
         F[3 * 5 + j] = T[2] * (T[0] * mt[0] + T[1] * mt[1]) * ith - rho * mt[2] * in2;
         F[4 * 5 + j] = (j == 4 ? Mtl : R(0.0)) - gd * sc;
@@ -584,9 +637,10 @@ __device__ inline int transport_perigee(const FieldDef& fd, const Cfg& cfg, cons
     R sp, cp, st, ct;
     angle_sincos(x[2], &sp, &cp);
     angle_sincos(x[3], &st, &ct);
-    R r[3], T[3];
+    R r[3], T[3], e0[3], e1[3];
+    loc_frame(sa, x, e0, e1);       // dr/dloc on surface a (also the fixed columns of a uniform field)
 #pragma unroll
-    for (int i = 0; i < 3; ++i) r[i] = sa[i] + x[0] * sa[3 + 3 * i + 0] + x[1] * sa[3 + 3 * i + 1];
+    for (int i = 0; i < 3; ++i) r[i] = sa[i] + loc_offset(sa, x, i);
     T[0] = cp * st; T[1] = sp * st; T[2] = ct;
     const R lam = x[4];
     const R lk = lam * kKappa;
@@ -598,8 +652,8 @@ __device__ inline int transport_perigee(const FieldDef& fd, const Cfg& cfg, cons
 #pragma unroll
         for (int j = 0; j < 5; ++j) { Mr[i][j] = 0.0; MT[i][j] = 0.0; }
         if (TangentCols<FK>::J0 == 0) {
-            Mr[i][0] = sa[3 + 3 * i + 0];
-            Mr[i][1] = sa[3 + 3 * i + 1];
+            Mr[i][0] = e0[i];
+            Mr[i][1] = e1[i];
         }
     }
     MT[0][2] = -(sp * st); MT[1][2] = cp * st; MT[2][2] = 0.0;
@@ -679,7 +733,7 @@ __device__ inline int transport_perigee(const FieldDef& fd, const Cfg& cfg, cons
         R mr[3], mt[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            mr[i] = fixed ? R(sa[3 + 3 * i + j]) : Mr[i][j];
+            mr[i] = fixed ? (j == 0 ? e0[i] : e1[i]) : Mr[i][j];
             mt[i] = fixed ? R(0.0) : MT[i][j];
         }
         const R sc = (T[0] * mr[0] + T[1] * mr[1] + dx * mt[0] + dy * mt[1]) * igp;
@@ -758,8 +812,10 @@ __device__ inline void transport_cov(const double F[25], const double C[21], dou
 //      = Cp - K P - P^T K^T + K S K^T,  P = H Cp, S = V + H Cp H^T
 // ---------------------------------------------------------------------------
 __device__ inline int kalman_update(const double xp[6], const double Cp[21], const double m[2],
-                                    const double V[3], double xf[6], double Cf[21], double* chi2) {
-    const double r0 = m[0] - xp[0], r1 = m[1] - xp[1];
+                                    const double V[3], double xf[6], double Cf[21], double* chi2,
+                                    bool ang1 = false) {
+    // ang1: the second local coordinate is an azimuth (disc), residual and value in (-pi, pi]
+    const double r0 = m[0] - xp[0], r1 = ang1 ? wrap_phi(m[1] - xp[1]) : m[1] - xp[1];
     const double S00 = V[0] + Cp[sy(0, 0)], S01 = V[1] + Cp[sy(0, 1)], S11 = V[2] + Cp[sy(1, 1)];
     const double det = S00 * S11 - S01 * S01;
     if (!(S00 > 0.0 && det > 0.0)) return ST_NOT_SPD;
@@ -775,6 +831,7 @@ __device__ inline int kalman_update(const double xp[6], const double Cp[21], con
 #pragma unroll
     for (int i = 0; i < 6; ++i) xf[i] = xp[i] + K[i][0] * r0 + K[i][1] * r1;
     xf[2] = wrap_phi(xf[2]);
+    if (ang1) xf[1] = wrap_phi(xf[1]);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         // (K S)_i
@@ -860,15 +917,17 @@ __device__ inline void smoother_gain_row(const double F[25], const double C[21],
 //   rts_cov:  Cs = Cf + A D A^T  (R holds Cf on entry, the result on exit)
 // ---------------------------------------------------------------------------
 __device__ inline void rts_diff(const double xs1[6], double CsD[21], const double xp1[6], const double Cp1[21],
-                                double dx[6]) {
+                                double dx[6], bool ang1 = false) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) dx[i] = xs1[i] - xp1[i];
     dx[2] = wrap_phi(dx[2]);
+    if (ang1) dx[1] = wrap_phi(dx[1]);
 #pragma unroll
     for (int q = 0; q < 21; ++q) CsD[q] -= Cp1[q];
 }
 
-__device__ inline void rts_mean(const double xf[6], const double A[36], const double dx[6], double xs[6]) {
+__device__ inline void rts_mean(const double xf[6], const double A[36], const double dx[6], double xs[6],
+                                bool ang1 = false) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double acc = xf[i];
@@ -877,6 +936,7 @@ __device__ inline void rts_mean(const double xf[6], const double A[36], const do
         xs[i] = acc;
     }
     xs[2] = wrap_phi(xs[2]);
+    if (ang1) xs[1] = wrap_phi(xs[1]);
 }
 
 __device__ inline void rts_cov(const double A[36], const double D[21], double R[21]) {
@@ -910,7 +970,7 @@ __device__ inline void rts_cov(const double A[36], const double D[21], double R[
 // if Cf + Cb is not positive definite.
 // ---------------------------------------------------------------------------
 __device__ inline bool two_filter_combine(const double xf[6], const double Cf[21], const double xb[6],
-                                          const double Cb[21], double xs[6], double Cs[21]) {
+                                          const double Cb[21], double xs[6], double Cs[21], bool ang1 = false) {
     double L[21], id[6], S[21];
 #pragma unroll
     for (int q = 0; q < 21; ++q) S[q] = Cf[q] + Cb[q];
@@ -929,6 +989,7 @@ __device__ inline bool two_filter_combine(const double xf[6], const double Cf[21
 #pragma unroll
     for (int i = 0; i < 6; ++i) dx[i] = xb[i] - xf[i];
     dx[2] = wrap_phi(dx[2]);
+    if (ang1) dx[1] = wrap_phi(dx[1]);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double acc = xf[i];
@@ -937,6 +998,7 @@ __device__ inline bool two_filter_combine(const double xf[6], const double Cf[21
         xs[i] = acc;
     }
     xs[2] = wrap_phi(xs[2]);
+    if (ang1) xs[1] = wrap_phi(xs[1]);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double e[6], f[6];                           // row i of (I - K) Cf and of K Cb

@@ -68,6 +68,7 @@ struct FitArgs {
     const double* rot;
     const double* x0;
     const double* align;        // [6][S] alignment corrections or NULL
+    const int32_t* stype;       // [S] surface types (0 plane, 1 disc) or NULL
     const double* seed;
     const double* seed_cov;
     FieldDef field;
@@ -91,6 +92,11 @@ struct FitArgs {
     double perigee[3];          // perigee target: a point of the line (parallel to z)
 };
 
+// Hit k of the track at CSR offset o lies on a disc (its azimuth wraps).
+__device__ inline bool disc_hit(const FitArgs& a, int o, int k) {
+    return a.stype && a.stype[a.sid[o + k]] == 1;
+}
+
 // Forward filter of the track held by workspace slot `slot` (track index t):
 // per hit propagation, covariance transport and the gain-matrix update.
 // Each hit is checked when the loop reaches it, with its surface id and
@@ -108,6 +114,7 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
     const int64_t N = a.n_tracks;
     int o, n;
     int status = check_head(a.off, a.seed, a.seed_cov, H, N, a.max_hits, t, o, n);
+    if (status == ST_OK && !seed_surface_ok(a.stype, a.seed_sid)) status = ST_BAD_INPUT;
     double x[6];
     load_rows(a.seed + t, N, x);
     Field<P, FK> fl;
@@ -130,7 +137,7 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
         const int s = s_nx;
         const double m[2] = {m_nx[0], m_nx[1]};
         const double V[3] = {V_nx[0], V_nx[1], V_nx[2]};
-        if (!hit_ok(s, a.n_surf, m, V)) { status = ST_BAD_INPUT; break; }
+        if (!hit_ok(s, a.n_surf, m, V, a.stype)) { status = ST_BAD_INPUT; break; }
         if (k + 1 < n) {
             s_nx = a.sid[o + k + 1];
             load_rows(a.loc + o + k + 1, H, m_nx);
@@ -173,7 +180,7 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
         for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = Cp[q];
         double ck, C[21];
         phase_boundary();
-        status = kalman_update(xp, Cp, m, V, x, C, &ck);
+        status = kalman_update(xp, Cp, m, V, x, C, &ck, is_disc(sb));
         if (status != ST_OK) break;
         phase_boundary();
         chi2 += ck;
@@ -186,7 +193,7 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
         prev = s;
     }
     if (status != ST_OK && status != ST_BAD_INPUT && status != ST_TOO_FEW &&
-        any_bad_hit(a.sid, a.loc, a.cov, H, a.n_surf, o, k + 1, n))
+        any_bad_hit(a.sid, a.loc, a.cov, H, a.n_surf, o, k + 1, n, a.stype))
         status = ST_BAD_INPUT;
     if (status == ST_OK) {
         a.chi2[t] = chi2;
@@ -242,8 +249,9 @@ __device__ bool bwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t
         for (int q = 0; q < 21; ++q) Cp1[q] = w[(OFF_CP + q) * TILE];
         load_rows(a.loc + o + n - 1, H, m);
         load_rows(a.cov + o + n - 1, H, V);
-        kalman_update(xp1, Cp1, m, V, x, C, &ck);
+        kalman_update(xp1, Cp1, m, V, x, C, &ck, disc_hit(a, o, n - 1));
     }
+    bool ang1 = disc_hit(a, o, n - 1);                 // hit k+1 is on a disc
     bool spd = true;
     int fail = ST_OK;
     int s1 = STOREF ? 0 : a.sid[o + n - 1];          // surface of hit k+1
@@ -277,10 +285,11 @@ __device__ bool bwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t
         for (int q = 0; q < 21; ++q) w1[(OFF_CP + q) * TILE] = C[q];
         double dx[6], L[21], id[6];
         spd = chol6(Cp1, L, id) && spd;
-        rts_diff(x, C, xp1, Cp1, dx);                    // C now holds D = Cs1 - Cp1
+        rts_diff(x, C, xp1, Cp1, dx, ang1);              // C now holds D = Cs1 - Cp1
+        const bool ang0 = k >= 0 && disc_hit(a, o, k);
         if (k >= 0) {
             double ck;
-            kalman_update(xp, Cp, m, V, xf, Cf, &ck);    // filtered state of hit k, as in the forward pass
+            kalman_update(xp, Cp, m, V, xf, Cf, &ck, ang0);   // filtered state of hit k, as in the forward pass
 #pragma unroll
             for (int i = 0; i < 6; ++i) xp1[i] = xp[i];
 #pragma unroll
@@ -306,8 +315,9 @@ __device__ bool bwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t
             for (int i = 0; i < 6; ++i) A[6 * c + i] = g[i];
         }
         phase_boundary();
-        rts_mean(xf, A, dx, x);
+        rts_mean(xf, A, dx, x, ang0);
         rts_cov(A, C, Cf);
+        ang1 = ang0;
 #pragma unroll
         for (int q = 0; q < 21; ++q) C[q] = Cf[q];
         phase_boundary();
@@ -365,14 +375,14 @@ __device__ bool bwd_two_filter(const FitArgs& a, const double* __restrict__ sm, 
         for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
         load_rows(a.loc + o + n - 1, H, m);
         load_rows(a.cov + o + n - 1, H, V);
-        kalman_update(xp, Cp, m, V, x, C, &ck);
+        kalman_update(xp, Cp, m, V, x, C, &ck, disc_hit(a, o, n - 1));
 #pragma unroll
         for (int i = 0; i < 6; ++i) w[(OFF_XP + i) * TILE] = x[i];
 #pragma unroll
         for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = C[q];
 #pragma unroll
         for (int q = 0; q < 21; ++q) C[q] *= a.bwd_scale;
-        if (kalman_update(x, C, m, V, xb, Cb, &ck) != ST_OK) fail = ST_NOT_SPD;
+        if (kalman_update(x, C, m, V, xb, Cb, &ck, disc_hit(a, o, n - 1)) != ST_OK) fail = ST_NOT_SPD;
     }
     int s1 = a.sid[o + n - 1];
     double xs[6], Cs[21];
@@ -380,6 +390,7 @@ __device__ bool bwd_two_filter(const FitArgs& a, const double* __restrict__ sm, 
         double xf[6], Cf[21], m[2], V[3];
         int s0 = a.seed_sid;
         double* w = wl + (k >= 0 ? k : 0) * (NW * TILE);
+        const bool ang = k >= 0 && disc_hit(a, o, k);
         if (k >= 0) {
             double xp[6], Cp[21], ck;
 #pragma unroll
@@ -389,7 +400,7 @@ __device__ bool bwd_two_filter(const FitArgs& a, const double* __restrict__ sm, 
             load_rows(a.loc + o + k, H, m);
             load_rows(a.cov + o + k, H, V);
             s0 = a.sid[o + k];
-            kalman_update(xp, Cp, m, V, xf, Cf, &ck);
+            kalman_update(xp, Cp, m, V, xf, Cf, &ck, ang);
         } else {
             load_rows(a.seed + t, N, xf);
             load_rows(a.seed_cov + t, N, Cf);
@@ -407,7 +418,7 @@ __device__ bool bwd_two_filter(const FitArgs& a, const double* __restrict__ sm, 
         Cq[sy(2, 2)] += q22;
         Cq[sy(3, 3)] += q33;
         phase_boundary();
-        if (!two_filter_combine(xf, Cf, xq, Cq, xs, Cs)) { fail = ST_NOT_SPD; break; }
+        if (!two_filter_combine(xf, Cf, xq, Cq, xs, Cs, ang)) { fail = ST_NOT_SPD; break; }
         phase_boundary();
         if (k >= 0) {
 #pragma unroll
@@ -415,7 +426,7 @@ __device__ bool bwd_two_filter(const FitArgs& a, const double* __restrict__ sm, 
 #pragma unroll
             for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = Cs[q];
             double ck;
-            if (kalman_update(xq, Cq, m, V, xb, Cb, &ck) != ST_OK) { fail = ST_NOT_SPD; break; }
+            if (kalman_update(xq, Cq, m, V, xb, Cb, &ck, ang) != ST_OK) { fail = ST_NOT_SPD; break; }
         }
         s1 = s0;
     }
@@ -532,7 +543,7 @@ k_fwd(FitArgs a) {
     static_assert(FUSED || STOREF, "the split smoother reads stored Jacobians");
     static_assert(!TWOF || (FUSED && !STOREF), "the two-filter smoother is fused and stores no Jacobians");
     extern __shared__ double sm[];
-    stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, sm);
+    stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, a.stype, sm);
     const int lane = threadIdx.x & (TILE - 1);
     double* cl = sm + a.n_surf * SURF_STRIDE + (threadIdx.x / TILE) * WAVE_LDS_DOUBLES + lane;
     int iter = 0;
@@ -600,6 +611,7 @@ __global__ void __launch_bounds__(256) k_perigee(FitArgs a) {
 #pragma unroll
     for (int f = 0; f < 9; ++f) sv[3 + f] = a.rot[f * S + s0];
     sv[12] = a.x0[s0];
+    sv[13] = 0.0;                       // the seed surface is a plane
     if (a.align) {
         double al[6];
 #pragma unroll
@@ -751,6 +763,7 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     a.rot = surf->rot;
     a.x0 = surf->x_over_X0;
     a.align = surf->align;
+    a.stype = surf->type;
     a.seed = seeds->par;
     a.seed_cov = seeds->cov;
     a.field = field_def(field);

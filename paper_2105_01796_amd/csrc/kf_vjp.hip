@@ -441,7 +441,7 @@ __device__ __attribute__((noinline)) void vjp_one(const VjpArgs& ag, const ldoub
 template <int FK, bool SORTED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_vjp(VjpArgs a) {
     extern __shared__ double sm[];
-    stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, sm);
+    stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, nullptr, sm);
     const int lane = threadIdx.x & (TILE - 1);
     ldouble* sx = (ldouble*)(sm + a.n_surf * SURF_STRIDE + (threadIdx.x / TILE) * (SX_N * TILE)) + lane;
     int iter = 0;
@@ -671,6 +671,7 @@ int kf_fit_tracks_vjp(const kf_config* cfg, const kf_surfaces* surf, const kf_fi
     if (cfg->smoother != KF_SMOOTHER_RTS) return KF_E_VALUE;     // the reverse pass is that of RTS
     if (cfg->target != KF_TARGET_SEED_SURFACE) return KF_E_VALUE;  // ... ending on the seed surface
     if (field->kind == KF_FIELD_MAP) return KF_E_VALUE;            // analytic fields only
+    if (surf->type) return KF_E_VALUE;                             // planes only
     if (meas->n_hits > 0 && !grad->meas) return KF_E_NULL;
     const VjpLayout L = vjp_layout(meas->n_tracks, meas->n_hits, meas->max_hits, surf->n);
     if (!workspace) return KF_E_WS;

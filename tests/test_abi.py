@@ -207,6 +207,9 @@ def test_vjp_argument_validation(kf):
     cfg.target = kf.KF_TARGET_PERIGEE           # ... ending on the seed surface
     assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_VALUE
     cfg.target = kf.KF_TARGET_SEED_SURFACE
+    surf.type = C.c_void_p(0x4000)              # ... on planes
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_VALUE
+    surf.type = None
     fld.kind = kf.KF_FIELD_MAP                  # ... in an analytic field
     fld.map = C.c_void_p(0x3000)
     fld.map_n[0] = fld.map_n[1] = fld.map_n[2] = 4
