@@ -59,7 +59,7 @@ extern "C" {
 #define KF_E_HIP (-5)       /* the HIP runtime reported an error */
 #define KF_E_VALUE (-6)     /* a configuration value is out of range (tolerance <= 0, ...), or the
                                workgroup size needs more LDS than the device has for this
-                               surface count (13 doubles per surface + 14.5 KiB per 64 threads) */
+                               surface count (14 doubles per surface + 14.5 KiB per 64 threads) */
 
 /* ---- per-track status ---- */
 #define KF_ST_OK 0

@@ -401,7 +401,7 @@ __device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& 
 // same FP64 second-order move finishes it.
 // ---------------------------------------------------------------------------
 // P is the stepping type (double, or float for MIXED); everything else is
-// FP64.  Surfaces a and b are 13 values each (c, R, x/X0).
+// FP64.  Surfaces a and b are 14 values each (c, R, x/X0, type).
 // Local -> global on a surface: position r = c + offset(loc), and the
 // columns e0 = dr/dloc0, e1 = dr/dloc1.  Plane: offset l0 u + l1 v; disc:
 // l0 (cos l1 u + sin l1 v).
