@@ -2,13 +2,17 @@
  * kf.h -- C ABI of the MI355X batched Kalman-filter track fitter (libkfmi.so).
  *
  * The library fits many independent charged-particle tracks at once.  Each
- * track is a list of 2-D hits on planar surfaces.  The fit is the Kalman-filter
+ * track is a list of 2-D hits on planes or discs.  The fit is the Kalman-filter
  * track fit of the paper (Sect. 2, Fig. 1): adaptive Runge-Kutta-Nystrom
  * propagation from surface to surface with the transport Jacobian and the
  * local<->global Jacobians (Sect. 4.1), a gain-matrix update on every measured
  * surface (Sect. 2, step 3), then a Rauch-Tung-Striebel smoother that reuses
- * the Jacobians stored during the forward pass (Sect. 2, smoother paragraph).
+ * the Jacobians stored during the forward pass (Sect. 2, smoother paragraph),
+ * or, on request, the paper's other smoother: a second Kalman filter run
+ * backwards and combined with the forward one (Sect. 2, Fig. 2).
  * The matrix inverse the smoother needs is always done in FP64 (Sect. 4.2.4).
+ * The field is uniform, solenoid-like or a tabulated map; the fitted
+ * parameters come on the seed surface or at the perigee of a line.
  * The per-track data sets follow Sect. 4.3: measurements, starting
  * parameters, fit configuration (target surface), and results (status,
  * track states, fitted parameters at the target surface).
@@ -19,14 +23,17 @@
  *                    phi in (-pi, pi], theta in [0, pi]
  *   covariances      packed upper triangle, row-major: (0,0),(0,1)..(0,5),(1,1)..(5,5)
  *   surfaces         planes with centre c and rotation R = [u v n] (columns);
- *                    loc0 = u.(r - c), loc1 = v.(r - c); planes are unbounded
+ *                    loc0 = u.(r - c), loc1 = v.(r - c); surfaces are unbounded;
+ *                    a disc (kf_surfaces.type) measures the polar coordinates of
+ *                    (u.(r - c), v.(r - c)) instead
  *   array layout     component-major ("[3][S]" means 3 rows of S items); every
  *                    array pointer is a DEVICE pointer owned by the caller
  *   hits             CSR over tracks: hits of track t are hit_offsets[t] ..
  *                    hit_offsets[t+1]-1, in the order the track crosses them
- *   seed surface     the starting parameters live on one surface (kf_seeds);
+ *   seed surface     the starting parameters live on one plane (kf_seeds);
  *                    the fitted parameters are returned on that same surface
- *                    (it is the fit's target surface)
+ *                    (it is the fit's target surface) unless kf_config.target
+ *                    asks for the perigee
  *
  * Execution: every entry point validates its arguments on the host before any
  * device work, then enqueues kernels on `stream` (a hipStream_t, NULL = the

@@ -366,6 +366,8 @@ __device__ bool bwd_two_filter(const FitArgs& a, const double* __restrict__ sm, 
     fl.init(a.field);
     int fail = ST_OK;
     double xb[6], Cb[21];
+    // surface types from the LDS table (the azimuth of a disc hit wraps)
+    const bool ang_last = is_disc(sm + a.sid[o + n - 1] * SURF_STRIDE);
     {
         double* w = wl + (n - 1) * (NW * TILE);
         double xp[6], Cp[21], m[2], V[3], x[6], C[21], ck;
@@ -375,14 +377,14 @@ __device__ bool bwd_two_filter(const FitArgs& a, const double* __restrict__ sm, 
         for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
         load_rows(a.loc + o + n - 1, H, m);
         load_rows(a.cov + o + n - 1, H, V);
-        kalman_update(xp, Cp, m, V, x, C, &ck, disc_hit(a, o, n - 1));
+        kalman_update(xp, Cp, m, V, x, C, &ck, ang_last);
 #pragma unroll
         for (int i = 0; i < 6; ++i) w[(OFF_XP + i) * TILE] = x[i];
 #pragma unroll
         for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = C[q];
 #pragma unroll
         for (int q = 0; q < 21; ++q) C[q] *= a.bwd_scale;
-        if (kalman_update(x, C, m, V, xb, Cb, &ck, disc_hit(a, o, n - 1)) != ST_OK) fail = ST_NOT_SPD;
+        if (kalman_update(x, C, m, V, xb, Cb, &ck, ang_last) != ST_OK) fail = ST_NOT_SPD;
     }
     int s1 = a.sid[o + n - 1];
     double xs[6], Cs[21];
@@ -390,7 +392,7 @@ __device__ bool bwd_two_filter(const FitArgs& a, const double* __restrict__ sm, 
         double xf[6], Cf[21], m[2], V[3];
         int s0 = a.seed_sid;
         double* w = wl + (k >= 0 ? k : 0) * (NW * TILE);
-        const bool ang = k >= 0 && disc_hit(a, o, k);
+        const bool ang = k >= 0 && is_disc(sm + a.sid[o + k] * SURF_STRIDE);
         if (k >= 0) {
             double xp[6], Cp[21], ck;
 #pragma unroll
