@@ -48,6 +48,7 @@ WORKLOADS = {
     5: "solenoid B=2T(1-0.1(z/1m)^2), 30 planes, pT log-uniform 0.5-100 GeV, |eta|<2.5, ragged 8-30 hits",
     6: "the tracks of C5 with the field as a map: the solenoid sampled every 25 mm (41x81x481 points, "
        "38 MB), trilinear",
+    7: "C2 measured on discs: polar hits (r, phi) about centres 100 mm off the tracks, phi straddling +-pi",
 }
 
 
@@ -247,7 +248,8 @@ def main():
                           "(PCIe-inclusive; not the headline value)"}
 
     adjoint = None
-    if not args.no_adjoint and int(ev.field.kind) != kfmi.KF_FIELD_MAP:   # the adjoint needs an analytic field
+    if (not args.no_adjoint and int(ev.field.kind) != kfmi.KF_FIELD_MAP    # the adjoint needs an analytic
+            and getattr(ev.detector, "stype", None) is None):              # field and planes
         rng_g = np.random.default_rng(1)
         g_chi2 = torch.ones(N, dtype=torch.float64, device=dev)
         g_par = torch.as_tensor(rng_g.standard_normal((6, ev.n_hits)), device=dev)

@@ -52,9 +52,9 @@ def lib():
         fit_args = [i, P, P, P, P, i, P, P, P, P, i, P, d, P, P, i, i, d, d, d, i]
         L.kfo_fit.argtypes = fit_args + [P] * 12 + [i, i, d, i, P, P]
         L.kfo_fit.restype = i
-        L.kfo_fit_vjp.argtypes = fit_args + [P] * 6 + [i]
+        L.kfo_fit_vjp.argtypes = fit_args + [P] * 6 + [i, P]
         L.kfo_fit_vjp.restype = i
-        L.kfo_count_ops.argtypes = fit_args + [P]
+        L.kfo_count_ops.argtypes = fit_args + [P, P]
         L.kfo_count_ops.restype = i
         L.kfo_transport.argtypes = [i, P, P, P, i, P, d, d, d, d, i, i, i, P, P, P, P, P]
         L.kfo_transport.restype = i
@@ -191,7 +191,7 @@ def fit_vjp(ev, g_chi2, g_par=None, g_tgt=None, n_threads: int = 0, **kw):
     g_align = np.zeros((6, a.S))
     g_seed = np.zeros((6, a.N))
     lib().kfo_fit_vjp(*a.args, _p(g_chi2), _p(g_par), _p(g_tgt), _p(g_meas), _p(g_align), _p(g_seed),
-                      int(n_threads))
+                      int(n_threads), _p(a.keep["stype"]))
     return g_meas, g_align, g_seed
 
 
@@ -199,7 +199,7 @@ def count_ops(ev, **kw) -> np.ndarray:
     """(N, 5) non-trivial op counts per track: add/sub, mul, div, sqrt, transcendental."""
     a = _Args(ev, **kw)
     out = np.zeros((a.N, 5), dtype=np.int64)
-    lib().kfo_count_ops(*a.args, _p(out))
+    lib().kfo_count_ops(*a.args, _p(out), _p(a.keep["stype"]))
     return out
 
 

@@ -1372,9 +1372,10 @@ int kfo_fit_vjp(int n_tracks, const int32_t* off, const int32_t* sid, const doub
                 const double* seed, const double* seed_cov, int seed_sid,
                 int ms, double mass, double tol, double land_tol, int max_steps,
                 const double* g_chi2, const double* g_par, const double* g_tgt,
-                double* g_meas, double* g_align, double* g_seed, int n_threads) {
+                double* g_meas, double* g_align, double* g_seed, int n_threads, const int32_t* stype) {
     Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, align, field_kind, b0, field_a,
                             seed, seed_cov, seed_sid, ms, mass, tol, land_tol, max_steps);
+    in.stype = stype;
     // derivatives are taken with respect to the alignment correction itself:
     // every pass rebuilds each surface from its nominal placement
     std::vector<Surf<double>> surf(n_surf);
@@ -1453,15 +1454,18 @@ int kfo_count_ops(int n_tracks, const int32_t* off, const int32_t* sid, const do
                   int n_surf, const double* center, const double* rot, const double* x0, const double* align,
                   int field_kind, const double* b0, double field_a,
                   const double* seed, const double* seed_cov, int seed_sid,
-                  int ms, double mass, double tol, double land_tol, int max_steps, int64_t* counts) {
+                  int ms, double mass, double tol, double land_tol, int max_steps, int64_t* counts,
+                  const int32_t* stype) {
     Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, align, field_kind, b0, field_a,
                             seed, seed_cov, seed_sid, ms, mass, tol, land_tol, max_steps);
+    in.stype = stype;
     std::vector<Surf<Cnt>> surf(n_surf);
     for (int s = 0; s < n_surf; ++s) {
         Surf<double> d = surf_d(in, s);
         for (int i = 0; i < 3; ++i) surf[s].c[i] = d.c[i];
         for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) surf[s].R[i][j] = d.R[i][j];
         surf[s].x0 = d.x0;
+        surf[s].type = d.type;
     }
     const int64_t H = in.H;
     for (int t = 0; t < n_tracks; ++t) {
