@@ -54,6 +54,15 @@ def test_discs_other_options(kf):
     bad.detector.stype[0] = 1
     out = _fit(kf, bad)
     assert np.all(out.status.cpu().numpy() == kf.KF_ST_BAD_INPUT)
+    # an unknown type on a hit surface fails the tracks that cross it, as in the oracle
+    odd = synth.telescope_event(300, 71, ragged=(4, 8), center_offset=(0.0, 100.0, 0.0), discs=True)
+    odd.detector.stype = odd.detector.stype.copy()
+    odd.detector.stype[4] = 2
+    out = _fit(kf, odd)
+    ref = _ref(odd)
+    st = out.status.cpu().numpy()
+    assert np.array_equal(st, ref.status) and np.any(st == kf.KF_ST_BAD_INPUT) and np.any(st == 0)
+    compare(out, ref, label="C7 unknown type on surface 4")
 
 
 def test_discs_full_size_sampled(kf):
