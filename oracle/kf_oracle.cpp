@@ -23,7 +23,12 @@
 //     runs from the last hit back to the seed surface, propagating against the
 //     direction of flight, and its predictions are combined with the forward
 //     filtered states;
-//   * the chi2 is built from measurement residuals (Sect. 2).
+//   * the chi2 is built from measurement residuals (Sect. 2);
+//   * optionally the fitted state is carried to the perigee of a line
+//     parallel to z (the parameters Sect. 5.2 quotes), the field is read
+//     from a tabulated map with trilinear interpolation (the stored field
+//     information of Sect. 4.1), and measuring surfaces are discs with polar
+//     local coordinates (a second surface type).
 // The paper defers the formulas to the works it cites (Kalman filter for
 // track fitting, RTS smoother, Runge-Kutta-Nystrom of Myrheim and Bugge);
 // the textbook forms are written out below.  Where the paper is silent the
@@ -38,10 +43,13 @@
 // value part only.
 //
 // Pins (tests/test_oracle_*.py): joint-Gaussian conditioning for the linear
-// filter+smoother core, straight-line closed forms for B = 0, the exact helix
-// for uniform B, finite differences for every Jacobian, Gauss-Newton least
-// squares for a field-free fit, pull and chi2 statistics, envelope theorem and
-// finite differences for the gradients.
+// filter+smoother core (and, with a weak prior as one more observation, for
+// the two-filter smoother), straight-line closed forms for B = 0, the exact
+// helix for uniform B, DOP853 for the solenoid (also to the perigee), scipy's
+// grid interpolator for the map, finite differences for every Jacobian,
+// Gauss-Newton least squares for a field-free fit, pull and chi2 statistics
+// (planes, discs, perigee), envelope theorem and finite differences for the
+// gradients.
 
 #include <cmath>
 #include <cstdint>
