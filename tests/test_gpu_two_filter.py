@@ -111,3 +111,16 @@ def test_two_filter_autotuner_and_graph(kf):
         for n, v in ref_t.items():
             assert torch.equal(getattr(g.out, n), v), (rep, n)
     g.release()
+
+
+def test_two_filter_and_perigee_solenoid_sampled(kf):
+    """The solenoid workload at 2e5 tracks with the two-filter smoother and
+    the perigee target together, checked on sampled tracks."""
+    _announce("C5 2e5 tracks, two-filter + perigee, sampled parity")
+    ev = synth.make_config(5, 200_000)
+    out = _fit(kf, ev, smoother=TWO, target=1, perigee=(0.0, 0.0, 0.0))
+    rng = np.random.default_rng(55)
+    idx = np.unique(np.concatenate([[0, ev.n_tracks - 1], rng.choice(ev.n_tracks, 400, replace=False)]))
+    ref = attach_offsets(oracle.fit(ev.subset(idx), extras=True, smoother="two_filter", perigee=np.zeros(3)),
+                         ev.subset(idx))
+    compare(_sampled(out, ev, idx), ref, tol=TOL[5], label="C5 two-filter perigee sampled")
