@@ -73,6 +73,20 @@ def lib():
         L.kfo_set_field_map.argtypes = [P, P, P, P]
         L.kfo_set_field_map.restype = i
         L.kfo_version.restype = C.c_char_p
+        L.kfo_count_update.argtypes = [P] * 5
+        L.kfo_count_update.restype = i
+        L.kfo_count_rts_step.argtypes = [P] * 8
+        L.kfo_count_rts_step.restype = i
+        L.kfo_count_transport.argtypes = [i, P, P, P, i, P, d, d, d, d, i, i, i, P, P, P, P]
+        L.kfo_count_transport.restype = i
+        L.kfo_count_rkn_step.argtypes = [i, P, d, d, P, d, P]
+        L.kfo_count_rkn_step.restype = i
+        L.kfo_count_units.argtypes = fit_args + [P, i, P, P]
+        L.kfo_count_units.restype = i
+        L.kfo_count_ms_noise.argtypes = [i, P, P, P, i, P, d, P]
+        L.kfo_count_ms_noise.restype = i
+        L.kfo_count_cov_transport.argtypes = [P, P, P, P]
+        L.kfo_count_cov_transport.restype = i
         _lib = L
     return _lib
 
@@ -200,6 +214,74 @@ def count_ops(ev, **kw) -> np.ndarray:
     a = _Args(ev, **kw)
     out = np.zeros((a.N, 5), dtype=np.int64)
     lib().kfo_count_ops(*a.args, _p(out), _p(a.keep["stype"]))
+    return out
+
+
+UNITS = ("seed check", "scatterer noise", "transport", "F (C+Q) F^T", "update", "chi2 sum", "RTS smoother")
+
+
+def count_units(ev, t, **kw):
+    """(status, units (7, 5), total (5,)) for track t: the counts of each unit of
+    its fit (UNITS order; columns as count_ops) on the fit's own states, and the
+    count of the whole fit."""
+    a = _Args(ev, **kw)
+    units = np.zeros((7, 5), dtype=np.int64)
+    total = np.zeros(5, dtype=np.int64)
+    st = lib().kfo_count_units(*a.args, _p(a.keep["stype"]), int(t), _p(units), _p(total))
+    return st, units, total
+
+
+def count_update(xp, Cp, m, V3):
+    """(status, counts (5,)) of one gain-matrix update: xp (6,), Cp (6,6), m (2,), V3 = (v00, v01, v11)."""
+    out = np.zeros(5, dtype=np.int64)
+    st = lib().kfo_count_update(_p(_f64(xp)), _p(_f64(Cp)), _p(_f64(m)), _p(_f64(V3)), _p(out))
+    return st, out
+
+
+def count_rts_step(xf, Cf, F, xp1, Cp1, xs1, Cs1):
+    """(status, counts (5,)) of one RTS step (6-vectors and 6x6 matrices)."""
+    out = np.zeros(5, dtype=np.int64)
+    st = lib().kfo_count_rts_step(*[_p(_f64(a)) for a in (xf, Cf, F, xp1, Cp1, xs1, Cs1)], _p(out))
+    return st, out
+
+
+def count_transport(det, field, sa, sb, x, mass=0.1056583755, tol=DEFAULT_TOL, land_tol=DEFAULT_LAND_TOL,
+                    max_steps=DEFAULT_MAX_STEPS):
+    """(status, counts (5,), trials) of one bound-to-bound transport."""
+    _use_field(field)
+    center, rot, x0 = _f64(det.center), _f64(det.rot), _f64(det.x_over_X0)
+    b0, xi = _f64(field.b0), _f64(x)
+    out = np.zeros(5, dtype=np.int64)
+    tr = np.zeros(1, np.int32)
+    stype = None if getattr(det, "stype", None) is None else _i32(det.stype)
+    st = lib().kfo_count_transport(center.shape[1], _p(center), _p(rot), _p(x0), int(field.kind), _p(b0),
+                                   float(field.a), float(mass), float(tol), float(land_tol), int(max_steps),
+                                   int(sa), int(sb), _p(xi), _p(tr), _p(stype), _p(out))
+    return st, out, int(tr[0])
+
+
+def count_ms_noise(det, s, x, mass=0.1056583755):
+    """counts (5,) of the thin-scatterer noise of surface s at bound state x."""
+    center, rot, x0 = _f64(det.center), _f64(det.rot), _f64(det.x_over_X0)
+    out = np.zeros(5, dtype=np.int64)
+    lib().kfo_count_ms_noise(center.shape[1], _p(center), _p(rot), _p(x0), int(s), _p(_f64(x)), float(mass),
+                             _p(out))
+    return out
+
+
+def count_cov_transport(F, C, Q):
+    """counts (5,) of F (C + Q) F^T as the track fit forms it (6x6 each)."""
+    out = np.zeros(5, dtype=np.int64)
+    lib().kfo_count_cov_transport(_p(_f64(F)), _p(_f64(C)), _p(_f64(Q)), _p(out))
+    return out
+
+
+def count_rkn_step(field, F, h, mass=0.1056583755):
+    """counts (5,) of one RKN step of the free state at fixed h."""
+    _use_field(field)
+    out = np.zeros(5, dtype=np.int64)
+    lib().kfo_count_rkn_step(int(field.kind), _p(_f64(field.b0)), float(field.a), float(mass), _p(_f64(F)),
+                             float(h), _p(out))
     return out
 
 

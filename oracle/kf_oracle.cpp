@@ -1498,6 +1498,241 @@ int kfo_count_ops(int n_tracks, const int32_t* off, const int32_t* sid, const do
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// operation counts of single routines (pins of the counting scalar)
+// ---------------------------------------------------------------------------
+namespace kfo {
+inline void put_counts(int64_t* counts) {
+    counts[0] = g_cnt.add; counts[1] = g_cnt.mul; counts[2] = g_cnt.div;
+    counts[3] = g_cnt.sqrt; counts[4] = g_cnt.trans;
+}
+}  // namespace kfo
+
+extern "C" {
+
+// Counts of one gain-matrix update (H = [I2 0]): xp[6], Cp[6][6], m[2], V
+// (v00, v01, v11).  counts[5] as kfo_count_ops.  Returns the update's status.
+int kfo_count_update(const double* xp, const double* Cp, const double* m, const double* V3, int64_t* counts) {
+    Cnt x[6], C[6][6], mm[2] = {m[0], m[1]}, V[2][2] = {{V3[0], V3[1]}, {V3[1], V3[2]}}, xf[6], Cf[6][6], c2;
+    for (int i = 0; i < 6; ++i) { x[i] = xp[i]; for (int j = 0; j < 6; ++j) C[i][j] = Cp[6 * i + j]; }
+    g_cnt = Counts();
+    int st = kalman_update(x, C, mm, V, xf, Cf, &c2);
+    put_counts(counts);
+    return st;
+}
+
+// Counts of one RTS step: the filtered state (xf, Cf) of k, the transport F
+// from k to k+1, the prediction (xp1, Cp1) and the smoothed state (xs1, Cs1)
+// of k+1 (6 / 36 values each, row-major).
+int kfo_count_rts_step(const double* xf, const double* Cf, const double* F, const double* xp1, const double* Cp1,
+                       const double* xs1, const double* Cs1, int64_t* counts) {
+    Cnt a[6], A[6][6], Fm[6][6], b[6], B[6][6], c[6], Cc[6][6], xs[6], Cs[6][6];
+    for (int i = 0; i < 6; ++i) {
+        a[i] = xf[i]; b[i] = xp1[i]; c[i] = xs1[i];
+        for (int j = 0; j < 6; ++j) {
+            A[i][j] = Cf[6 * i + j]; Fm[i][j] = F[6 * i + j]; B[i][j] = Cp1[6 * i + j]; Cc[i][j] = Cs1[6 * i + j];
+        }
+    }
+    g_cnt = Counts();
+    int st = rts_step(a, A, Fm, b, B, c, Cc, xs, Cs);
+    put_counts(counts);
+    return st;
+}
+
+// Counts of one bound-to-bound transport (arguments as kfo_transport).
+int kfo_count_transport(int n_surf, const double* center, const double* rot, const double* x0, int field_kind,
+                        const double* b0, double field_a, double mass, double tol, double land_tol, int max_steps,
+                        int sa, int sb, const double* x, int32_t* trials, const int32_t* stype, int64_t* counts) {
+    Inputs in = make_inputs(0, nullptr, nullptr, nullptr, nullptr, n_surf, center, rot, x0, nullptr, field_kind, b0,
+                            field_a, nullptr, nullptr, 0, 0, mass, tol, land_tol, max_steps);
+    in.stype = stype;
+    Surf<Cnt> A, B;
+    for (int k = 0; k < 2; ++k) {
+        Surf<double> d = surf_d(in, k == 0 ? sa : sb);
+        Surf<Cnt>& o = k == 0 ? A : B;
+        for (int i = 0; i < 3; ++i) o.c[i] = d.c[i];
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) o.R[i][j] = d.R[i][j];
+        o.x0 = d.x0;
+        o.type = d.type;
+    }
+    Cnt xi[6], xr[6], Fk[6][6];
+    for (int i = 0; i < 6; ++i) xi[i] = x[i];
+    int tr = 0;
+    g_cnt = Counts();
+    int st = transport(in.field, in.cfg, A, B, xi, xr, Fk, &tr);
+    put_counts(counts);
+    *trials = tr;
+    return st;
+}
+
+// Counts of the thin-scatterer noise of surface s for the bound state x.
+int kfo_count_ms_noise(int n_surf, const double* center, const double* rot, const double* x0, int s,
+                       const double* x, double mass, int64_t* counts) {
+    Inputs in = make_inputs(0, nullptr, nullptr, nullptr, nullptr, n_surf, center, rot, x0, nullptr, 0, center, 0.0,
+                            nullptr, nullptr, 0, 1, mass, 0.0, 0.0, 0);
+    Surf<double> d = surf_d(in, s);
+    Surf<Cnt> sf;
+    for (int i = 0; i < 3; ++i) sf.c[i] = d.c[i];
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) sf.R[i][j] = d.R[i][j];
+    sf.x0 = d.x0;
+    Cnt xi[6], Q[6][6];
+    for (int i = 0; i < 6; ++i) xi[i] = x[i];
+    g_cnt = Counts();
+    ms_noise(sf, xi, mass, Q);
+    put_counts(counts);
+    return 0;
+}
+
+// Counts of the covariance prediction F (C + Q) F^T as the track fit forms it
+// (F, C, Q: 6x6 row-major).
+int kfo_count_cov_transport(const double* F, const double* C, const double* Q, int64_t* counts) {
+    Cnt Fk[6][6], CQ[6][6], T1[6][6], Ft[6][6], Cp[6][6];
+    for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) Fk[i][j] = F[6 * i + j];
+    g_cnt = Counts();
+    for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) CQ[i][j] = Cnt(C[6 * i + j]) + Cnt(Q[6 * i + j]);
+    matmul(Fk, CQ, T1);
+    transpose(Fk, Ft);
+    matmul(T1, Ft, Cp);
+    put_counts(counts);
+    return 0;
+}
+
+// Per-unit counts of the fit of track t (RTS smoother, fitted state on the
+// seed surface).  The FP64 fit gives the track's states; each unit of the fit
+// is then counted on those very states (full, unsymmetrised matrices):
+//   units[0] seed covariance check (its Cholesky factor)
+//   units[1] scatterer noise        units[2] transport (RKN steps, Jacobian)
+//   units[3] F (C + Q) F^T          units[4] gain-matrix update
+//   units[5] chi2 sum               units[6] RTS smoother steps
+// total receives the count of the whole fit (kfo_count_ops for this track).
+// Returns the track's status.
+int kfo_count_units(int n_tracks, const int32_t* off, const int32_t* sid, const double* loc, const double* cov,
+                    int n_surf, const double* center, const double* rot, const double* x0, const double* align,
+                    int field_kind, const double* b0, double field_a,
+                    const double* seed, const double* seed_cov, int seed_sid,
+                    int ms, double mass, double tol, double land_tol, int max_steps, const int32_t* stype, int t,
+                    int64_t* units, int64_t* total) {
+    Inputs in = make_inputs(n_tracks, off, sid, loc, cov, n_surf, center, rot, x0, align, field_kind, b0, field_a,
+                            seed, seed_cov, seed_sid, ms, mass, tol, land_tol, max_steps);
+    in.stype = stype;
+    std::vector<Surf<double>> sd(n_surf);
+    std::vector<Surf<Cnt>> sc(n_surf);
+    for (int s = 0; s < n_surf; ++s) {
+        sd[s] = surf_d(in, s);
+        for (int i = 0; i < 3; ++i) sc[s].c[i] = sd[s].c[i];
+        for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) sc[s].R[i][j] = sd[s].R[i][j];
+        sc[s].x0 = sd[s].x0;
+        sc[s].type = sd[s].type;
+    }
+    const int64_t H = in.H;
+    const int o = off[t], n = off[t + 1] - off[t];
+    std::vector<double> md(2 * n), V(3 * n);
+    std::vector<Cnt> mc(2 * n);
+    for (int k = 0; k < n; ++k) {
+        md[2 * k] = loc[o + k]; md[2 * k + 1] = loc[H + o + k];
+        mc[2 * k] = md[2 * k]; mc[2 * k + 1] = md[2 * k + 1];
+        for (int a = 0; a < 3; ++a) V[3 * k + a] = cov[a * H + o + k];
+    }
+    double xd[6], c21[21];
+    Cnt xc[6];
+    for (int i = 0; i < 6; ++i) { xd[i] = seed[i * n_tracks + t]; xc[i] = xd[i]; }
+    for (int i = 0; i < 21; ++i) c21[i] = seed_cov[i * n_tracks + t];
+    for (int u = 0; u < 7 * 5; ++u) units[u] = 0;
+    // the whole fit, counted
+    g_cnt = Counts();
+    TrackOut<Cnt> rc;
+    fit_track(in.field, in.cfg, sc.data(), n_surf, n, sid + o, mc.data(), V.data(), xc, c21, seed_sid, rc);
+    put_counts(total);
+    // the fit's states in FP64
+    TrackOut<double> r;
+    int st = fit_track(in.field, in.cfg, sd.data(), n_surf, n, sid + o, md.data(), V.data(), xd, c21, seed_sid, r);
+    if (st != ST_OK) return st;
+    auto add_unit = [&](int u) {
+        units[5 * u + 0] += g_cnt.add; units[5 * u + 1] += g_cnt.mul; units[5 * u + 2] += g_cnt.div;
+        units[5 * u + 3] += g_cnt.sqrt; units[5 * u + 4] += g_cnt.trans;
+        g_cnt = Counts();
+    };
+    auto to_cnt = [](const double* a36, Cnt (&M)[6][6]) {
+        for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) M[i][j] = a36[6 * i + j];
+    };
+    double C0d[6][6];
+    unpack21(c21, C0d);
+    Cnt C0[6][6], L0[6][6];
+    for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) C0[i][j] = C0d[i][j];
+    g_cnt = Counts();
+    cholesky6(C0, L0);
+    add_unit(0);
+    // forward filter, unit by unit, from the FP64 states
+    std::vector<Cnt> Fst(36 * n);
+    Cnt chi2 = 0.0;
+    for (int k = 0; k < n; ++k) {
+        const int prev = k == 0 ? seed_sid : sid[o + k - 1];
+        Cnt x[6], C[6][6];
+        for (int i = 0; i < 6; ++i) {
+            x[i] = k == 0 ? xd[i] : r.xf[6 * (k - 1) + i];
+            for (int j = 0; j < 6; ++j) C[i][j] = k == 0 ? C0d[i][j] : r.Cf[36 * (k - 1) + 6 * i + j];
+        }
+        Cnt Q[6][6];
+        if (in.cfg.ms) ms_noise(sc[prev], x, mass, Q);
+        else for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) Q[i][j] = 0.0;
+        add_unit(1);
+        Cnt xp[6], Fk[6][6];
+        int tr = 0;
+        transport(in.field, in.cfg, sc[prev], sc[sid[o + k]], x, xp, Fk, &tr);
+        add_unit(2);
+        Cnt CQ[6][6], T1[6][6], Ft[6][6], Cp[6][6];
+        for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) CQ[i][j] = C[i][j] + Q[i][j];
+        matmul(Fk, CQ, T1);
+        transpose(Fk, Ft);
+        matmul(T1, Ft, Cp);
+        add_unit(3);
+        Cnt xpk[6], Cpk[6][6], mk[2] = {mc[2 * k], mc[2 * k + 1]};
+        for (int i = 0; i < 6; ++i) xpk[i] = r.xp[6 * k + i];
+        to_cnt(&r.Cp[36 * k], Cpk);
+        const double* v = &V[3 * k];
+        Cnt Vk[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
+        Cnt xf[6], Cf[6][6], ck;
+        kalman_update(xpk, Cpk, mk, Vk, xf, Cf, &ck, sc[sid[o + k]].type == 1);
+        add_unit(4);
+        chi2 = chi2 + ck;
+        add_unit(5);
+        for (int q = 0; q < 36; ++q) Fst[36 * k + q] = Fk[q / 6][q % 6];
+    }
+    // RTS smoother from the FP64 states
+    for (int k = n - 2; k >= -1; --k) {
+        Cnt xf[6], Cf[6][6], F[6][6], xp1[6], Cp1[6][6], xs1[6], Cs1[6][6], xs[6], Cs[6][6];
+        for (int i = 0; i < 6; ++i) {
+            xf[i] = k >= 0 ? r.xf[6 * k + i] : xd[i];
+            xp1[i] = r.xp[6 * (k + 1) + i];
+            xs1[i] = r.xs[6 * (k + 1) + i];
+            for (int j = 0; j < 6; ++j) {
+                Cf[i][j] = k >= 0 ? r.Cf[36 * k + 6 * i + j] : C0d[i][j];
+                F[i][j] = Fst[36 * (k + 1) + 6 * i + j];
+                Cp1[i][j] = r.Cp[36 * (k + 1) + 6 * i + j];
+                Cs1[i][j] = r.Cs[36 * (k + 1) + 6 * i + j];
+            }
+        }
+        rts_step(xf, Cf, F, xp1, Cp1, xs1, Cs1, xs, Cs, sc[sid[o + k + 1]].type == 1,
+                 k >= 0 && sc[sid[o + k]].type == 1);
+        add_unit(6);
+    }
+    return ST_OK;
+}
+
+// Counts of one RKN step of the free state F[8] at fixed h (kfo_rkn_step).
+int kfo_count_rkn_step(int field_kind, const double* b0, double field_a, double mass, const double* F, double h,
+                       int64_t* counts) {
+    FieldDef f; f.kind = field_kind; for (int i = 0; i < 3; ++i) f.b0[i] = b0[i]; f.a = field_a; f.map = &g_map;
+    Cnt Fi[8], Fo[8], Dm[8][8];
+    for (int i = 0; i < 8; ++i) Fi[i] = F[i];
+    g_cnt = Counts();
+    rkn_step(f, mass, Fi, Cnt(h), Fo, Dm);
+    put_counts(counts);
+    return 0;
+}
+
+}  // extern "C"
+
 extern "C" {
 // Multiple-scattering process noise Q (6x6, row-major) for bound state x on surface s.
 int kfo_ms_noise(int n_surf, const double* center, const double* rot, const double* x0, int s,
