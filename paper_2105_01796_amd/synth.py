@@ -24,6 +24,8 @@ Conventions (shared *by definition* with the fitters, not by code):
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field as dc_field
 import numpy as np
 
@@ -412,6 +414,39 @@ def telescope_event(n_tracks, seed, n_planes=10, bz=2.0, x_over_X0=0.0, ms=False
     return _to_discs(ev) if discs else ev
 
 
+def _integrate_slice(st, lam, xs, pitch, substeps, b0z, a, min_nT):
+    """Truth states at every plane for the rows of `st`: (reach, states (6, M, P))."""
+    M, P = st.shape[1], len(xs)
+    alive = np.ones(M, dtype=bool)
+    reach = np.zeros(M, dtype=np.int64)
+    hs = np.zeros((6, M, P))
+    for j in range(P):
+        x0 = xs[j]
+        h = pitch / substeps
+        for k in range(substeps):
+            st = _rk4_x(st, lam, x0 + k * h, h, b0z, a, M_MU)
+            alive &= st[3] >= min_nT
+            st[3] = np.where(alive, st[3], 1.0)   # keep dead rows finite
+        reach += alive
+        tn = np.sqrt(st[3] ** 2 + st[4] ** 2 + st[5] ** 2)
+        hs[:, :, j] = np.stack([st[0], st[1], np.arctan2(st[4], st[3]),
+                                np.arccos(st[5] / tn), lam, st[2]])
+    return reach, hs
+
+
+def _integrate_rows(st, lam, xs, pitch, substeps, b0z, a, min_nT, rows_per_task=32768):
+    """_integrate_slice over row blocks on a thread pool (numpy releases the
+    GIL in its array loops).  Every operation is elementwise per row, so the
+    result does not depend on the split."""
+    M = st.shape[1]
+    starts = list(range(0, M, rows_per_task))
+    workers = max(1, min(16, os.cpu_count() or 1, len(starts)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        parts = list(ex.map(lambda r0: _integrate_slice(st[:, r0:r0 + rows_per_task], lam[r0:r0 + rows_per_task], xs,
+                                                        pitch, substeps, b0z, a, min_nT), starts))
+    return np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts], axis=1)
+
+
 def solenoid_event(n_tracks, seed, n_planes=30, b0z=2.0, a=1e-7, nmin=8, p_hole=0.1,
                    min_nT=0.05, substeps=6, f_inf=1.0, pt_range=(0.5, 100.0), eta_max=2.5,
                    phi_max=0.1, name="solenoid"):
@@ -431,21 +466,8 @@ def solenoid_event(n_tracks, seed, n_planes=30, b0z=2.0, a=1e-7, nmin=8, p_hole=
         drawn += M
         st = np.stack([np.zeros(M), np.zeros(M), np.zeros(M),
                        np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)])
-        alive = np.ones(M, dtype=bool)
-        reach = np.zeros(M, dtype=np.int64)
-        hs = np.zeros((6, M, P))
         pitch = det.center[0, 1] - det.center[0, 0]
-        for j in range(P):
-            x0 = det.center[0, j]
-            h = pitch / substeps
-            for k in range(substeps):
-                st = _rk4_x(st, lam, x0 + k * h, h, b0z, a, M_MU)
-                alive &= st[3] >= min_nT
-                st[3] = np.where(alive, st[3], 1.0)   # keep dead rows finite
-            reach += alive
-            tn = np.sqrt(st[3] ** 2 + st[4] ** 2 + st[5] ** 2)
-            hs[:, :, j] = np.stack([st[0], st[1], np.arctan2(st[4], st[3]),
-                                    np.arccos(st[5] / tn), lam, st[2]])
+        reach, hs = _integrate_rows(st, lam, det.center[0, :P], pitch, substeps, b0z, a, min_nT)
         ok = reach >= nmin
         take = np.nonzero(ok)[0][: N - got]
         chunks.append((q[take], p[take], phi[take], theta[take], reach[take], hs[:, take]))
