@@ -38,9 +38,9 @@
  * Execution: every entry point validates its arguments on the host before any
  * device work, then enqueues kernels on `stream` (a hipStream_t, NULL = the
  * null stream) and returns without waiting.  Inputs must stay valid until the
- * stream reaches the work.  The library allocates device memory only for its
- * own small persistent tables; the caller passes a workspace of at least
- * kf_workspace_bytes().  Calls that share a workspace must not overlap.
+ * stream reaches the work.  The library allocates no device memory: the
+ * caller passes a workspace of at least kf_workspace_bytes().  Calls that
+ * share a workspace must not overlap.
  *
  * Errors: a negative return is an argument error found on the host before any
  * launch (nothing was enqueued), or KF_E_HIP if the HIP runtime refused a

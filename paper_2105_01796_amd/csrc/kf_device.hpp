@@ -325,18 +325,25 @@ __device__ inline P rkn_trial(const Field<P, FK>& fl, const P rabs[3], const P T
 
 // Transport-Jacobian update for an accepted step: the columns (l0, l1, phi,
 // theta, q/p) of d(free state)/d(bound start) are pushed through the stage
-// equations at fixed h (forward tangents).  d k_i/d(q/p) = k_i / (q/p).
+// equations at fixed h (forward tangents).  The explicit q/p dependence of a
+// stage is d k_i/d(q/p) = kappa T_i x B_i, formed as k_i / (q/p); for q/p = 0
+// exactly (no curvature: every stage direction is the step's start direction
+// T0) it is kappa T0 x B_i itself.
 // In a uniform field dk/dr = 0, so the l0 and l1 columns stay (u, v; 0, 0)
 // exactly and are neither stored nor propagated: columns start at JT0.
 template <int FK> struct TangentCols { static constexpr int J0 = (FK == FIELD_UNIFORM) ? 2 : 0; };
 template <class P, int FK>
 __device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& S, const P k[4][3], P lam, P h,
-                                   P Mr[3][5], P MT[3][5]) {
-    const P h2 = h * P(0.5), hh = h * h, lk = lam * P(kKappa), ilam = P(1) / lam;
-    P LB[3];
+                                   const P T0[3], P Mr[3][5], P MT[3][5]) {
+    const bool straight = lam == P(0);
+    const P h2 = h * P(0.5), hh = h * h, lk = lam * P(kKappa), ilam = straight ? P(0) : P(1) / lam;
+    P LB[3], kq0[3];
     if constexpr (FK == FIELD_UNIFORM) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) LB[i] = lk * fl.b[i];
+        cross(T0, fl.b, kq0);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) kq0[i] *= P(kKappa);
     }
 #pragma unroll
     for (int j = TangentCols<FK>::J0; j < 5; ++j) {
@@ -368,9 +375,24 @@ __device__ inline void rkn_tangent(const Field<P, FK>& fl, const Stages<P, FK>& 
 #pragma unroll
                 for (int i = 0; i < 3; ++i) c[i] = lk * (c[i] + c2[i]);
             }
+            P kq[3] = {P(0), P(0), P(0)};
+            if (j == 4) {
+                if constexpr (FK == FIELD_UNIFORM) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) kq[i] = straight ? kq0[i] : k[st][i] * ilam;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) kq[i] = k[st][i] * ilam;
+                    if (straight) {
+                        cross(T0, S.B[st], kq);
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) kq[i] *= P(kKappa);
+                    }
+                }
+            }
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                dk[i] = (j == 4) ? c[i] + k[st][i] * ilam : c[i];
+                dk[i] = (j == 4) ? c[i] + kq[i] : c[i];
                 if (st == 0) { sR[i] = dk[i]; sT[i] = dk[i]; }
                 else if (st < 3) { sR[i] += dk[i]; sT[i] += P(2) * dk[i]; }
                 else sT[i] += dk[i];
@@ -508,7 +530,7 @@ __device__ inline int transport(const Field<P, FK>& fl, const FieldDef& fd, cons
         V fac = V(0.9) * sqrt(sqrt(tol / (err > tiny ? err : tiny)));
         fac = fac < V(0.25) ? V(0.25) : (fac > V(4) ? V(4) : fac);
         if (err <= tol) {
-            rkn_tangent<P, FK>(fl, S, k, lam, h, Mr, MT);
+            rkn_tangent<P, FK>(fl, S, k, lam, h, T, Mr, MT);
             phase_boundary();
             const R hd = R(h);
             Mtl = Mtl + hd * gpd;
@@ -681,7 +703,7 @@ __device__ inline int transport_perigee(const FieldDef& fd, const Cfg& cfg, cons
         R fac = 0.9 * sqrt(sqrt(cfg.tol / (err > 1e-300 ? err : 1e-300)));
         fac = fac < 0.25 ? 0.25 : (fac > 4.0 ? 4.0 : fac);
         if (err <= cfg.tol) {
-            rkn_tangent<R, FK>(fl, S, k, lam, h, Mr, MT);
+            rkn_tangent<R, FK>(fl, S, k, lam, h, T, Mr, MT);
             phase_boundary();
             Mtl = Mtl + h * gpd;
 #pragma unroll

@@ -113,7 +113,7 @@ __device__ inline int gap_run(const Field<double, FK>& fl, const Cfg& cfg, int s
                 capped_out = capped;
                 return 1;
             }
-            rkn_tangent<double, FK>(fl, S, k, g.lam, h, g.Mr, g.MT);
+            rkn_tangent<double, FK>(fl, S, k, g.lam, h, T, g.Mr, g.MT);
             g.Mtl = g.Mtl + h * g.gpd;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -187,7 +187,9 @@ struct GapBar {
 template <int FK>
 __device__ inline void step_reverse(const Field<double, FK>& fl, const double* sb, const GapRun<FK>& g, double h,
                                     bool capped, const Stages<double, FK>& S, const double k[4][3], GapBar& gb) {
-    const double lam = g.lam, lk = lam * kKappa, ilam = 1.0 / lam;
+    // explicit q/p dependence of stage k_i: k_i / (q/p), or kappa T_i x B_i when q/p = 0
+    const bool straight = g.lam == 0.0;
+    const double lam = g.lam, lk = lam * kKappa, ilam = straight ? 0.0 : 1.0 / lam;
     double r[3], T[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -269,6 +271,12 @@ __device__ inline void step_reverse(const Field<double, FK>& fl, const double* s
                 cross(Ts[st], gs[st], c2);
 #pragma unroll
                 for (int i = 0; i < 3; ++i) dk[st][i] = lk * (c1[i] + c2[i]) + (j == 4 ? k[st][i] * ilam : 0.0);
+                if (j == 4 && straight) {
+                    double q[3];
+                    cross(Ts[st], Bs[st], q);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) dk[st][i] += kKappa * q[i];
+                }
             }
         }
         double Mrb[3], MTb[3], dkb[4][3], dTb[4][3], drb[4][3];
@@ -300,12 +308,17 @@ __device__ inline void step_reverse(const Field<double, FK>& fl, const double* s
                 e[i] = lk * dkb[st][i];
                 gbar[i] = 0.0;
             }
-            if (j == 4) {
+            if (j == 4 && !straight) {
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     kb[st][i] += dkb[st][i] * ilam;
                     gb.lam -= dkb[st][i] * k[st][i] * ilam * ilam;
                 }
+            } else if (j == 4) {
+                double eq[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) eq[i] = kKappa * dkb[st][i];
+                cross_vjp(Ts[st], Bs[st], eq, Tsb[st], Bsb[st]);
             }
             cross_vjp(dTs[st], Bs[st], e, dTb[st], Bsb[st]);
             cross_vjp(Ts[st], gs[st], e, Tsb[st], gbar);

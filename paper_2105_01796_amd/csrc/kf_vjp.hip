@@ -19,7 +19,7 @@
 //            the RKN stages, the tangent-column (transport Jacobian) update,
 //            the capped step sizes, the final move onto the plane and the
 //            local <-> global conversions (kf_gap_reverse.hpp); the small
-//            thin-scatterer noise term by dual numbers.
+//            thin-scatterer noise term by its closed-form derivative.
 //
 // Per-hit alignment contributions go to a [6][H + N] buffer; a deterministic
 // two-level reduction (fixed chunks summed in a fixed order, then a
@@ -630,7 +630,8 @@ VjpLayout vjp_layout(int64_t n_tracks, int64_t n_hits, int max_hits, int n_surf)
 }
 
 // Four waves per workgroup share one surface table while it and their four
-// stashes fit the LDS (up to 39 surfaces on gfx950); wider detectors run one
+// stashes fit the LDS (up to 36 surfaces on gfx950: 160 KiB less four
+// 78 x 64-double stashes leaves 4 KiB, 112 bytes per surface); wider detectors run one
 // wave per workgroup (fewer resident waves as the table grows).
 template <int FK, bool SORTED>
 hipError_t launch_vjp(const VjpArgs& a, hipStream_t stream) {

@@ -87,6 +87,24 @@ def test_vjp_matches_oracle(kf, cfg, n):
         _close(out.seed.cpu().numpy(), ref_s, f"C{cfg} sched {sched} seed")
 
 
+@pytest.mark.parametrize("bz", [0.0, 2.0])
+def test_vjp_zero_qop_seeds(kf, bz):
+    """Seeds with q/p = 0 exactly (straight first gap; with the field off
+    every gap is straight): the explicit q/p term of the stage derivatives is
+    kappa T x B, not k / (q/p)."""
+    _announce(f"vjp q/p = 0 seeds, Bz = {bz}")
+    ev = synth.telescope_event(60, 43, bz=bz)
+    ev.seed_par[4, :] = 0.0
+    g = _cotangents(ev, 43)
+    ref_m, ref_a, ref_s = oracle.fit_vjp(ev, *g)
+    for sched in (1, 2):
+        out = _gpu_vjp(kf, ev, g, schedule=sched)
+        assert np.all(out.status.cpu().numpy() == 0)
+        _close(out.meas.cpu().numpy(), ref_m, f"q/p=0 Bz={bz} sched {sched} meas")
+        _close(out.align.cpu().numpy(), ref_a, f"q/p=0 Bz={bz} sched {sched} align")
+        _close(out.seed.cpu().numpy(), ref_s, f"q/p=0 Bz={bz} sched {sched} seed")
+
+
 def test_vjp_wide_detector(kf):
     """60 planes (61 surfaces): past the per-lane-table limit of the alignment
     reduction, so the serial per-chunk reduction runs."""

@@ -1,6 +1,7 @@
 """HIP fit vs the CPU oracle, element by element, through the C ABI.
 
-FP64 path: relative 1e-9 per element (1e-8 for the solenoid workload; see
+FP64 path: relative 1e-9 per element (in the solenoid field the fitted loc1
+and theta variance on the seed plane are held to the FP64 floor, 1e-8; see
 parity.py), identical status and ndf, RKN trial counts identical on >= 99.9 %
 of hits.  Mixed path: parameters within 1e-3 sigma.
 Full-size runs (1e5 tracks, the benchmark's launch configuration) are checked
@@ -15,15 +16,19 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from parity import DIAG, attach_offsets, compare, par_err  # noqa: E402
+from parity import DIAG, SOLENOID_FLOOR_ROWS, attach_offsets, compare, par_err  # noqa: E402
 
 import oracle  # noqa: E402
 from paper_2105_01796_amd import synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-# FP64 relative bar per workload (see parity.py for the solenoid floor)
+# FP64 relative bar: 1e-9 per element; in the solenoid field the fitted loc1
+# and theta variance on the seed plane are held to the FP64 floor instead
+# (SOLENOID_FLOOR_ROWS, see parity.py).  TOL is the whole-result bar that the
+# smoother-variant and perigee modules still use for the solenoid.
 TOL = {1: 1e-9, 2: 1e-9, 3: 1e-9, 4: 1e-9, 5: 1e-8}
+FLOOR = {5: SOLENOID_FLOOR_ROWS}
 
 
 @pytest.fixture(scope="module")
@@ -66,7 +71,7 @@ def test_configs_fp64_small(kf, cfg, n):
     ev = synth.make_config(cfg, n)
     for sched in (1, 2):
         out = _fit(kf, ev, schedule=sched)
-        compare(out, _ref(ev), tol=TOL[cfg], label=f"C{cfg} sched {sched}")
+        compare(out, _ref(ev), floor_rows=FLOOR.get(cfg), label=f"C{cfg} sched {sched}")
 
 
 @pytest.mark.parametrize("cfg,n", [(2, 3000), (3, 3000), (5, 2000)])
@@ -79,7 +84,7 @@ def test_fused_one_wave_per_simd_shapes(kf, cfg, n):
     for sched, block in ((1, 256), (2, 256), (2, 64), (1, 128)):
         for prec in (kf.KF_PREC_FP64,):
             out = _fit(kf, ev, schedule=sched, block=block, occupancy=1, split_smoother=0, precision=prec)
-            compare(out, ref, tol=TOL[cfg], label=f"C{cfg} fused occ1 sched {sched} block {block}")
+            compare(out, ref, floor_rows=FLOOR.get(cfg), label=f"C{cfg} fused occ1 sched {sched} block {block}")
 
 
 @pytest.mark.parametrize("cfg,n", [(1, 100), (2, 3000), (3, 3000), (5, 2000)])
@@ -91,7 +96,7 @@ def test_recomputed_jacobians_fp64(kf, cfg, n):
     ref = _ref(ev)
     for sched, block, occ in ((1, 256, 1), (2, 64, 1), (2, 128, 2)):
         out = _fit(kf, ev, schedule=sched, block=block, occupancy=occ, jacobians=kf.KF_JAC_RECOMPUTE)
-        compare(out, ref, tol=TOL[cfg], label=f"C{cfg} recompute sched {sched} occ {occ}")
+        compare(out, ref, floor_rows=FLOOR.get(cfg), label=f"C{cfg} recompute sched {sched} occ {occ}")
 
 
 @pytest.mark.parametrize("cfg,n,chunks,streams", [(3, 3000, 5, 2), (5, 2000, 3, 3), (2, 1000, 1, 1), (1, 100, 200, 2)])
@@ -119,6 +124,24 @@ def test_field_free_and_misaligned_geometry(kf):
     # give the fitter the tilted/shifted planes the hits were simulated on
     out = _fit(kf, ev, detector=ev.detector_true)
     compare(out, _ref(ev, detector=ev.detector_true), label="misaligned")
+
+
+@pytest.mark.parametrize("bz", [0.0, 2.0])
+def test_zero_qop_seeds(kf, bz):
+    """Seeds with q/p = 0 exactly.  Field off: q/p is unobservable and stays 0,
+    so every gap is a straight line whose transport Jacobian has a zero q/p
+    column (no 0 * inf).  2 T: the first gap is straight, q/p then moves off 0
+    through the first update."""
+    _announce(f"q/p = 0 seeds, Bz = {bz}")
+    ev = synth.telescope_event(500, 41, bz=bz)
+    ev.seed_par[4, :] = 0.0
+    ref = _ref(ev)
+    assert np.all(ref.status == 0)
+    for sched in (1, 2):
+        compare(_fit(kf, ev, schedule=sched), ref, label=f"q/p=0 Bz={bz} sched {sched}")
+    out = _fit(kf, ev, precision=kf.KF_PREC_MIXED)
+    _, sp = par_err(out.tgt_par, ref.tgt_par, ref.tgt_cov)
+    assert np.array_equal(out.status.cpu().numpy(), ref.status) and sp.max() < 1e-3
 
 
 def _sampled(out, ev, idx):
@@ -151,7 +174,7 @@ def test_full_size_solenoid_sampled_fp64(kf):
     out = _fit(kf, ev)
     rng = np.random.default_rng(5)
     idx = np.unique(np.concatenate([[0, ev.n_tracks - 1], rng.choice(ev.n_tracks, 400, replace=False)]))
-    compare(_sampled(out, ev, idx), _ref(ev.subset(idx)), tol=TOL[5], label="C5 sampled")
+    compare(_sampled(out, ev, idx), _ref(ev.subset(idx)), floor_rows=FLOOR[5], label="C5 sampled")
 
 
 @pytest.mark.parametrize("cfg,n,jac", [(1, 100, 0), (2, 3000, 0), (3, 3000, 0), (5, 2000, 0), (2, 3000, 1),
