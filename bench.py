@@ -92,6 +92,25 @@ def host_threads() -> int:
     return max(1, n)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def step_stats(per):
+    """Mean, RMS spread (the paper's mean +- RMS over repeated runs), median,
+    min and max of the per-step times (ms)."""
+    import numpy as np
+    a = np.asarray(per, dtype=float)
+    return {"mean": float(a.mean()), "rms": float(a.std()), "median": float(np.median(a)),
+            "min": float(a.min()), "max": float(a.max()), "n": int(a.size)}
+
+
 def time_plan(plan, steps, warmup):
     import torch
     stream = torch.cuda.current_stream()
@@ -193,8 +212,9 @@ def main():
     mixed = None
     if not args.no_mixed:
         planm, tunedm = prepared_plan(kfmi.KF_PREC_MIXED)
-        msm, kmsm, _ = time_plan(planm, args.steps, args.warmup)
+        msm, kmsm, perm = time_plan(planm, args.steps, args.warmup)
         mixed = {"value": N / (msm * 1e-3), "ms_per_step": msm, "launch_ms": kmsm,
+                 "launch_ms_stats": step_stats(perm),
                  "speedup_vs_fp64": ms64 / msm, "launch": tunedm}
 
     two_filter = None
@@ -300,9 +320,23 @@ def main():
             if time.time() - t0 >= args.cpu_seconds:
                 break
         dt = time.time() - t0
+        # one thread on a smaller sample (about a quarter of the all-core time)
+        m1 = min(N, 2000)
+        sub1 = ev.subset(np.arange(m1))
+        t1 = time.time()
+        done1 = 0
+        while True:
+            oracle.fit(sub1, n_threads=1)
+            done1 += m1
+            if time.time() - t1 >= args.cpu_seconds / 4:
+                break
+        dt1 = time.time() - t1
         cpu = {"value": done / dt, "unit": "tracks/s", "cores": nth, "kind": "oracle",
                "sample": f"first {m} tracks of the same workload, fitted {done // m}x in {dt:.1f} s "
-                         f"(FP64 filter+smoother, OpenMP over tracks)"}
+                         f"(FP64 filter+smoother, OpenMP over tracks)",
+               "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+               "one_thread": {"value": done1 / dt1, "unit": "tracks/s",
+                              "sample": f"first {m1} tracks, fitted {done1 // m1}x in {dt1:.1f} s on 1 thread"}}
 
     out = {
         "metric": METRIC,
@@ -319,7 +353,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"C{args.config}: " + WORKLOADS[args.config], "tracks": N,
                    "hits": ev.n_hits, "precision": "fp64", "launch_ms": kms64,
-                   "launch_ms_min": min(per64), "tracks_ok": n_ok, "options": base_opt,
+                   "launch_ms_min": min(per64), "launch_ms_stats": step_stats(per64), "tracks_ok": n_ok,
+                   "options": base_opt,
                    "launch": tuned64, "graph": not args.no_graph,
                    "gen_seconds": round(t_gen, 2)},
         "mixed": mixed,

@@ -306,8 +306,13 @@ int kf_fit_tracks_staged(const kf_config *cfg, const kf_surfaces *surf, const kf
  * propagation of each gap is replayed with the forward pass's own step
  * decisions and reversed step by step (stages, transport-Jacobian columns,
  * step sizes capped at the target plane, landing, local <-> global maps), so
- * the gradient is that of the discrete fit the forward call computes.  Every step of
- * the adjoint runs in FP64 whatever cfg->precision says.  The alignment
+ * the gradient is that of the discrete fit the forward call computes.  The
+ * precision follows cfg->precision: with KF_PREC_FP64 every step is FP64;
+ * with KF_PREC_MIXED the forward recompute and the replay of each gap step in
+ * FP32 on the FP64 anchor exactly as the mixed fit does (same states, same
+ * step decisions), and everything else -- the reverse sweep through the
+ * steps, evaluated at the replayed states, the update, covariance and
+ * smoother algebra and every adjoint accumulation -- is FP64.  The alignment
  * gradient of a surface sums over all tracks in a fixed order: the result is
  * bitwise reproducible.  A track whose recomputed fit fails contributes
  * nothing to the alignment gradient and gets NaN in its meas and seed rows. */

@@ -1,4 +1,4 @@
-// kf_gap_reverse.hpp -- reverse mode through one propagation gap (FP64).
+// kf_gap_reverse.hpp -- reverse mode through one propagation gap.
 //
 // The gap maps the bound state x on surface a to the predicted state xp on
 // surface b and the transport Jacobian F (Sect. 4.1: adaptive RKN stepping,
@@ -9,7 +9,10 @@
 //
 // The step sequence is the forward pass's: gap_run replays the adaptive loop
 // with the same routines (rkn_trial, rkn_tangent) and the same expressions as
-// transport, so it takes the same decisions.  Reverse order: the final part
+// transport, in the same stepping precision P (double, or float for the mixed
+// fit: FP32 increments on the FP64 anchor), so it takes the same decisions.
+// Everything after the replay is FP64: each replayed state is widened and the
+// reverse sweep evaluates the derivatives there, accumulating in FP64.  Reverse order: the final part
 // (free -> bound, F, final move) at the landed state, then the accepted steps
 // from last to first, the state at the start of each recovered by replaying
 // the gap from its start (a few steps per gap, so the quadratic replay cost
@@ -29,26 +32,30 @@
 
 namespace kfm {
 
-// running state of a gap replay (FP64)
-template <int FK>
+// running state of a gap replay: the FP64 anchor (start state, straight-line
+// part rl of the position, time, d t / d(q/p)) and the increments and tangent
+// columns in the stepping precision P, as transport keeps them
+template <class P, int FK>
 struct GapRun {
     double r0[3], T0[3], nb[3];
     double lam, gd, gpd, d0;
-    double rl[3], dr[3], dT[3];
-    double dt, Mtl, hmag;
-    double Mr[3][5], MT[3][5];
+    double rl[3];
+    P dr[3], dT[3];
+    double dt, Mtl;
+    P hmag;
+    P Mr[3][5], MT[3][5];
     int trials, accepted;
 };
 
-// Start of the gap: bound -> free on surface a, initial tangents.
-template <int FK>
+// Start of the gap: bound -> free on surface a (a plane), initial tangents.
+template <class P, int FK>
 __device__ inline void gap_start(const Cfg& cfg, const double* sa, const double* sb, const double x[6],
-                                 GapRun<FK>& g) {
+                                 GapRun<P, FK>& g) {
     double sp, cp, st, ct;
     angle_sincos(x[2], &sp, &cp);
     angle_sincos(x[3], &st, &ct);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) g.r0[i] = sa[i] + x[0] * sa[3 + 3 * i + 0] + x[1] * sa[3 + 3 * i + 1];
+    for (int i = 0; i < 3; ++i) g.r0[i] = sa[i] + (x[0] * sa[3 + 3 * i + 0] + x[1] * sa[3 + 3 * i + 1]);
     g.T0[0] = cp * st; g.T0[1] = sp * st; g.T0[2] = ct;
     g.lam = x[4];
     g.gd = sqrt(1.0 + cfg.mass * cfg.mass * g.lam * g.lam) / kC;
@@ -56,76 +63,116 @@ __device__ inline void gap_start(const Cfg& cfg, const double* sa, const double*
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
 #pragma unroll
-        for (int j = 0; j < 5; ++j) { g.Mr[i][j] = 0.0; g.MT[i][j] = 0.0; }
+        for (int j = 0; j < 5; ++j) { g.Mr[i][j] = P(0); g.MT[i][j] = P(0); }
         if (TangentCols<FK>::J0 == 0) {
-            g.Mr[i][0] = sa[3 + 3 * i + 0];
-            g.Mr[i][1] = sa[3 + 3 * i + 1];
+            g.Mr[i][0] = P(sa[3 + 3 * i + 0]);
+            g.Mr[i][1] = P(sa[3 + 3 * i + 1]);
         }
     }
-    g.MT[0][2] = -(sp * st); g.MT[1][2] = cp * st; g.MT[2][2] = 0.0;
-    g.MT[0][3] = cp * ct;    g.MT[1][3] = sp * ct; g.MT[2][3] = -st;
+    g.MT[0][2] = P(-(sp * st)); g.MT[1][2] = P(cp * st); g.MT[2][2] = P(0);
+    g.MT[0][3] = P(cp * ct);    g.MT[1][3] = P(sp * ct); g.MT[2][3] = P(-st);
     g.Mtl = 0.0;
     g.nb[0] = sb[3 + 2]; g.nb[1] = sb[3 + 5]; g.nb[2] = sb[3 + 8];
     g.d0 = g.nb[0] * (sb[0] - g.r0[0]) + g.nb[1] * (sb[1] - g.r0[1]) + g.nb[2] * (sb[2] - g.r0[2]);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) { g.rl[i] = 0.0; g.dr[i] = 0.0; g.dT[i] = 0.0; }
+    for (int i = 0; i < 3; ++i) { g.rl[i] = 0.0; g.dr[i] = P(0); g.dT[i] = P(0); }
     g.dt = 0.0;
-    g.hmag = -1.0;
+    g.hmag = P(-1);
     g.trials = 0;
     g.accepted = 0;
 }
 
-// Replay the adaptive loop (the expressions of transport with P =
-// double).  Returns 1 when the accepted step number `stop` is reached, with
-// the state at its start and its h, capped flag, stages and k; 0 when the gap
-// has landed (state before the final move); -1 if the replay fails.
-template <int FK>
-__device__ inline int gap_run(const Field<double, FK>& fl, const Cfg& cfg, int stop, GapRun<FK>& g,
-                              double& h_out, bool& capped_out, Stages<double, FK>& S, double k[4][3]) {
-    const double tol = cfg.tol;
+// Replay the adaptive loop: the expressions of transport<P>, term for term.
+// Returns 1 when the accepted step number `stop` is reached, with the state
+// at its start and its h, capped flag, stages and k; 0 when the gap has
+// landed (state before the final move); -1 if the replay fails.
+template <class P, int FK>
+__device__ inline int gap_run(const Field<P, FK>& fl, const Cfg& cfg, int stop, GapRun<P, FK>& g,
+                              P& h_out, bool& capped_out, Stages<P, FK>& S, P k[4][3]) {
+    using R = double;
+    using V = P;
+    const V tol = V(cfg.tol);
+    const bool mixed = sizeof(V) < sizeof(double);
+    const P lam = P(g.lam);
     for (;;) {
-        double T[3], rabs[3], Td[3];
+        P T[3], rabs[3];
+        R Td[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            Td[i] = g.T0[i] + g.dT[i];
-            T[i] = Td[i];
-            rabs[i] = (g.r0[i] + g.rl[i]) + g.dr[i];
+            Td[i] = g.T0[i] + R(g.dT[i]);
+            T[i] = P(Td[i]);
+            rabs[i] = P(g.r0[i] + g.rl[i]) + g.dr[i];
         }
-        const double nTd = g.nb[0] * Td[0] + g.nb[1] * Td[1] + g.nb[2] * Td[2];
-        const double distd = g.d0 - (g.nb[0] * g.rl[0] + g.nb[1] * g.rl[1] + g.nb[2] * g.rl[2])
-                                  - (g.nb[0] * g.dr[0] + g.nb[1] * g.dr[1] + g.nb[2] * g.dr[2]);
+        const R nTd = g.nb[0] * Td[0] + g.nb[1] * Td[1] + g.nb[2] * Td[2];
+        const R distd = g.d0 - (g.nb[0] * g.rl[0] + g.nb[1] * g.rl[1] + g.nb[2] * g.rl[2])
+                             - (g.nb[0] * R(g.dr[0]) + g.nb[1] * R(g.dr[1]) + g.nb[2] * R(g.dr[2]));
         if (::fabs(nTd) < 1e-6) return -1;
-        if (::fabs(distd) < cfg.land_tol) return 0;
+        const double ltol = mixed ? 1e-5 : cfg.land_tol;
+        if (::fabs(distd) < ltol) return 0;
         if (g.trials >= cfg.max_steps) return -1;
-        const double d = distd / nTd;
-        const double dv = d;
-        if (g.hmag < 0.0) g.hmag = dv < 0.0 ? -dv : dv;
-        const bool capped = (dv < 0.0 ? -dv : dv) <= g.hmag;
-        const double h = capped ? d : (dv < 0.0 ? -g.hmag : g.hmag);
-        const double err = rkn_trial<double, FK>(fl, rabs, T, g.lam, h, S, k);
+        const P d = P(distd / nTd);
+        const V dv = d;
+        if (g.hmag < V(0)) g.hmag = dv < V(0) ? -dv : dv;
+        const bool capped = (dv < V(0) ? -dv : dv) <= g.hmag;
+        const P h = capped ? d : P(dv < V(0) ? -g.hmag : g.hmag);
+        const V err = rkn_trial<P, FK>(fl, rabs, T, lam, h, S, k);
         ++g.trials;
-        const double tiny = 1e-300;
-        double fac = 0.9 * sqrt(sqrt(tol / (err > tiny ? err : tiny)));
-        fac = fac < 0.25 ? 0.25 : (fac > 4.0 ? 4.0 : fac);
+        const V tiny = V(mixed ? 1e-30 : 1e-300);
+        V fac = V(0.9) * sqrt(sqrt(tol / (err > tiny ? err : tiny)));
+        fac = fac < V(0.25) ? V(0.25) : (fac > V(4) ? V(4) : fac);
         if (err <= tol) {
             if (g.accepted == stop) {
                 h_out = h;
                 capped_out = capped;
                 return 1;
             }
-            rkn_tangent<double, FK>(fl, S, k, g.lam, h, T, g.Mr, g.MT);
-            g.Mtl = g.Mtl + h * g.gpd;
+            rkn_tangent<P, FK>(fl, S, k, lam, h, T, g.Mr, g.MT);
+            const R hd = R(h);
+            g.Mtl = g.Mtl + hd * g.gpd;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                g.rl[i] = g.rl[i] + h * Td[i];
-                g.dr[i] = g.dr[i] + h * h * (1.0 / 6.0) * (k[0][i] + k[1][i] + k[2][i]);
-                g.dT[i] = g.dT[i] + h * (1.0 / 6.0) * (k[0][i] + 2.0 * k[1][i] + 2.0 * k[2][i] + k[3][i]);
+                g.rl[i] = g.rl[i] + hd * Td[i];
+                g.dr[i] = g.dr[i] + h * h * (P(1) / P(6)) * (k[0][i] + k[1][i] + k[2][i]);
+                g.dT[i] = g.dT[i] + h * (P(1) / P(6)) * (k[0][i] + P(2) * k[1][i] + P(2) * k[2][i] + k[3][i]);
             }
-            g.dt = g.dt + h * g.gd;
+            g.dt = g.dt + hd * g.gd;
             ++g.accepted;
         }
-        g.hmag = (h < 0.0 ? -h : h) * fac;
+        const V hv = h;
+        g.hmag = (hv < V(0) ? -hv : hv) * fac;
     }
+}
+
+// The replayed state in FP64 for the reverse sweep (the FP64 replay is
+// already that state).
+template <int FK>
+__device__ inline const GapRun<double, FK>& widen(const GapRun<double, FK>& g, GapRun<double, FK>&) { return g; }
+template <int FK>
+__device__ inline const GapRun<double, FK>& widen(const GapRun<float, FK>& g, GapRun<double, FK>& w) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        w.r0[i] = g.r0[i];
+        w.T0[i] = g.T0[i];
+        w.nb[i] = g.nb[i];
+        w.rl[i] = g.rl[i];
+        w.dr[i] = double(g.dr[i]);
+        w.dT[i] = double(g.dT[i]);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            w.Mr[i][j] = double(g.Mr[i][j]);
+            w.MT[i][j] = double(g.MT[i][j]);
+        }
+    }
+    w.lam = g.lam;
+    w.gd = g.gd;
+    w.gpd = g.gpd;
+    w.d0 = g.d0;
+    w.dt = g.dt;
+    w.Mtl = g.Mtl;
+    w.hmag = double(g.hmag);
+    w.trials = g.trials;
+    w.accepted = g.accepted;
+    return w;
 }
 
 // grad B at r applied to v is Field::grad_apply; its transpose:
@@ -182,14 +229,14 @@ struct GapBar {
 };
 
 // Reverse of one accepted step.  Inputs: the state at the step start (g), its
-// h, capped flag, stages S and k; gb holds the adjoints of the step's outputs
+// h, capped flag and stage accelerations k; gb holds the adjoints of the step's outputs
 // on entry and of its inputs on return.
 template <int FK>
-__device__ inline void step_reverse(const Field<double, FK>& fl, const double* sb, const GapRun<FK>& g, double h,
-                                    bool capped, const Stages<double, FK>& S, const double k[4][3], GapBar& gb) {
-    // explicit q/p dependence of stage k_i: k_i / (q/p), or kappa T_i x B_i when q/p = 0
-    const bool straight = g.lam == 0.0;
-    const double lam = g.lam, lk = lam * kKappa, ilam = straight ? 0.0 : 1.0 / lam;
+__device__ inline void step_reverse(const Field<double, FK>& fl, const double* sb, const GapRun<double, FK>& g,
+                                    double h, bool capped, const double k[4][3], GapBar& gb) {
+    // explicit q/p dependence of stage k_i = (q/p) kappa T_i x B_i: kappa T_i x B_i
+    // (one form for every q/p, q/p = 0 included; reversed through T_i and B_i)
+    const double lam = g.lam, lk = lam * kKappa;
     double r[3], T[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -270,8 +317,8 @@ __device__ inline void step_reverse(const Field<double, FK>& fl, const double* s
                 cross(dTs[st], Bs[st], c1);
                 cross(Ts[st], gs[st], c2);
 #pragma unroll
-                for (int i = 0; i < 3; ++i) dk[st][i] = lk * (c1[i] + c2[i]) + (j == 4 ? k[st][i] * ilam : 0.0);
-                if (j == 4 && straight) {
+                for (int i = 0; i < 3; ++i) dk[st][i] = lk * (c1[i] + c2[i]);
+                if (j == 4) {
                     double q[3];
                     cross(Ts[st], Bs[st], q);
 #pragma unroll
@@ -308,13 +355,7 @@ __device__ inline void step_reverse(const Field<double, FK>& fl, const double* s
                 e[i] = lk * dkb[st][i];
                 gbar[i] = 0.0;
             }
-            if (j == 4 && !straight) {
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    kb[st][i] += dkb[st][i] * ilam;
-                    gb.lam -= dkb[st][i] * k[st][i] * ilam * ilam;
-                }
-            } else if (j == 4) {
+            if (j == 4) {
                 double eq[3];
 #pragma unroll
                 for (int i = 0; i < 3; ++i) eq[i] = kKappa * dkb[st][i];
@@ -446,7 +487,7 @@ __device__ inline void step_reverse(const Field<double, FK>& fl, const double* s
 // caller decides the memory it lives in).  Sets gb.
 template <int FK, class FbP>
 __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa, const double* sb,
-                                   const GapRun<FK>& g, double t0, const double xpb[6], FbP Fb, int64_t fs,
+                                   const GapRun<double, FK>& g, double t0, const double xpb[6], FbP Fb, int64_t fs,
                                    GapBar& gb) {
     const double lam = g.lam, lk = lam * kKappa;
     // landed state and the final move
@@ -649,7 +690,7 @@ __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa
 // Reverse of the gap's start: bound -> free on surface a and the initial
 // tangent columns; adds to xb[0..4] and the surface-a adjoints.
 template <int FK>
-__device__ inline void start_reverse(const Cfg& cfg, const double* sa, const double x[6], const GapRun<FK>& g,
+__device__ inline void start_reverse(const Cfg& cfg, const double* sa, const double x[6], const GapRun<double, FK>& g,
                                      GapBar& gb, double xb[6]) {
     double sp, cp, st, ct;
     angle_sincos(x[2], &sp, &cp);
@@ -695,9 +736,10 @@ __device__ inline void start_reverse(const Cfg& cfg, const double* sa, const dou
 // Reverse of one gap: xb += dL/dx, sab/sbb (13 each: c, R row-major; x/X0
 // unused) += dL/d(surface placement), for the adjoints xpb of the predicted
 // state and Fb of the stored transport Jacobian (entry q at Fb[q * fs]; FbP
-// as in end_reverse).  Returns false if the replay did not reproduce a
-// successful gap.
-template <int FK, class FbP>
+// as in end_reverse).  P: the forward pass's stepping precision, which the
+// replay uses.  Returns false if the replay did not reproduce a successful
+// gap.
+template <class P, int FK, class FbP>
 __device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg_in, const double* sa, const double* sb,
                                    const double x[6], const double xpb[6], FbP Fb, int64_t fs, double xb[6],
                                    double sab[13], double sbb[13]) {
@@ -706,22 +748,30 @@ __device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg_in, const 
     const Cfg cfg = cfg_in;
     Field<double, FK> fl;
     fl.init(fd);
-    GapRun<FK> g;
-    Stages<double, FK> S;
-    double k[4][3], h;
+    Field<P, FK> flp;
+    flp.init(fd);
+    GapRun<P, FK> g;
+    GapRun<double, FK> gw;
+    Stages<P, FK> S;
+    P k[4][3], h;
     bool capped;
-    gap_start<FK>(cfg, sa, sb, x, g);
-    if (gap_run<FK>(fl, cfg, 1 << 30, g, h, capped, S, k) != 0) return false;
+    gap_start<P, FK>(cfg, sa, sb, x, g);
+    if (gap_run<P, FK>(flp, cfg, 1 << 30, g, h, capped, S, k) != 0) return false;
     const int n_acc = g.accepted;
     GapBar gb;
-    end_reverse<FK>(fl, sa, sb, g, x[5], xpb, Fb, fs, gb);
+    end_reverse<FK>(fl, sa, sb, widen<FK>(g, gw), x[5], xpb, Fb, fs, gb);
     for (int s = n_acc - 1; s >= 0; --s) {
-        gap_start<FK>(cfg, sa, sb, x, g);
-        if (gap_run<FK>(fl, cfg, s, g, h, capped, S, k) != 1) return false;
-        step_reverse<FK>(fl, sb, g, h, capped, S, k, gb);
+        gap_start<P, FK>(cfg, sa, sb, x, g);
+        if (gap_run<P, FK>(flp, cfg, s, g, h, capped, S, k) != 1) return false;
+        double kd[4][3];
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) kd[st][i] = double(k[st][i]);
+        step_reverse<FK>(fl, sb, widen<FK>(g, gw), double(h), capped, kd, gb);
     }
-    gap_start<FK>(cfg, sa, sb, x, g);
-    start_reverse<FK>(cfg, sa, x, g, gb, xb);
+    gap_start<P, FK>(cfg, sa, sb, x, g);
+    start_reverse<FK>(cfg, sa, x, widen<FK>(g, gw), gb, xb);
     // surface placement adjoints in the 13-value layout: c, then R row-major
     // (columns u, v, n)
 #pragma unroll

@@ -3,7 +3,9 @@
 // For L = sum_t g_chi2 chi2_t + sum_hits g_par . xs + sum_t g_tgt . x_target,
 // one lane per track runs two sweeps over its hits:
 //
-//   forward  (k = 0 .. n-1): the filter of Sect. 2 / Sect. 4.1 again, storing
+//   forward  (k = 0 .. n-1): the filter of Sect. 2 / Sect. 4.1 again (in the
+//            fit's precision: FP32 stepping on an FP64 anchor for the mixed
+//            fit, so the recomputed states are the mixed fit's), storing
 //            per hit the predicted state and covariance, the transport
 //            Jacobian F_k, the noise terms and the filtered state and
 //            covariance.  The reverse of the RTS mean recursion only needs the
@@ -113,10 +115,10 @@ __device__ inline void stl(ldouble* x, int off, const double (&v)[N]) {
 // ---------------------------------------------------------------------------
 // forward sweep: filter recompute + reverse RTS mean recursion
 // ---------------------------------------------------------------------------
-template <int FK>
+template <class P, int FK>
 __device__ __attribute__((always_inline)) int vjp_fwd(const VjpArgs& a, const double* __restrict__ sm, double* wl, int t, int o, int n) {
     const int64_t H = a.n_hits, N = a.n_tracks;
-    Field<double, FK> fl;
+    Field<P, FK> fl;
     fl.init(a.field);
     double x[6];
     load_rows(a.seed + t, N, x);
@@ -136,7 +138,7 @@ __device__ __attribute__((always_inline)) int vjp_fwd(const VjpArgs& a, const do
         if (a.cfg.ms) highland(sa, x, a.cfg.mass, &q[0], &q[1]);
         double xp[6], F[25];
         int tr = 0;
-        status = transport<double, FK>(fl, a.field, a.cfg, sa, sb, x, xp, F, &tr);
+        status = transport<P, FK>(fl, a.field, a.cfg, sa, sb, x, xp, F, &tr);
         if (status != ST_OK) break;
         phase_boundary();
         double* w = wl + k * (NCV * TILE);
@@ -242,8 +244,9 @@ __device__ inline void noise_vjp(const double* sa, const double x[6], double mas
 // the alignment of sa and sb to ga and gb.  sx (LDS) holds the start state
 // (SX_X0) and the adjoints (SX_XPB, SX_FB, SX_QB).  The propagation is
 // reversed by hand (kf_gap_reverse.hpp; it reads the adjoint of F column by
-// column), the noise by its closed-form derivative.
-template <int FK>
+// column; the replay in the forward pass's stepping precision P), the noise
+// by its closed-form derivative.
+template <class P, int FK>
 __device__ __attribute__((always_inline)) void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const double* __restrict__ sb,
                         const ldouble* sx, double xb[6], double ga[6], double gb[6]) {
     double x[6], xpb[6];
@@ -252,7 +255,7 @@ __device__ __attribute__((always_inline)) void gap_vjp(const VjpArgs& a, const d
     double sab[13], sbb[13];
 #pragma unroll
     for (int i = 0; i < 13; ++i) { sab[i] = 0.0; sbb[i] = 0.0; }
-    gap_reverse<FK>(a.field, a.cfg, sa, sb, x, xpb, sx + SX_FB * TILE, TILE, xb, sab, sbb);
+    gap_reverse<P, FK>(a.field, a.cfg, sa, sb, x, xpb, sx + SX_FB * TILE, TILE, xb, sab, sbb);
     if (a.cfg.ms && sa[12] > 0.0) noise_vjp(sa, x, a.cfg.mass, sx[SX_QB * TILE], sx[(SX_QB + 1) * TILE], xb, sab);
     double t[6];
     placement_to_alignment(sa, sab, t);
@@ -266,7 +269,7 @@ __device__ __attribute__((always_inline)) void gap_vjp(const VjpArgs& a, const d
 // ---------------------------------------------------------------------------
 // backward sweep
 // ---------------------------------------------------------------------------
-template <int FK>
+template <class P, int FK>
 __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const double* __restrict__ sm, double* wl,
                                                        ldouble* sx, int t, int o, int n) {
     const int64_t H = a.n_hits, N = a.n_tracks;
@@ -383,7 +386,7 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
         double xb[6], ga[6], gb[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) { xb[i] = 0.0; ga[i] = 0.0; gb[i] = 0.0; }
-        gap_vjp<FK>(a, sm + prev * SURF_STRIDE, sm + s * SURF_STRIDE, sx, xb, ga, gb);
+        gap_vjp<P, FK>(a, sm + prev * SURF_STRIDE, sm + s * SURF_STRIDE, sx, xb, ga, gb);
         {
             double c[6];
             ldl(sx, SX_AA, c);
@@ -414,7 +417,7 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
 // body (the sweeps above are inlined into it).  At two waves per SIMD (half
 // the registers) its spills made the C2 adjoint 1.8x slower (measured), so the
 // kernels are built for one wave per SIMD only.
-template <int FK>
+template <class P, int FK>
 __device__ __attribute__((noinline)) void vjp_one(const VjpArgs& ag, const ldouble* sml, ldouble* sx, int64_t slot,
                                                   int t) {
     const VjpArgs& a = ag;
@@ -425,9 +428,9 @@ __device__ __attribute__((noinline)) void vjp_one(const VjpArgs& ag, const ldoub
     int o, n;
     int status = check_track(a.off, a.sid, a.loc, a.cov, a.seed, a.seed_cov, H, N, a.n_surf, a.max_hits, t, o, n);
     double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
-    if (status == ST_OK) status = vjp_fwd<FK>(a, sm, wl, t, o, n);
+    if (status == ST_OK) status = vjp_fwd<P, FK>(a, sm, wl, t, o, n);
     if (status == ST_OK) {
-        vjp_bwd<FK>(a, sm, wl, sx, t, o, n);
+        vjp_bwd<P, FK>(a, sm, wl, sx, t, o, n);
     } else {
         const double nan = __longlong_as_double(0x7ff8000000000000LL);
         for (int k = 0; k < n; ++k) fill_rows<2>(a.g_meas + o + k, H, nan);
@@ -438,7 +441,7 @@ __device__ __attribute__((noinline)) void vjp_one(const VjpArgs& ag, const ldoub
 
 // Dynamic LDS: the surface table, then per wave the backward sweep's stash
 // [SX_N][64] doubles.
-template <int FK, bool SORTED>
+template <class P, int FK, bool SORTED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) k_vjp(VjpArgs a) {
     extern __shared__ double sm[];
     stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, nullptr, sm);
@@ -449,7 +452,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))
         const int tile = next_tile<SORTED>(a.tile_counter, iter);
         if (tile >= a.n_tiles) break;
         const int64_t i = (int64_t)tile * TILE + lane;
-        if (i < a.n_tracks) vjp_one<FK>(a, (const ldouble*)sm, sx, i, SORTED ? a.order[i] : (int)i);
+        if (i < a.n_tracks) vjp_one<P, FK>(a, (const ldouble*)sm, sx, i, SORTED ? a.order[i] : (int)i);
     }
 }
 
@@ -633,13 +636,13 @@ VjpLayout vjp_layout(int64_t n_tracks, int64_t n_hits, int max_hits, int n_surf)
 // stashes fit the LDS (up to 36 surfaces on gfx950: 160 KiB less four
 // 78 x 64-double stashes leaves 4 KiB, 112 bytes per surface); wider detectors run one
 // wave per workgroup (fewer resident waves as the table grows).
-template <int FK, bool SORTED>
+template <class P, int FK, bool SORTED>
 hipError_t launch_vjp(const VjpArgs& a, hipStream_t stream) {
     const size_t stash = (size_t)SX_N * TILE * sizeof(double);
     const size_t table = (size_t)a.n_surf * SURF_STRIDE * sizeof(double);
     const int block = table + 4 * stash <= lds_cap() ? 4 * TILE : TILE;
     const size_t shm = table + (size_t)(block / TILE) * stash;
-    hipError_t e = allow_lds(k_vjp<FK, SORTED>, shm);
+    hipError_t e = allow_lds(k_vjp<P, FK, SORTED>, shm);
     if (e != hipSuccess) return e;
     const int need = (int)(((int64_t)a.n_tiles * TILE + block - 1) / block);
     int grid = need;
@@ -647,8 +650,17 @@ hipError_t launch_vjp(const VjpArgs& a, hipStream_t stream) {
         const int persistent = num_cu() * 4 * TILE / block;    // one wave per SIMD
         grid = grid < persistent ? grid : persistent;
     }
-    hipLaunchKernelGGL((k_vjp<FK, SORTED>), dim3(grid), dim3(block), shm, stream, a);
+    hipLaunchKernelGGL((k_vjp<P, FK, SORTED>), dim3(grid), dim3(block), shm, stream, a);
     return hipGetLastError();
+}
+
+template <bool SORTED>
+hipError_t launch_vjp_prec(const VjpArgs& a, bool mixed, int field_kind, hipStream_t stream) {
+    if (mixed)
+        return field_kind == KF_FIELD_UNIFORM ? launch_vjp<float, FIELD_UNIFORM, SORTED>(a, stream)
+                                              : launch_vjp<float, FIELD_SOLENOID, SORTED>(a, stream);
+    return field_kind == KF_FIELD_UNIFORM ? launch_vjp<double, FIELD_UNIFORM, SORTED>(a, stream)
+                                          : launch_vjp<double, FIELD_SOLENOID, SORTED>(a, stream);
 }
 
 }  // namespace
@@ -733,11 +745,9 @@ int kf_fit_tracks_vjp(const kf_config* cfg, const kf_surfaces* surf, const kf_fi
         e = enqueue_length_sort(a.off, a.n_tracks, a.max_hits, (int32_t*)(wsb + L.counts_off), (int32_t*)a.order,
                                 a.tile_counter, stream);
         if (e != hipSuccess) return KF_E_HIP;
-        e = field->kind == KF_FIELD_UNIFORM ? launch_vjp<FIELD_UNIFORM, true>(a, stream)
-                                            : launch_vjp<FIELD_SOLENOID, true>(a, stream);
+        e = launch_vjp_prec<true>(a, cfg->precision == KF_PREC_MIXED, field->kind, stream);
     } else {
-        e = field->kind == KF_FIELD_UNIFORM ? launch_vjp<FIELD_UNIFORM, false>(a, stream)
-                                            : launch_vjp<FIELD_SOLENOID, false>(a, stream);
+        e = launch_vjp_prec<false>(a, cfg->precision == KF_PREC_MIXED, field->kind, stream);
     }
     if (e != hipSuccess) return KF_E_HIP;
     if (grad->align) {

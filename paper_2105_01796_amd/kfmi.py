@@ -465,8 +465,8 @@ def kf_fit_tracks_vjp(batch: Batch, g_chi2=None, g_par=None, g_tgt=None, opt: Op
 
 class TrackFit(torch.autograd.Function):
     """(loc (2, H), align (6, S) or None) -> (smoothed par (6, H), target par
-    (6, N), chi2 (N,)) by kf_fit_tracks; backward by kf_fit_tracks_vjp (FP64
-    whatever opt.precision says).  Every other input of the batch is a
+    (6, N), chi2 (N,)) by kf_fit_tracks; backward by kf_fit_tracks_vjp in the
+    same precision (opt.precision).  Every other input of the batch is a
     constant."""
 
     @staticmethod

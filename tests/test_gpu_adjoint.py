@@ -25,6 +25,7 @@ from paper_2105_01796_amd import synth  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 REL = 1e-5
+MIXED_REL = 1e-3      # mixed-precision adjoint: of the row scale (floor 1)
 
 
 @pytest.fixture(scope="module")
@@ -85,6 +86,42 @@ def test_vjp_matches_oracle(kf, cfg, n):
         _close(out.meas.cpu().numpy(), ref_m, f"C{cfg} sched {sched} meas")
         _close(out.align.cpu().numpy(), ref_a, f"C{cfg} sched {sched} align")
         _close(out.seed.cpu().numpy(), ref_s, f"C{cfg} sched {sched} seed")
+
+
+@pytest.mark.parametrize("cfg,n", [(1, 100), (2, 300), (3, 300), (4, 300), (5, 100)])
+def test_vjp_mixed_precision(kf, cfg, n):
+    """The mixed-precision adjoint (FP32 recompute and replay of the
+    propagation, FP64 reverse sweep and accumulation) against the oracle's
+    FP64 gradient, held to 1e-3 of each gradient row's largest magnitude.
+    The bar follows from the mixed fit's own (parameters within 1e-3 sigma
+    of FP64): the chi2 gradient of a hit is 2 V^-1 times its smoothed
+    residual, so a shift of the smoothed state by 1e-3 of its sigma moves it
+    by at most ~1e-3 of the row's largest entry (residuals of several sigma);
+    per element, a gradient near zero has no relative bound.  Checked with
+    the full cotangents and with the chi2 cotangent off (the gradient is
+    then the smoother's gains alone, no residuals).  Statuses equal the mixed
+    fit's."""
+    _announce(f"vjp mixed C{cfg} n={n}")
+    import torch
+    ev = synth.make_config(cfg, n)
+    g = _cotangents(ev, 200 + cfg)
+    ref_m, ref_a, ref_s = oracle.fit_vjp(ev, *g)
+    b = kf.Batch.from_event(ev)
+    fit_st = kf.Plan(b, kf.Options(precision=kf.KF_PREC_MIXED)).run().status.cpu().numpy()
+    for sched in (1, 2):
+        out = _gpu_vjp(kf, ev, g, schedule=sched, precision=kf.KF_PREC_MIXED)
+        assert np.array_equal(out.status.cpu().numpy(), fit_st)
+        assert np.all(fit_st == 0)
+        _close(out.meas.cpu().numpy(), ref_m, f"mixed C{cfg} sched {sched} meas", rel=MIXED_REL, floor=1.0)
+        _close(out.align.cpu().numpy(), ref_a, f"mixed C{cfg} sched {sched} align", rel=MIXED_REL, floor=1.0)
+        _close(out.seed.cpu().numpy(), ref_s, f"mixed C{cfg} sched {sched} seed", rel=MIXED_REL, floor=1.0)
+    g0 = (np.zeros(ev.n_tracks), g[1], g[2])
+    ref_m, ref_a, ref_s = oracle.fit_vjp(ev, *g0)
+    out = _gpu_vjp(kf, ev, g0, precision=kf.KF_PREC_MIXED)
+    torch.cuda.synchronize()
+    _close(out.meas.cpu().numpy(), ref_m, f"mixed C{cfg} gains-only meas", rel=MIXED_REL, floor=1.0)
+    _close(out.align.cpu().numpy(), ref_a, f"mixed C{cfg} gains-only align", rel=MIXED_REL, floor=1.0)
+    _close(out.seed.cpu().numpy(), ref_s, f"mixed C{cfg} gains-only seed", rel=MIXED_REL, floor=1.0)
 
 
 @pytest.mark.parametrize("bz", [0.0, 2.0])
