@@ -67,6 +67,8 @@ extern "C" {
 #define KF_E_VALUE (-6)     /* a configuration value is out of range (tolerance <= 0, ...), or the
                                workgroup size needs more LDS than the device has for this
                                surface count (14 doubles per surface + 14.5 KiB per 64 threads) */
+#define KF_E_SCRATCH (-7)   /* kf_fit_tracks_noalloc: the batch needs more workspace than the
+                               library's static scratch (KF_NOALLOC_SCRATCH_BYTES) */
 
 /* ---- per-track status ---- */
 #define KF_ST_OK 0
@@ -262,6 +264,30 @@ void kf_plan_destroy(kf_plan *plan);
 int kf_autotune(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
                 const kf_measurements *meas, const kf_seeds *seeds, const kf_outputs *out,
                 void *workspace, size_t workspace_bytes, void *stream, kf_config *best, float *best_ms);
+
+/* ---- fit without a caller workspace and without allocation ----
+ *
+ * For callers that cannot allocate device memory at all (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * kf_fit_tracks_noalloc runs exactly the fit of kf_fit_tracks (same kernels,
+ * same launch settings, same results bit for bit) but takes its workspace
+ * from a static device array of KF_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on, until the process ends.  It calls no
+ * hipMalloc, hipFree or other allocating routine.  The scratch of the current
+ * device is used; `stream` must belong to that device.  Its address is looked
+ * up once per device, on the first call made with that device current.
+ * Batches whose kf_workspace_bytes() exceeds KF_NOALLOC_SCRATCH_BYTES are
+ * refused with KF_E_SCRATCH before anything is enqueued (64 MiB holds e.g.
+ * 16,000 tracks of 10 hits or 5,000 tracks of 30 hits).  All calls on one
+ * device share the one array: calls whose work overlaps on the device race
+ * (serialise them, e.g. on one stream).  What must start at zero (the
+ * length-sort counters) is cleared by a kernel of every call; the rest is
+ * written before it is read.  Other arguments and return codes as
+ * kf_fit_tracks. */
+#define KF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int kf_fit_tracks_noalloc(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
+                          const kf_measurements *meas, const kf_seeds *seeds, const kf_outputs *out,
+                          void *stream);
 
 /* ---- fit from host memory, copies overlapped with the fit ----
  *

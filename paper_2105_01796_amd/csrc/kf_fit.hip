@@ -940,6 +940,35 @@ hipError_t copy_rows(void* dst, size_t dpitch, const void* src, size_t spitch, s
 
 }  // namespace
 
+// ---- the workspace of kf_fit_tracks_noalloc ----
+// A static device array: every device the library runs on holds its own copy
+// until the process ends.  In host code the name `scratch` is only a handle
+// for the runtime; the device address comes from hipGetSymbolAddress, looked
+// up once per device with that device current (noalloc_scratch), and only
+// that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[KF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of the current device's scratch (nullptr on a HIP error).
+void* noalloc_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* kf_version(void) { return "kfmi 0.1 (gfx950, fp64 + mixed)"; }
@@ -953,6 +982,7 @@ const char* kf_status_string(int code) {
         case KF_E_WS: return "workspace missing or too small";
         case KF_E_HIP: return "HIP runtime error";
         case KF_E_VALUE: return "configuration value out of range";
+        case KF_E_SCRATCH: return "batch needs more workspace than the static scratch of kf_fit_tracks_noalloc";
         case KF_ST_NO_INTERSECT: return "track: no intersection with a surface";
         case KF_ST_STEP_CAP: return "track: step cap reached";
         case KF_ST_NOT_SPD: return "track: covariance not positive definite";
@@ -980,6 +1010,19 @@ int kf_fit_tracks(const kf_config* cfg, const kf_surfaces* surf, const kf_field*
     num_cu();
     const kf_config r = resolve(cfg, field, meas);
     return enqueue_fit(&r, surf, field, meas, seeds, out, workspace, (hipStream_t)stream);
+}
+
+int kf_fit_tracks_noalloc(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field,
+                          const kf_measurements* meas, const kf_seeds* seeds, const kf_outputs* out, void* stream) {
+    int rc = validate(cfg, surf, field, meas, seeds, out);
+    if (rc != KF_OK) return rc;
+    if (meas->n_tracks == 0) return KF_OK;
+    if (ws_layout(meas->n_tracks, meas->max_hits).total > KF_NOALLOC_SCRATCH_BYTES) return KF_E_SCRATCH;
+    void* ws = noalloc_scratch();
+    if (!ws) return KF_E_HIP;
+    num_cu();
+    const kf_config r = resolve(cfg, field, meas);
+    return enqueue_fit(&r, surf, field, meas, seeds, out, ws, (hipStream_t)stream);
 }
 
 struct kf_plan {

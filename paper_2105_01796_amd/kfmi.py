@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_PKG, "libkfmi.so")
 
 # ---- constants (include/kf.h) ----
 KF_OK, KF_E_NULL, KF_E_SIZE, KF_E_ENUM, KF_E_WS, KF_E_HIP, KF_E_VALUE = 0, -1, -2, -3, -4, -5, -6
+KF_E_SCRATCH = -7
+KF_NOALLOC_SCRATCH_BYTES = 64 << 20
 KF_ST_OK, KF_ST_NO_INTERSECT, KF_ST_STEP_CAP, KF_ST_NOT_SPD, KF_ST_BAD_INPUT, KF_ST_TOO_FEW = range(6)
 KF_FIELD_UNIFORM, KF_FIELD_SOLENOID, KF_FIELD_MAP = 0, 1, 2
 KF_PREC_FP64, KF_PREC_MIXED = 0, 1
@@ -79,7 +81,7 @@ class kf_gradients(C.Structure):
 # every symbol include/kf.h declares
 EXPORTS = ("kf_version", "kf_status_string", "kf_workspace_bytes", "kf_fit_tracks", "kf_plan_create",
            "kf_plan_launch", "kf_plan_destroy", "kf_autotune", "kf_vjp_workspace_bytes", "kf_fit_tracks_vjp",
-           "kf_staged_workspace_bytes", "kf_fit_tracks_staged")
+           "kf_staged_workspace_bytes", "kf_fit_tracks_staged", "kf_fit_tracks_noalloc")
 
 _lib = None
 
@@ -117,6 +119,8 @@ def lib():
         L.kf_staged_workspace_bytes.argtypes = [P, P, C.c_int32, C.c_int32, C.c_int32]
         L.kf_fit_tracks_staged.restype = C.c_int
         L.kf_fit_tracks_staged.argtypes = [P, P, P, P, P, P, P, C.c_size_t, C.c_int32, P, C.c_int32]
+        L.kf_fit_tracks_noalloc.restype = C.c_int
+        L.kf_fit_tracks_noalloc.argtypes = [P, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -359,6 +363,24 @@ def kf_fit_tracks(batch: Batch, opt: Options | None = None, extras: bool = False
     """Filter + RTS smoother of every track in `batch` on its device (async on
     the current stream)."""
     return Plan(batch, opt, extras).run()
+
+
+def kf_fit_tracks_noalloc(batch: Batch, out: Fit, opt: Options | None = None, stream=None) -> Fit:
+    """The fit of kf_fit_tracks with the library's static scratch as its
+    workspace (no device allocation by the library; the caller provides the
+    outputs `out`).  Raises KFError(KF_E_SCRATCH) for batches too large for
+    KF_NOALLOC_SCRATCH_BYTES."""
+    opt = opt or Options()
+    cfg, surf, field, meas, seeds = _structs(batch, opt)
+    outs = kf_outputs(_ptr(out.par), _ptr(out.cov), _ptr(out.tgt_par), _ptr(out.tgt_cov), _ptr(out.chi2),
+                      _ptr(out.ndf), _ptr(out.status), _ptr(out.trials), _ptr(out.filt_par), _ptr(out.filt_cov))
+    if stream is None:
+        stream = torch.cuda.current_stream(batch.loc.device)
+    rc = lib().kf_fit_tracks_noalloc(C.byref(cfg), C.byref(surf), C.byref(field), C.byref(meas), C.byref(seeds),
+                                     C.byref(outs), C.c_void_p(stream.cuda_stream))
+    if rc != KF_OK:
+        raise KFError(rc, "kf_fit_tracks_noalloc")
+    return out
 
 
 # ---------------------------------------------------------------------------

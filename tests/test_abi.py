@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(kf):
 
 
 def test_status_strings(kf):
-    for code in [0, -1, -2, -3, -4, -5, -6, 1, 2, 3, 4, 5]:
+    for code in [0, -1, -2, -3, -4, -5, -6, -7, 1, 2, 3, 4, 5]:
         assert kf.kf_status_string(code) != "unknown code"
     assert kf.kf_status_string(99) == "unknown code"
 
@@ -160,6 +160,30 @@ def test_argument_validation(kf):
     # nothing to do: no tracks is OK without touching the device
     meas.n_tracks = 0
     assert _call(kf, *a) == kf.KF_OK
+
+
+def test_noalloc_checks_arguments_and_scratch_size_on_the_host(kf):
+    """kf_fit_tracks_noalloc validates like kf_fit_tracks and refuses a batch
+    whose workspace exceeds its static scratch before touching the device."""
+    L = kf.lib()
+
+    def call(cfg, surf, fld, meas, seeds, out):
+        return L.kf_fit_tracks_noalloc(C.byref(cfg), C.byref(surf), C.byref(fld), C.byref(meas),
+                                       C.byref(seeds), C.byref(out), None)
+
+    assert L.kf_fit_tracks_noalloc(None, None, None, None, None, None, None) == kf.KF_E_NULL
+    a = _args(kf, N=20000, H=200000, max_hits=10)
+    cfg, surf, fld, meas, seeds, out = a
+    assert L.kf_workspace_bytes(C.byref(cfg), C.byref(meas), surf.n) > kf.KF_NOALLOC_SCRATCH_BYTES
+    assert call(*a) == kf.KF_E_SCRATCH
+    cfg.precision = 7
+    assert call(*a) == kf.KF_E_ENUM
+    cfg.precision = 0
+    meas.max_hits = kf.KF_MAX_HITS + 1
+    assert call(*a) == kf.KF_E_SIZE
+    meas.max_hits = 10
+    meas.n_tracks = 0
+    assert call(*a) == kf.KF_OK
 
 
 def test_workspace_size_grows_with_tracks_and_hits(kf):
