@@ -72,6 +72,8 @@ def lib():
         L.kfo_field_at.restype = None
         L.kfo_set_field_map.argtypes = [P, P, P, P]
         L.kfo_set_field_map.restype = i
+        L.kfo_set_surface_radius.argtypes = [i, P]
+        L.kfo_set_surface_radius.restype = i
         L.kfo_version.restype = C.c_char_p
         L.kfo_count_update.argtypes = [P] * 5
         L.kfo_count_update.restype = i
@@ -113,6 +115,21 @@ def _use_field(field):
         raise ValueError("bad field map")
 
 
+_radius_keep = []
+
+
+def _use_surfaces(det):
+    """Hand the detector's cylinder radii (if any) to the library before a call."""
+    rad = getattr(det, "radius", None)
+    if rad is None:
+        _radius_keep[:] = []
+        lib().kfo_set_surface_radius(0, None)
+        return
+    r = np.ascontiguousarray(rad, dtype=np.float64)
+    _radius_keep[:] = [r]
+    lib().kfo_set_surface_radius(int(r.size), _p(r))
+
+
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
@@ -144,6 +161,7 @@ class _Args:
                  max_steps=DEFAULT_MAX_STEPS, loc=None, seed_par=None, align=None):
         det = detector if detector is not None else ev.detector
         _use_field(ev.field)
+        _use_surfaces(det)
         self.keep = dict(
             off=_i32(ev.hit_offsets), sid=_i32(ev.surface_id), loc=_f64(ev.loc if loc is None else loc),
             cov=_f64(ev.cov), center=_f64(det.center), rot=_f64(det.rot), x0=_f64(det.x_over_X0),
@@ -249,6 +267,7 @@ def count_transport(det, field, sa, sb, x, mass=0.1056583755, tol=DEFAULT_TOL, l
                     max_steps=DEFAULT_MAX_STEPS):
     """(status, counts (5,), trials) of one bound-to-bound transport."""
     _use_field(field)
+    _use_surfaces(det)
     center, rot, x0 = _f64(det.center), _f64(det.rot), _f64(det.x_over_X0)
     b0, xi = _f64(field.b0), _f64(x)
     out = np.zeros(5, dtype=np.int64)
@@ -289,6 +308,7 @@ def transport(det, field, sa, sb, x, mass=0.1056583755, tol=DEFAULT_TOL, land_to
               max_steps=DEFAULT_MAX_STEPS):
     """Bound state x on surface sa -> (status, x' on sb, F = dx'/dx (6,6), trials)."""
     _use_field(field)
+    _use_surfaces(det)
     center, rot, x0 = _f64(det.center), _f64(det.rot), _f64(det.x_over_X0)
     b0 = _f64(field.b0)
     xi = _f64(x)

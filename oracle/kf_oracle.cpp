@@ -162,10 +162,19 @@ struct Cfg {
     double perigee[3] = {0.0, 0.0, 0.0};   // perigee line: through this point, parallel to z
 };
 
+// Surface types (d = r - c; R columns u, v, w with w = n for the flat ones):
+//   0 plane     local (u.d, v.d)
+//   1 disc      the plane's polar coordinates (|(u.d, v.d)|, atan2(v.d, u.d))
+//   2 cylinder  axis through c along w, radius rho: local (w.d, atan2(v.d, u.d)),
+//               the position along the axis and the azimuth about it
+//   3 line      a wire through c along w (a straw): local (signed distance of
+//               closest approach d.e with e = (w x T)/|w x T|, position w.d
+//               along the wire); only loc0 is measured
 template <class S>
 struct Surf {                 // R columns: u, v, n; x0 = thickness in X0
     S c[3]; S R[3][3]; double x0;
-    int type = 0;             // 0 plane: local (u.d, v.d); 1 disc: polar (|d_uv|, atan2(v.d, u.d)), d = r - c
+    int type = 0;             // as above
+    double radius = 0.0;      // cylinder radius (type 2)
 };
 
 // ---------------------------------------------------------------------------
@@ -305,7 +314,37 @@ template <class S>
 void bound_to_free(const Surf<S>& s, const S P[6], S F[8], S J[8][6]) {
     S sp = sin(P[2]), cp = cos(P[2]), st = sin(P[3]), ct = cos(P[3]);
     for (int i = 0; i < 8; ++i) for (int j = 0; j < 6; ++j) J[i][j] = 0.0;
-    if (s.type == 1) {
+    if (s.type == 2) {
+        // cylinder: r = c + rho (cos l1 u + sin l1 v) + l0 w
+        S cl = cos(P[1]), sl = sin(P[1]);
+        for (int i = 0; i < 3; ++i) {
+            F[i] = s.c[i] + s.radius * (cl * s.R[i][0] + sl * s.R[i][1]) + P[0] * s.R[i][2];
+            J[i][0] = s.R[i][2];
+            J[i][1] = s.radius * (cl * s.R[i][1] - sl * s.R[i][0]);
+        }
+    } else if (s.type == 3) {
+        // line: r = c + l0 e + l1 w, e = (w x T)/|w x T| with T from (phi, theta)
+        S T[3] = {cp * st, sp * st, ct};
+        S dTp[3] = {-(sp * st), cp * st, S(0.0)};
+        S dTt[3] = {cp * ct, sp * ct, -st};
+        S w[3] = {s.R[0][2], s.R[1][2], s.R[2][2]};
+        S m[3], mp[3], mt[3];
+        cross(w, T, m);
+        cross(w, dTp, mp);
+        cross(w, dTt, mt);
+        S mn = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+        S e[3] = {m[0] / mn, m[1] / mn, m[2] / mn};
+        // de = (I - e e^T) dm / |m|
+        S ep = (e[0] * mp[0] + e[1] * mp[1] + e[2] * mp[2]);
+        S et = (e[0] * mt[0] + e[1] * mt[1] + e[2] * mt[2]);
+        for (int i = 0; i < 3; ++i) {
+            F[i] = s.c[i] + P[0] * e[i] + P[1] * w[i];
+            J[i][0] = e[i];
+            J[i][1] = w[i];
+            J[i][2] = P[0] * (mp[i] - e[i] * ep) / mn;
+            J[i][3] = P[0] * (mt[i] - e[i] * et) / mn;
+        }
+    } else if (s.type == 1) {
         // disc: r = c + l0 (cos l1 u + sin l1 v)
         S cl = cos(P[1]), sl = sin(P[1]);
         for (int i = 0; i < 3; ++i) {
@@ -335,10 +374,30 @@ void free_to_bound(const Surf<S>& s, const S F[8], S P[6], S J[6][8]) {
     S a = s.R[0][0] * d[0] + s.R[1][0] * d[1] + s.R[2][0] * d[2];
     S b = s.R[0][1] * d[0] + s.R[1][1] * d[1] + s.R[2][1] * d[2];
     S rr = 0.0;
+    S e[3] = {S(0.0), S(0.0), S(0.0)}, dl0dT[3] = {S(0.0), S(0.0), S(0.0)};
     if (s.type == 1) {
         rr = sqrt(a * a + b * b);
         P[0] = rr;
         P[1] = atan2(b, a);
+    } else if (s.type == 2) {
+        P[0] = s.R[0][2] * d[0] + s.R[1][2] * d[1] + s.R[2][2] * d[2];
+        P[1] = atan2(b, a);
+    } else if (s.type == 3) {
+        // signed distance along e = (w x T)/|w x T| (T as given, not renormalised)
+        S w[3] = {s.R[0][2], s.R[1][2], s.R[2][2]};
+        S T[3] = {F[4], F[5], F[6]};
+        S m[3];
+        cross(w, T, m);
+        S mn = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+        for (int i = 0; i < 3; ++i) e[i] = m[i] / mn;
+        S de = e[0] * d[0] + e[1] * d[1] + e[2] * d[2];
+        P[0] = de;
+        P[1] = w[0] * d[0] + w[1] * d[1] + w[2] * d[2];
+        // d(d.e)/dT = ((d - (d.e) e) x w) / |m|
+        S dp[3] = {d[0] - de * e[0], d[1] - de * e[1], d[2] - de * e[2]};
+        S q[3];
+        cross(dp, w, q);
+        for (int i = 0; i < 3; ++i) dl0dT[i] = q[i] / mn;
     } else {
         P[0] = a;
         P[1] = b;
@@ -356,6 +415,18 @@ void free_to_bound(const Surf<S>& s, const S F[8], S P[6], S J[6][8]) {
         for (int i = 0; i < 3; ++i) {
             J[0][i] = (a * s.R[i][0] + b * s.R[i][1]) / rr;
             J[1][i] = (a * s.R[i][1] - b * s.R[i][0]) / (rr * rr);
+        }
+    } else if (s.type == 2) {
+        S q2 = a * a + b * b;
+        for (int i = 0; i < 3; ++i) {
+            J[0][i] = s.R[i][2];
+            J[1][i] = (a * s.R[i][1] - b * s.R[i][0]) / q2;
+        }
+    } else if (s.type == 3) {
+        for (int i = 0; i < 3; ++i) {
+            J[0][i] = e[i];
+            J[0][4 + i] = dl0dT[i];
+            J[1][i] = s.R[i][2];
         }
     } else {
         for (int i = 0; i < 3; ++i) { J[0][i] = s.R[i][0]; J[1][i] = s.R[i][1]; }
@@ -460,8 +531,108 @@ double rkn_step(const FieldDef& f, double mass, const S F[8], S h, S Fn[8], S (&
 //   stop when |n.(c - r)| < land_tol, then move the remaining distance d onto
 //   the plane to second order in d.
 // D receives the product of the accepted steps' Jacobians.
+// Curved measuring surfaces (cylinder, line): the distance to go and, at the
+// landed point, the constraint g = 0 that defines the surface, its rate
+// g' = dg/ds along the trajectory and its gradient in the free state.
+//   cylinder: g = (|d_perp|^2 - rho^2)/2, d_perp = d - (w.d) w; the distance to
+//             go is the straight-line path length to the crossing of
+//             |d_perp + s T_perp| = rho where the track moves outward (the
+//             larger root; none: no intersection), so a cylinder is reached
+//             from inside going forward and from outside going backward;
+//             grad g = (d_perp, 0, 0, 0, 0)
+//   line:     g = d_perp . T (zero at the closest approach to the wire); the
+//             distance to go is the Newton step -g/g', g' = |T_perp|^2 +
+//             d_perp . T' (must exceed 1e-6: a closest, not a farthest,
+//             approach); grad g = (T_perp, 0, d_perp, 0)
+template <class S>
+int curved_step(const FieldDef& f, double mass, const Surf<S>& s, const S F[8], S* step, S* g, S* gp, S dg[8],
+                S dFds[8]) {
+    S r[3] = {F[0], F[1], F[2]}, T[3] = {F[4], F[5], F[6]};
+    S B[3], dB[3][3], TxB[3];
+    field_at(f, r, B, dB);
+    cross(T, B, TxB);
+    S lam = F[7];
+    for (int i = 0; i < 3; ++i) { dFds[i] = T[i]; dFds[4 + i] = lam * kB * TxB[i]; }
+    dFds[3] = sqrt(1.0 + mass * mass * lam * lam) / kC;
+    dFds[7] = 0.0;
+    S w[3] = {s.R[0][2], s.R[1][2], s.R[2][2]};
+    S d[3] = {r[0] - s.c[0], r[1] - s.c[1], r[2] - s.c[2]};
+    S dw = w[0] * d[0] + w[1] * d[1] + w[2] * d[2];
+    S Tw = w[0] * T[0] + w[1] * T[1] + w[2] * T[2];
+    S dp[3], Tp[3];
+    for (int i = 0; i < 3; ++i) { dp[i] = d[i] - dw * w[i]; Tp[i] = T[i] - Tw * w[i]; }
+    for (int i = 0; i < 8; ++i) dg[i] = 0.0;
+    S dpT = dp[0] * Tp[0] + dp[1] * Tp[1] + dp[2] * Tp[2];
+    S TpT = Tp[0] * Tp[0] + Tp[1] * Tp[1] + Tp[2] * Tp[2];
+    if (s.type == 2) {
+        S dpd = dp[0] * dp[0] + dp[1] * dp[1] + dp[2] * dp[2];
+        S c0 = dpd - s.radius * s.radius;
+        *g = 0.5 * c0;
+        *gp = dpT;
+        for (int i = 0; i < 3; ++i) dg[i] = dp[i];
+        S disc = dpT * dpT - TpT * c0;
+        if (!(val(TpT) > 1e-12) || !(val(disc) >= 0.0)) return ST_NO_INTERSECT;
+        // the crossing where the track moves outward (d_perp . T_perp = +sqrt(disc)
+        // there), the larger root, in the form without cancellation
+        S sq = sqrt(disc);
+        if (val(dpT) <= 0.0) *step = (sq - dpT) / TpT;
+        else *step = -c0 / (dpT + sq);
+        return ST_OK;
+    }
+    // line
+    *g = dpT;
+    *gp = TpT + dp[0] * dFds[4] + dp[1] * dFds[5] + dp[2] * dFds[6];
+    for (int i = 0; i < 3; ++i) { dg[i] = Tp[i]; dg[4 + i] = dp[i]; }
+    if (!(val(*gp) > 1e-6)) return ST_NO_INTERSECT;
+    *step = -(*g) / (*gp);
+    return ST_OK;
+}
+
+// Adaptive propagation onto a curved surface, with the plane propagation's
+// step control on the distance to go of curved_step; land when that
+// distance is below land_tol, then move it to second order.
+template <class S>
+int propagate_curved(const FieldDef& f, const Cfg& cfg, const Surf<S>& s, S F[8], S (&D)[8][8], int* n_trials) {
+    for (int i = 0; i < 8; ++i) for (int j = 0; j < 8; ++j) D[i][j] = (i == j) ? 1.0 : 0.0;
+    double hmag = -1.0;
+    int trials = 0;
+    for (;;) {
+        S d, g, gp, dg[8], dFds[8];
+        int st = curved_step(f, cfg.mass, s, F, &d, &g, &gp, dg, dFds);
+        if (st != ST_OK) { *n_trials = trials; return st; }
+        if (std::fabs(val(d)) < cfg.land_tol) break;
+        if (trials >= cfg.max_steps) { *n_trials = trials; return ST_STEP_CAP; }
+        if (hmag < 0.0) hmag = std::fabs(val(d));
+        S h = (std::fabs(val(d)) <= hmag) ? d : S(std::copysign(hmag, val(d)));
+        S Fn[8], Ds[8][8];
+        double err = rkn_step(f, cfg.mass, F, h, Fn, Ds);
+        ++trials;
+        double fac = 0.9 * std::pow(cfg.tol / std::max(err, 1e-300), 0.25);
+        fac = std::min(4.0, std::max(0.25, fac));
+        if (err <= cfg.tol) {
+            for (int i = 0; i < 8; ++i) F[i] = Fn[i];
+            S Dn[8][8];
+            matmul(Ds, D, Dn);
+            for (int i = 0; i < 8; ++i) for (int j = 0; j < 8; ++j) D[i][j] = Dn[i][j];
+        }
+        hmag = std::fabs(val(h)) * fac;
+    }
+    {
+        S d, g, gp, dg[8], dFds[8];
+        curved_step(f, cfg.mass, s, F, &d, &g, &gp, dg, dFds);
+        for (int i = 0; i < 3; ++i) {
+            F[i] = F[i] + d * dFds[i] + 0.5 * d * d * dFds[4 + i];
+            F[4 + i] = F[4 + i] + d * dFds[4 + i];
+        }
+        F[3] = F[3] + d * dFds[3];
+    }
+    *n_trials = trials;
+    return ST_OK;
+}
+
 template <class S>
 int propagate(const FieldDef& f, const Cfg& cfg, const Surf<S>& s, S F[8], S (&D)[8][8], int* n_trials) {
+    if (s.type == 2 || s.type == 3) return propagate_curved(f, cfg, s, F, D, n_trials);
     for (int i = 0; i < 8; ++i) for (int j = 0; j < 8; ++j) D[i][j] = (i == j) ? 1.0 : 0.0;
     const S* n3[3] = {&s.R[0][2], &s.R[1][2], &s.R[2][2]};
     double hmag = -1.0;
@@ -515,6 +686,17 @@ int propagate(const FieldDef& f, const Cfg& cfg, const Surf<S>& s, S F[8], S (&D
 // along the trajectory back onto the plane (first order).
 template <class S>
 void path_correction(const FieldDef& f, double mass, const Surf<S>& s, const S F[8], S (&Pc)[8][8]) {
+    if (s.type == 2 || s.type == 3) {
+        // onto the constraint g = 0 along dF/ds: P = I - dF/ds grad(g)^T / g'
+        // (g' = grad(g) . dF/ds)
+        S d, g, gp, dg[8], dFds[8];
+        curved_step(f, mass, s, F, &d, &g, &gp, dg, dFds);
+        S rate = 0.0;
+        for (int j = 0; j < 8; ++j) rate = rate + dg[j] * dFds[j];
+        for (int i = 0; i < 8; ++i)
+            for (int j = 0; j < 8; ++j) Pc[i][j] = ((i == j) ? S(1.0) : S(0.0)) - dFds[i] * dg[j] / rate;
+        return;
+    }
     S r[3] = {F[0], F[1], F[2]}, T[3] = {F[4], F[5], F[6]};
     S B[3], dB[3][3], TxB[3];
     field_at(f, r, B, dB);
@@ -681,7 +863,22 @@ void ms_noise(const Surf<S>& s, const S x[6], double mass, S (&Q)[6][6]) {
     if (!(s.x0 > 0.0)) return;
     S st = sin(x[3]);
     S T[3] = {cos(x[2]) * st, sin(x[2]) * st, cos(x[3])};
-    S nT = s.R[0][2] * T[0] + s.R[1][2] * T[1] + s.R[2][2] * T[2];
+    // path through the layer: x0 over the cosine of the incidence on the
+    // surface normal (plane, disc: n; cylinder: the radial direction at the
+    // state's azimuth); a straw (line) is crossed across its wire, x0 over
+    // the sine of the angle between the track and the wire
+    S nT;
+    if (s.type == 2) {
+        S cl = cos(x[1]), sl = sin(x[1]);
+        nT = 0.0;
+        for (int i = 0; i < 3; ++i) nT = nT + (cl * s.R[i][0] + sl * s.R[i][1]) * T[i];
+    } else if (s.type == 3) {
+        S w[3] = {s.R[0][2], s.R[1][2], s.R[2][2]}, m[3];
+        cross(w, T, m);
+        nT = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    } else {
+        nT = s.R[0][2] * T[0] + s.R[1][2] * T[1] + s.R[2][2] * T[2];
+    }
     S path = s.x0 / fabs(nT);
     S p = 1.0 / fabs(x[4]);
     S beta = p / sqrt(p * p + mass * mass);
@@ -725,6 +922,42 @@ int kalman_update(const S xp[6], const S (&Cp)[6][6], const S m[2], const S (&V)
         }
     *chi2 = r[0] * (Si[0][0] * r[0] + Si[0][1] * r[1]) + r[1] * (Si[1][0] * r[0] + Si[1][1] * r[1]);
     return ST_OK;
+}
+
+// One-dimensional update (a straw measures loc0 only): H = e0^T, the same
+// gain-matrix formalism and Joseph form with a scalar residual covariance.
+template <class S>
+int kalman_update1(const S xp[6], const S (&Cp)[6][6], const S m0, double V00, S xf[6], S (&Cf)[6][6], S* chi2) {
+    S r = m0 - xp[0];
+    S Sm = V00 + Cp[0][0];
+    if (!(val(Sm) > 0.0)) return ST_NOT_SPD;
+    S K[6];
+    for (int i = 0; i < 6; ++i) K[i] = Cp[i][0] / Sm;
+    for (int i = 0; i < 6; ++i) xf[i] = xp[i] + K[i] * r;
+    xf[2] = wrap_phi(xf[2]);
+    S IKH[6][6];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) IKH[i][j] = ((i == j) ? S(1.0) : S(0.0)) - ((j == 0) ? K[i] : S(0.0));
+    S T1[6][6], IKHt[6][6], T2[6][6];
+    matmul(IKH, Cp, T1);
+    transpose(IKH, IKHt);
+    matmul(T1, IKHt, T2);
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) Cf[i][j] = T2[i][j] + K[i] * V00 * K[j];
+    *chi2 = r * r / Sm;
+    return ST_OK;
+}
+
+// Per surface type: is loc1 an azimuth (disc, cylinder), and how many local
+// coordinates a hit measures (a line: loc0 only).
+inline bool loc1_is_angle(int type) { return type == 1 || type == 2; }
+inline int meas_dim(int type) { return type == 3 ? 1 : 2; }
+
+template <class S>
+int update_on(int type, const S xp[6], const S (&Cp)[6][6], const S m[2], const S (&V)[2][2], S xf[6],
+              S (&Cf)[6][6], S* chi2) {
+    if (type == 3) return kalman_update1(xp, Cp, m[0], val(V[0][0]), xf, Cf, chi2);
+    return kalman_update(xp, Cp, m, V, xf, Cf, chi2, loc1_is_angle(type));
 }
 
 // ---------------------------------------------------------------------------
@@ -846,13 +1079,20 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
     out.chi2 = NAN;
     // input validation
     if (n < 3) return out.status = ST_TOO_FEW;
-    // the seed surface is a plane; hit surfaces are planes or discs
+    // the seed surface is a plane; hit surfaces are planes, discs, cylinders
+    // (radius > 0) or lines; a line hit has only loc0 and v00 (the rest unread)
     if (seed_sid < 0 || seed_sid >= n_surf || surf[seed_sid].type != 0) return out.status = ST_BAD_INPUT;
     for (int k = 0; k < n; ++k) {
         if (sid[k] < 0 || sid[k] >= n_surf) return out.status = ST_BAD_INPUT;
-        if (surf[sid[k]].type != 0 && surf[sid[k]].type != 1) return out.status = ST_BAD_INPUT;
-        for (int a = 0; a < 2; ++a) if (!std::isfinite(val(m[2 * k + a]))) return out.status = ST_BAD_INPUT;
+        const int ty = surf[sid[k]].type;
+        if (ty < 0 || ty > 3) return out.status = ST_BAD_INPUT;
+        if (ty == 2 && !(surf[sid[k]].radius > 0.0)) return out.status = ST_BAD_INPUT;
         const double* v = V3 + 3 * k;
+        if (ty == 3) {
+            if (!std::isfinite(val(m[2 * k])) || !std::isfinite(v[0]) || !(v[0] > 0.0)) return out.status = ST_BAD_INPUT;
+            continue;
+        }
+        for (int a = 0; a < 2; ++a) if (!std::isfinite(val(m[2 * k + a]))) return out.status = ST_BAD_INPUT;
         if (!(std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]))) return out.status = ST_BAD_INPUT;
         if (!(v[0] > 0.0 && v[0] * v[2] - v[1] * v[1] > 0.0)) return out.status = ST_BAD_INPUT;
     }
@@ -889,7 +1129,7 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
         const double* v = V3 + 3 * k;
         S V[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
         S ck;
-        st = kalman_update(xp, Cp, mk, V, x, C, &ck, surf[sid[k]].type == 1);
+        st = update_on(surf[sid[k]].type, xp, Cp, mk, V, x, C, &ck);
         if (st != ST_OK) return out.status = st;
         chi2 = chi2 + ck;
         for (int i = 0; i < 6; ++i) {
@@ -925,7 +1165,7 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
             S mk[2] = {m[2 * (n - 1)], m[2 * (n - 1) + 1]};
             const double* v = V3 + 3 * (n - 1);
             S V[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
-            int st = kalman_update(xl, Cl, mk, V, xb, Cb, &ck, surf[sid[n - 1]].type == 1);
+            int st = update_on(surf[sid[n - 1]].type, xl, Cl, mk, V, xb, Cb, &ck);
             if (st != ST_OK) return out.status = st;
         }
         for (int k = n - 2; k >= -1; --k) {
@@ -945,7 +1185,7 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
             if (cfg.ms) ms_noise(sb, xf, cfg.mass, Q);
             else for (int i = 0; i < 6; ++i) for (int j = 0; j < 6; ++j) Q[i][j] = 0.0;
             backward_predict(G, Q, Cb, Cq);
-            const bool ang = k >= 0 && surf[sid[k]].type == 1;
+            const bool ang = k >= 0 && loc1_is_angle(surf[sid[k]].type);
             st = two_filter_combine(xf, Cf, xq, Cq, xs, Cs, ang);
             if (st != ST_OK) return out.status = st;
             for (int i = 0; i < 6; ++i) {
@@ -959,7 +1199,7 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
                 const double* v = V3 + 3 * k;
                 S V[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
                 S ck;
-                st = kalman_update(xq, Cq, mk, V, xb, Cb, &ck, ang);
+                st = update_on(surf[sid[k]].type, xq, Cq, mk, V, xb, Cb, &ck);
                 if (st != ST_OK) return out.status = st;
             }
         }
@@ -980,8 +1220,8 @@ int fit_track_seed_surface(const FieldDef& f, const Cfg& cfg, const Surf<S>* sur
                 Cs1[i][j] = out.Cs[36 * (k + 1) + 6 * i + j];
             }
         }
-        int st = rts_step(xf, Cf, F, xp1, Cp1, xs1, Cs1, xs, Cs, surf[sid[k + 1]].type == 1,
-                          k >= 0 && surf[sid[k]].type == 1);
+        int st = rts_step(xf, Cf, F, xp1, Cp1, xs1, Cs1, xs, Cs, loc1_is_angle(surf[sid[k + 1]].type),
+                          k >= 0 && loc1_is_angle(surf[sid[k]].type));
         if (st != ST_OK) return out.status = st;
         for (int i = 0; i < 6; ++i) {
             if (k >= 0) out.xs[6 * k + i] = xs[i]; else out.tgt[i] = xs[i];
@@ -1039,6 +1279,7 @@ void aligned_surface(const Surf<double>& s0, const S a[6], Surf<S>& o) {
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) o.R[i][j] = R[i][j];
     o.x0 = s0.x0;
     o.type = s0.type;
+    o.radius = s0.radius;
 }
 
 
@@ -1054,6 +1295,11 @@ struct Inputs {
     const int32_t* stype = nullptr;   // [S] surface types (0 plane, 1 disc) or NULL (all planes)
 };
 
+// Cylinder radii of the surfaces (set by kfo_set_surface_radius; like the
+// field map, one table for every call until it is replaced).
+static const double* g_radius = nullptr;
+static int g_radius_n = 0;
+
 // nominal surface s (before any alignment correction)
 inline Surf<double> surf_nominal(const Inputs& in, int s) {
     Surf<double> o;
@@ -1061,6 +1307,7 @@ inline Surf<double> surf_nominal(const Inputs& in, int s) {
     for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) o.R[i][j] = in.rot[(3 * i + j) * in.n_surf + s];
     o.x0 = in.x0[s];
     o.type = in.stype ? in.stype[s] : 0;
+    o.radius = (g_radius && s < g_radius_n) ? g_radius[s] : 0.0;
     return o;
 }
 
@@ -1128,6 +1375,13 @@ int kfo_set_field_map(const int32_t* n, const double* origin, const double* spac
     return 0;
 }
 
+// Cylinder radii per surface ([n], kept alive by the caller; NULL: none).
+int kfo_set_surface_radius(int n, const double* radius) {
+    g_radius = radius;
+    g_radius_n = radius ? n : 0;
+    return 0;
+}
+
 // Full fit of every track.  Arrays are component-major ([component][item]).
 // Optional outputs may be NULL.  smoother: 0 RTS, 1 two-filter (bwd_scale:
 // inflation of the backward filter's starting covariance).  target: 0 seed
@@ -1185,7 +1439,12 @@ int kfo_fit(int n_tracks, const int32_t* off, const int32_t* sid, const double* 
         for (int i = 0; i < 6; ++i) tgt_par[i * N + t] = r.tgt[i];
         for (int q = 0; q < 21; ++q) tgt_cov[q * N + t] = r.tgt_cov[PACK_I[q]][PACK_J[q]];
         chi2[t] = r.chi2;
-        ndf[t] = 2 * n - (bnz ? 5 : 4);
+        int dims = 0;     // measured coordinates: two per hit, one on a line
+        for (int k = 0; k < n; ++k) {
+            const int sk = sid[o + k];
+            dims += (sk >= 0 && sk < n_surf) ? meas_dim(surf[sk].type) : 2;
+        }
+        ndf[t] = dims - (bnz ? 5 : 4);
         status[t] = (uint8_t)r.status;
     }
     return 0;
@@ -1474,6 +1733,7 @@ int kfo_count_ops(int n_tracks, const int32_t* off, const int32_t* sid, const do
         for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) surf[s].R[i][j] = d.R[i][j];
         surf[s].x0 = d.x0;
         surf[s].type = d.type;
+        surf[s].radius = d.radius;
     }
     const int64_t H = in.H;
     for (int t = 0; t < n_tracks; ++t) {
@@ -1554,6 +1814,7 @@ int kfo_count_transport(int n_surf, const double* center, const double* rot, con
         for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) o.R[i][j] = d.R[i][j];
         o.x0 = d.x0;
         o.type = d.type;
+        o.radius = d.radius;
     }
     Cnt xi[6], xr[6], Fk[6][6];
     for (int i = 0; i < 6; ++i) xi[i] = x[i];
@@ -1623,6 +1884,7 @@ int kfo_count_units(int n_tracks, const int32_t* off, const int32_t* sid, const 
         for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) sc[s].R[i][j] = sd[s].R[i][j];
         sc[s].x0 = sd[s].x0;
         sc[s].type = sd[s].type;
+        sc[s].radius = sd[s].radius;
     }
     const int64_t H = in.H;
     const int o = off[t], n = off[t + 1] - off[t];
@@ -1692,7 +1954,7 @@ int kfo_count_units(int n_tracks, const int32_t* off, const int32_t* sid, const 
         const double* v = &V[3 * k];
         Cnt Vk[2][2] = {{v[0], v[1]}, {v[1], v[2]}};
         Cnt xf[6], Cf[6][6], ck;
-        kalman_update(xpk, Cpk, mk, Vk, xf, Cf, &ck, sc[sid[o + k]].type == 1);
+        update_on(sc[sid[o + k]].type, xpk, Cpk, mk, Vk, xf, Cf, &ck);
         add_unit(4);
         chi2 = chi2 + ck;
         add_unit(5);
@@ -1712,8 +1974,8 @@ int kfo_count_units(int n_tracks, const int32_t* off, const int32_t* sid, const 
                 Cs1[i][j] = r.Cs[36 * (k + 1) + 6 * i + j];
             }
         }
-        rts_step(xf, Cf, F, xp1, Cp1, xs1, Cs1, xs, Cs, sc[sid[o + k + 1]].type == 1,
-                 k >= 0 && sc[sid[o + k]].type == 1);
+        rts_step(xf, Cf, F, xp1, Cp1, xs1, Cs1, xs, Cs, loc1_is_angle(sc[sid[o + k + 1]].type),
+                 k >= 0 && loc1_is_angle(sc[sid[o + k]].type));
         add_unit(6);
     }
     return ST_OK;

@@ -52,7 +52,9 @@ class Detector:
     center: np.ndarray      # (3, S) f64
     rot: np.ndarray         # (9, S) f64, row-major 3x3 with columns u, v, n
     x_over_X0: np.ndarray   # (S,) f64
-    stype: np.ndarray | None = None   # (S,) int32 surface types: 0 plane, 1 disc (None: all planes)
+    stype: np.ndarray | None = None   # (S,) int32 surface types: 0 plane, 1 disc, 2 cylinder, 3 line
+                                      # (None: all planes)
+    radius: np.ndarray | None = None  # (S,) f64 cylinder radii (type 2), or None
 
     @property
     def n(self) -> int:
@@ -214,6 +216,48 @@ def helix_to_plane(r0, phi0, theta, rho, c, n, iters=30):
         T = helix_dir(phi0, theta, rho, s)
         g = n[0] * (r[0] - c[0]) + n[1] * (r[1] - c[1]) + n[2] * (r[2] - c[2])
         dg = n[0] * T[0] + n[1] * T[1] + n[2] * T[2]
+        ds = g / dg
+        s = s - ds
+        if np.all(np.abs(ds) < 1e-13 * np.maximum(1.0, np.abs(s))):
+            break
+    return s
+
+
+def helix_to_cylinder(r0, phi0, theta, rho, radius, iters=40):
+    """Path length s > 0 where the helix (B along z) first reaches the cylinder
+    x^2 + y^2 = radius^2 about the z axis, from inside (Newton on
+    g = |r_xy|^2 - radius^2 from the straight-line crossing)."""
+    T0 = helix_dir(phi0, theta, rho, np.zeros_like(phi0))
+    a = T0[0] ** 2 + T0[1] ** 2
+    b = r0[0] * T0[0] + r0[1] * T0[1]
+    c = r0[0] ** 2 + r0[1] ** 2 - radius ** 2
+    s = (-b + np.sqrt(b * b - a * c)) / a
+    for _ in range(iters):
+        r = helix_point(r0, phi0, theta, rho, s)
+        T = helix_dir(phi0, theta, rho, s)
+        g = r[0] ** 2 + r[1] ** 2 - radius ** 2
+        dg = 2.0 * (r[0] * T[0] + r[1] * T[1])
+        ds = g / dg
+        s = s - ds
+        if np.all(np.abs(ds) < 1e-13 * np.maximum(1.0, np.abs(s))):
+            break
+    return s
+
+
+def helix_to_wire(r0, phi0, theta, rho, wx, wy, iters=40):
+    """Path length s of the helix's closest approach to the wire through
+    (wx, wy) parallel to z: Newton on g = (r - w)_xy . T_xy, from the
+    straight-line closest approach."""
+    T0 = helix_dir(phi0, theta, rho, np.zeros_like(phi0))
+    s = -((r0[0] - wx) * T0[0] + (r0[1] - wy) * T0[1]) / (T0[0] ** 2 + T0[1] ** 2)
+    st = np.sin(theta)
+    for _ in range(iters):
+        r = helix_point(r0, phi0, theta, rho, s)
+        T = helix_dir(phi0, theta, rho, s)
+        dx, dy = r[0] - wx, r[1] - wy
+        g = dx * T[0] + dy * T[1]
+        # dT_xy/ds = rho (-T_y, T_x)
+        dg = T[0] ** 2 + T[1] ** 2 + rho * (-dx * T[1] + dy * T[0])
         ds = g / dg
         s = s - ds
         if np.all(np.abs(ds) < 1e-13 * np.maximum(1.0, np.abs(s))):
@@ -489,7 +533,131 @@ def solenoid_event(n_tracks, seed, n_planes=30, b0z=2.0, a=1e-7, nmin=8, p_hole=
 # ----------------------------------------------------------------------------
 # named workloads
 # ----------------------------------------------------------------------------
-CONFIG_SEEDS = {1: 1001, 2: 1002, 3: 1003, 4: 1004, 5: 1005, 6: 1005, 7: 1007}
+CONFIG_SEEDS = {1: 1001, 2: 1002, 3: 1003, 4: 1004, 5: 1005, 6: 1005, 7: 1007, 8: 1008}
+
+
+# barrel workload: five cylinders about the z axis, then five layers of
+# straws (wires parallel to z), seed plane x = 0 through the axis
+BARREL_RADII = (30.0, 60.0, 90.0, 120.0, 150.0)
+STRAW_LAYERS_X = (180.0, 210.0, 240.0, 270.0, 300.0)
+STRAW_PITCH = 10.0
+STRAW_WIRES = 9                 # per layer, y = -40 .. 40 mm
+SIGMA_STRAW = 0.1               # mm, drift-distance resolution
+
+
+def barrel_detector(x_over_X0=0.0) -> Detector:
+    """Seed plane x = 0 (surface 0), cylinders 1..5 (axis z through the origin,
+    u = x, v = y, so the azimuth about the axis is measured from x), then the
+    straws of layer l, wire i as surface 6 + 9 l + i (wire through
+    (x_l, y_i, 0) along z)."""
+    nc, nl, nw = len(BARREL_RADII), len(STRAW_LAYERS_X), STRAW_WIRES
+    S = 1 + nc + nl * nw
+    center = np.zeros((3, S))
+    rot = np.zeros((9, S))
+    rot[:, 0] = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]]).reshape(9)   # u = y, v = z, n = x
+    rot[:, 1:] = np.eye(3).reshape(9, 1)
+    stype = np.zeros(S, dtype=np.int32)
+    radius = np.zeros(S)
+    stype[1:1 + nc] = 2
+    radius[1:1 + nc] = BARREL_RADII
+    y0 = -0.5 * STRAW_PITCH * (nw - 1)
+    for l, xl in enumerate(STRAW_LAYERS_X):
+        for i in range(nw):
+            s = 1 + nc + l * nw + i
+            center[:, s] = (xl, y0 + i * STRAW_PITCH, 0.0)
+            stype[s] = 3
+    x0 = np.full(S, float(x_over_X0))
+    x0[0] = 0.0
+    return Detector(center=center, rot=rot, x_over_X0=x0, stype=stype, radius=radius)
+
+
+def barrel_event(n_tracks, seed, bz=2.0, x_over_X0=0.0, ms=False, f_inf=1.0, pt_range=(1.0, 10.0),
+                 phi_max=0.1, eta_max=0.2, name="barrel"):
+    """Exact helices (uniform Bz) through five cylinders (hits: position
+    along the axis and azimuth, 50 um and 50 um / radius) and five straw
+    layers (hit: the signed distance of closest approach to the nearest
+    wire, 100 um; the position along the wire is not measured)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    N = n_tracks
+    nc, nl, nw = len(BARREL_RADII), len(STRAW_LAYERS_X), STRAW_WIRES
+    P = nc + nl
+    det = barrel_detector(x_over_X0 if ms else 0.0)
+    fld = Field(FIELD_UNIFORM, (0.0, 0.0, float(bz)), 0.0)
+    q, p, phi, theta = _kinematics(rng, N, pt_range, False, phi_max, eta_max)
+    lam = q / p
+    kicks = rng.standard_normal((N, P, 2)) if ms else None
+    hit_rand = rng.standard_normal((N, P, 2))
+    seed_rand = rng.standard_normal((N, 6))
+    rho = -lam * K_B * bz
+    g_t = np.sqrt(1.0 + M_MU ** 2 * lam ** 2) / C_LIGHT
+    r = np.zeros((3, N))
+    t = np.zeros(N)
+    ph = phi.copy()
+    th = theta.copy()
+    hit_state = np.zeros((6, N, P))
+    sid = np.zeros((N, P), dtype=np.int32)
+    sig = np.zeros((2, N, P))
+    for j in range(P):
+        if j < nc:
+            s = helix_to_cylinder(r, ph, th, rho, BARREL_RADII[j])
+            r = helix_point(r, ph, th, rho, s)
+            ph = ph + rho * s
+            t = t + s * g_t
+            az = np.arctan2(r[1], r[0])
+            hit_state[:, :, j] = np.stack([r[2], az, ph, th, lam, t])
+            sid[:, j] = 1 + j
+            sig[0, :, j] = SIGMA_HIT
+            sig[1, :, j] = SIGMA_HIT / BARREL_RADII[j]
+            normal = np.stack([np.cos(az), np.sin(az), np.zeros(N)])
+        else:
+            l = j - nc
+            xl = STRAW_LAYERS_X[l]
+            cx = np.array([xl, 0.0, 0.0])
+            sx = helix_to_plane(r, ph, th, rho, cx, np.array([1.0, 0.0, 0.0]))
+            yc = helix_point(r, ph, th, rho, sx)[1]
+            y0 = -0.5 * STRAW_PITCH * (nw - 1)
+            wi = np.clip(np.rint((yc - y0) / STRAW_PITCH), 0, nw - 1).astype(np.int64)
+            wy = y0 + wi * STRAW_PITCH
+            s = helix_to_wire(r, ph, th, rho, xl, wy)
+            r = helix_point(r, ph, th, rho, s)
+            ph = ph + rho * s
+            t = t + s * g_t
+            T = helix_dir(ph, th, rho, np.zeros(N))
+            txy = np.hypot(T[0], T[1])
+            e = np.stack([-T[1] / txy, T[0] / txy, np.zeros(N)])        # (z x T)/|z x T|
+            d = r - np.stack([np.full(N, xl), wy, np.zeros(N)])
+            hit_state[:, :, j] = np.stack([(e * d).sum(axis=0), d[2], ph, th, lam, t])
+            sid[:, j] = 1 + nc + l * nw + wi
+            sig[0, :, j] = SIGMA_STRAW
+            normal = None
+        if ms and det.x_over_X0[sid[0, j]] > 0:
+            T = helix_dir(ph, th, rho, np.zeros(N))
+            if normal is not None:
+                cosi = np.abs((normal * T).sum(axis=0))
+            else:
+                cosi = np.hypot(T[0], T[1])                       # |z x T|: across the wire
+            path = det.x_over_X0[sid[0, j]] / cosi
+            th0 = highland_theta0(p, M_MU, path)
+            ph = ph + th0 * kicks[:, j, 0] / np.sin(th)
+            th = th + th0 * kicks[:, j, 1]
+    off = np.arange(N + 1, dtype=np.int64) * P
+    truth_hit = hit_state.reshape(6, N * P)
+    loc = truth_hit[:2] + sig.reshape(2, N * P) * hit_rand.reshape(N * P, 2).T
+    straw = np.zeros((N, P), dtype=bool)
+    straw[:, nc:] = True
+    straw = straw.reshape(-1)
+    loc[1, straw] = 0.0                                            # not measured on a straw
+    loc[1, ~straw] = np.angle(np.exp(1j * loc[1, ~straw]))
+    cov = np.zeros((3, N * P))
+    cov[0] = sig[0].reshape(-1) ** 2
+    cov[2] = sig[1].reshape(-1) ** 2                                # 0 on straws (unread)
+    truth0 = np.stack([np.zeros(N), np.zeros(N), phi, theta, lam, np.zeros(N)])
+    seed_par, seed_cov = _make_seeds(seed_rand, truth0, f_inf)
+    return Event(name=name, detector=det, field=fld, hit_offsets=off.astype(np.int32),
+                 surface_id=sid.reshape(-1), loc=np.ascontiguousarray(loc), cov=cov,
+                 seed_par=seed_par, seed_cov=seed_cov, seed_surface=0, truth_par0=truth0,
+                 truth_hit=np.ascontiguousarray(truth_hit), multiple_scattering=ms,
+                 meta=dict(seed=seed, bz=bz))
 
 
 def make_config(cfg: int, n_tracks: int | None = None, seed: int | None = None, **kw) -> Event:
@@ -506,6 +674,11 @@ def make_config(cfg: int, n_tracks: int | None = None, seed: int | None = None, 
     7: C2 measured on discs: every plane's centre moved to y = +100 mm and
        the hits given in polar coordinates (r, phi) about it (phi straddles
        +-pi), 50 um in r and 50 um / r in phi.
+    8: 1e5 tracks (C1 kinematics) through a barrel: five cylinders about the
+       z axis (radius 30..150 mm; hits: z and the azimuth) and five layers of
+       straws (wires parallel to z at x = 180..300 mm, 10 mm apart; hit: the
+       signed drift distance, 100 um), 2 T, 0.2 % X0 per layer with Highland
+       kicks.
     """
     seed = CONFIG_SEEDS[cfg] if seed is None else seed
     if cfg == 1:
@@ -521,6 +694,8 @@ def make_config(cfg: int, n_tracks: int | None = None, seed: int | None = None, 
     if cfg == 7:
         return telescope_event(n_tracks or 100_000, seed, x_over_X0=0.005, ms=True, center_offset=(0.0, 100.0, 0.0),
                                discs=True, name="C7", **kw)
+    if cfg == 8:
+        return barrel_event(n_tracks or 100_000, seed, x_over_X0=0.002, ms=True, name="C8", **kw)
     if cfg == 6:
         ev = solenoid_event(n_tracks or 1_000_000, seed, name="C6", **kw)
         ev.field = sample_field_map(ev.field, (-50.0, -1000.0, -6000.0), (950.0, 1000.0, 6000.0), (25.0, 25.0, 25.0))
