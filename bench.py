@@ -13,7 +13,11 @@ mixed-precision fit, the same fit with the two-filter smoother (a backward
 Kalman filter, i.e. a second propagation, instead of RTS), the fit with the
 fitted parameters given at the perigee, a fit + adjoint
 step (kf_fit_tracks then kf_fit_tracks_vjp with chi2, smoothed-parameter and
-target cotangents) and the fit from pinned host buffers (PCIe included).
+target cotangents) in FP64 and in mixed precision, the fit from pinned host
+buffers (PCIe included), and, as an extra key, 1e6 tracks of the solenoid
+workload (FP64 and mixed fit, fit + adjoint).  Per-step times come with their
+mean, RMS spread and median (the paper reports mean +- RMS over repeated
+runs).
 
 The roofline entry uses the oracle's count of non-trivial floating-point
 operations per track (add/sub, mul, div, sqrt) times the tracks in a launch,
@@ -49,39 +53,61 @@ WORKLOADS = {
     6: "the tracks of C5 with the field as a map: the solenoid sampled every 25 mm (41x81x481 points, "
        "38 MB), trilinear",
     7: "C2 measured on discs: polar hits (r, phi) about centres 100 mm off the tracks, phi straddling +-pi",
+    8: "1e5 tracks through a barrel: 5 cylinders about z (r=30..150 mm; hits z, azimuth) and 5 layers of "
+       "straws (wires along z at x=180..300 mm; 1-D drift-distance hits), Bz=2 T, 0.2% X0/layer Highland MS",
 }
 
 
-FIT_SOURCES = ("kf_fit.hip", "kf_common.hpp", "kf_device.hpp")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fwd_c2_1e5_traffic.txt")
+FIT_SOURCES = ("kf_fit.hip", "kf_fit_kernels.hpp", "kf_curved.hpp", "kf_common.hpp", "kf_device.hpp",
+               *(f"kf_fit_{fk}_{p}.hip" for fk in ("uniform", "solenoid", "map") for p in ("fp64", "mixed")))
+VJP_SOURCES = ("kf_vjp.hip", "kf_adjoint.hpp", "kf_gap_reverse.hpp", "kf_common.hpp", "kf_device.hpp")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "k_fwd_c2_1e5_traffic.txt")
+FIT_COUNTER_FILE = os.path.join(PROFILES, "k_fwd_c2_1e5_fp64_counters.txt")
+VJP_COUNTER_FILE = os.path.join(PROFILES, "k_vjp_c2_1e5_fp64_counters.txt")
 
 
-def fit_source_hash() -> str:
+def source_hash(names) -> str:
     h = hashlib.sha256()
-    for name in FIT_SOURCES:
+    for name in names:
         with open(os.path.join(ROOT, "paper_2105_01796_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(config: int, n_tracks: int):
-    """HBM bytes per FP64 fit launch from the counter summary, or None when the
-    summary is missing, for another workload, or older than the fit sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+def fit_source_hash() -> str:
+    return source_hash(FIT_SOURCES)
+
+
+def recorded(path: str, key: str, config: int, n_tracks: int, sources):
+    """A figure per launch from a counter summary under profiles/, or None when
+    the summary is missing, for another workload, or older than the kernel's
+    sources."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
-        if kv.get("source_hash") != fit_source_hash():
+        if kv.get("source_hash") != source_hash(sources):
             return None
         if int(kv["config"]) != config or int(kv["tracks"]) != n_tracks:
             return None
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def recorded_traffic(config: int, n_tracks: int):
+    """HBM bytes per FP64 fit launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)."""
+    return recorded(TRAFFIC_FILE, "hbm_bytes_per_launch", config, n_tracks, FIT_SOURCES)
+
+
+def log(msg: str) -> None:
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
 def host_threads() -> int:
@@ -150,6 +176,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the fit + adjoint leg")
     ap.add_argument("--no-two-filter", action="store_true", help="skip the two-filter smoother leg")
     ap.add_argument("--no-perigee", action="store_true", help="skip the perigee-target leg")
+    ap.add_argument("--no-solenoid", action="store_true",
+                    help="skip the extra leg on 1e6 solenoid tracks (FP64 and mixed fit, fit + adjoint)")
     ap.add_argument("--no-staged", action="store_true",
                     help="skip the host-buffer leg (copies in, fit, copies out, chunked over streams)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -204,6 +232,7 @@ def main():
         return plan, tuned
 
     # FP64 leg (the headline value)
+    log(f"workload C{args.config}, {N} tracks, {ev.n_hits} hits: FP64 fit (autotune, graph)")
     plan64, tuned64 = prepared_plan(kfmi.KF_PREC_FP64)
     ms64, kms64, per64 = time_plan(plan64, args.steps, args.warmup)
     st = plan64.out.status.cpu().numpy()
@@ -211,6 +240,7 @@ def main():
 
     mixed = None
     if not args.no_mixed:
+        log("mixed-precision fit")
         planm, tunedm = prepared_plan(kfmi.KF_PREC_MIXED)
         msm, kmsm, perm = time_plan(planm, args.steps, args.warmup)
         mixed = {"value": N / (msm * 1e-3), "ms_per_step": msm, "launch_ms": kmsm,
@@ -221,6 +251,7 @@ def main():
     if not args.no_two_filter:
         # the other smoother of Sect. 2: a backward Kalman filter (second
         # propagation) combined with the forward filter, same workload
+        log("two-filter smoother")
         plant, tunedt = prepared_plan(kfmi.KF_PREC_FP64, smoother=kfmi.KF_SMOOTHER_TWO_FILTER)
         mst, kmst, _ = time_plan(plant, args.steps, args.warmup)
         two_filter = {"value": N / (mst * 1e-3), "unit": "tracks/s", "ms_per_step": mst, "launch_ms": kmst,
@@ -234,6 +265,7 @@ def main():
     if not args.no_perigee:
         # fitted parameters at the perigee of the z axis instead of the seed
         # plane: one more FP64 propagation per track after the smoother
+        log("perigee target")
         planp, _ = prepared_plan(kfmi.KF_PREC_FP64, target=kfmi.KF_TARGET_PERIGEE, perigee=(0.0, 0.0, 0.0))
         msp, kmsp, _ = time_plan(planp, args.steps, args.warmup)
         perigee = {"value": N / (msp * 1e-3), "unit": "tracks/s", "ms_per_step": msp, "launch_ms": kmsp,
@@ -247,6 +279,7 @@ def main():
     if not args.no_staged:
         # the same fit from pinned host buffers: transfers included (PCIe), chunks
         # pipelined over streams so that copies overlap the fit
+        log("host-staged fit")
         bh = kfmi.Batch.staged_from_event(ev, device=dev)
         opt_st = dict(base_opt)
         if tuned64:
@@ -270,6 +303,7 @@ def main():
     adjoint = None
     if (not args.no_adjoint and int(ev.field.kind) != kfmi.KF_FIELD_MAP    # the adjoint needs an analytic
             and getattr(ev.detector, "stype", None) is None):              # field and planes
+        log("fit + adjoint")
         rng_g = np.random.default_rng(1)
         g_chi2 = torch.ones(N, dtype=torch.float64, device=dev)
         g_par = torch.as_tensor(rng_g.standard_normal((6, ev.n_hits)), device=dev)
@@ -281,13 +315,80 @@ def main():
                 plan64.run(stream)
                 vjp.run(g_chi2, g_par, g_tgt, stream=stream)
 
+        class AdjointOnly:
+            def __init__(self, v):
+                self.v = v
+
+            def run(self, stream):
+                self.v.run(g_chi2, g_par, g_tgt, stream=stream)
+
         adj_steps = max(1, min(args.steps, 5))
         msa, kmsa, _ = time_plan(FitAndAdjoint(), adj_steps, min(args.warmup, 1))
+        msv, _, perv = time_plan(AdjointOnly(vjp), adj_steps, 1)
         st_a = vjp.grad.status.cpu().numpy()
         adjoint = {"value": N / (msa * 1e-3), "unit": "tracks/s", "ms_per_step": msa, "steps": adj_steps,
-                   "vjp_ms": msa - ms64, "tracks_ok": int((st_a == 0).sum()),
+                   "vjp_ms": msv, "vjp_ms_stats": step_stats(perv), "tracks_ok": int((st_a == 0).sum()),
                    "what": "kf_fit_tracks + kf_fit_tracks_vjp (d chi2, d smoothed params, d target params "
                            "-> d measurements, d alignment of every plane, d seeds), FP64"}
+        if mixed is not None:
+            vjpm = kfmi.VjpPlan(batch, kfmi.Options(precision=kfmi.KF_PREC_MIXED), want_align=True, want_seed=True)
+
+            class MixedFitAndAdjoint:
+                def run(self, stream):
+                    planm.run(stream)
+                    vjpm.run(g_chi2, g_par, g_tgt, stream=stream)
+
+            msam, _, _ = time_plan(MixedFitAndAdjoint(), adj_steps, 1)
+            msvm, _, _ = time_plan(AdjointOnly(vjpm), adj_steps, 1)
+            adjoint["mixed"] = {"value": N / (msam * 1e-3), "unit": "tracks/s", "ms_per_step": msam,
+                                "vjp_ms": msvm, "speedup_vs_fp64": msa / msam,
+                                "what": "the same step with the mixed fit and the mixed adjoint (FP32 "
+                                        "recompute and replay of the propagation, FP64 reverse sweep)"}
+            del vjpm
+        del vjp
+
+    solenoid = None
+    if not args.no_solenoid and args.config == 2:
+        # 1e6 tracks of the solenoid workload (30 planes, ragged 8-30 hits, pT
+        # 0.5-100 GeV, |eta| < 2.5): FP64 and mixed fits, and fit + adjoint in
+        # both precisions; an extra key, the headline stays the workload above
+        log("solenoid workload, 1e6 tracks: generating")
+        t5 = time.time()
+        ev5 = synth.make_config(5, 1_000_000)
+        t5 = time.time() - t5
+        b5 = kfmi.Batch.from_event(ev5, device=dev)
+        N5 = ev5.n_tracks
+        rng5 = np.random.default_rng(5)
+        g5 = (torch.ones(N5, dtype=torch.float64, device=dev),
+              torch.as_tensor(rng5.standard_normal((6, ev5.n_hits)), device=dev),
+              torch.as_tensor(rng5.standard_normal((6, N5)), device=dev))
+        solenoid = {"workload": "C5: " + WORKLOADS[5], "tracks": N5, "hits": ev5.n_hits,
+                    "gen_seconds": round(t5, 2)}
+        for name, prec in (("fp64", kfmi.KF_PREC_FP64), ("mixed", kfmi.KF_PREC_MIXED)):
+            log(f"solenoid workload, 1e6 tracks: {name} fit and fit + adjoint")
+            p5 = kfmi.Plan(b5, kfmi.Options(precision=prec, **base_opt))
+            if not args.no_autotune:
+                p5.autotune()
+            if not args.no_graph:
+                p5.capture()
+            ms5, _, per5 = time_plan(p5, 5, 1)
+            v5 = kfmi.VjpPlan(b5, kfmi.Options(precision=prec), want_align=True, want_seed=True)
+
+            class Fit5AndAdjoint:
+                def run(self, stream):
+                    p5.run(stream)
+                    v5.run(*g5, stream=stream)
+
+            ms5a, _, _ = time_plan(Fit5AndAdjoint(), 3, 1)
+            solenoid[name] = {"fit": {"value": N5 / (ms5 * 1e-3), "unit": "tracks/s", "ms_per_step": ms5,
+                                      "ms_stats": step_stats(per5),
+                                      "tracks_ok": int((p5.out.status.cpu().numpy() == 0).sum())},
+                              "fit_adjoint": {"value": N5 / (ms5a * 1e-3), "unit": "tracks/s", "ms_per_step": ms5a,
+                                              "tracks_ok": int((v5.grad.status.cpu().numpy() == 0).sum())}}
+            p5.release()
+            del p5, v5
+            torch.cuda.empty_cache()
+        del b5, g5, ev5
 
     # algorithmic work per track (oracle operation count on a sample)
     import oracle
@@ -305,9 +406,26 @@ def main():
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                 "flops_per_track": flops_per_track, "hits_per_track": hits_per_track,
                 "io_bytes_per_launch": io_bytes, "io_GBs": io_bytes / (kms64 * 1e-3) / 1e9}
+    # the FP64 instructions the fit kernel executes (hardware counters of the
+    # same launch shape, recorded under profiles/): the executed rate beside the
+    # algorithmic one (the kernel recomputes each filtered state in the smoother)
+    ex = recorded(FIT_COUNTER_FILE, "fp64_flops_per_launch", args.config, N, FIT_SOURCES)
+    roofline["executed"] = None if ex is None else {
+        "flops_per_launch": ex, "achieved": ex / (kms64 * 1e-3) / 1e12, "frac": ex / (kms64 * 1e-3) / 1e12 /
+        PEAK_FP64_TFLOPS, "source": os.path.relpath(FIT_COUNTER_FILE, ROOT),
+        "what": "64 x (ADD + MUL + 2 FMA + TRANS) F64 wave instructions per launch (every lane counted)"}
+    if adjoint is not None:
+        exa = recorded(VJP_COUNTER_FILE, "fp64_flops_per_launch", args.config, N, VJP_SOURCES)
+        adjoint["roofline"] = None if exa is None else {
+            "bound": "alu", "achieved": exa / (adjoint["vjp_ms"] * 1e-3) / 1e12, "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": exa / (adjoint["vjp_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "flops_per_launch": exa, "source": os.path.relpath(VJP_COUNTER_FILE, ROOT),
+            "what": "executed FP64 work of the adjoint kernel (64 x (ADD + MUL + 2 FMA + TRANS) F64 wave "
+                    "instructions, hardware counters recorded) over the adjoint call's event time"}
 
     cpu = None
     if not args.no_cpu_baseline:
+        log("CPU baseline (oracle)")
         nth = host_threads()
         m = min(N, 20000)
         sub = ev.subset(np.arange(m))
@@ -362,6 +480,7 @@ def main():
         "two_filter": two_filter,
         "perigee": perigee,
         "staged": staged,
+        "solenoid_1e6": solenoid,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

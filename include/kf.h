@@ -2,7 +2,8 @@
  * kf.h -- C ABI of the MI355X batched Kalman-filter track fitter (libkfmi.so).
  *
  * The library fits many independent charged-particle tracks at once.  Each
- * track is a list of 2-D hits on planes or discs.  The fit is the Kalman-filter
+ * track is a list of hits on planes, discs, cylinders (2-D hits) or straws
+ * (lines: 1-D hits, the drift distance).  The fit is the Kalman-filter
  * track fit of the paper (Sect. 2, Fig. 1): adaptive Runge-Kutta-Nystrom
  * propagation from surface to surface with the transport Jacobian and the
  * local<->global Jacobians (Sect. 4.1), a gain-matrix update on every measured
@@ -25,7 +26,10 @@
  *   surfaces         planes with centre c and rotation R = [u v n] (columns);
  *                    loc0 = u.(r - c), loc1 = v.(r - c); surfaces are unbounded;
  *                    a disc (kf_surfaces.type) measures the polar coordinates of
- *                    (u.(r - c), v.(r - c)) instead
+ *                    (u.(r - c), v.(r - c)) instead; a cylinder (axis through c
+ *                    along n) the position along the axis and the azimuth about
+ *                    it; a line (straw: wire through c along n) the signed
+ *                    distance of closest approach to the wire
  *   array layout     component-major ("[3][S]" means 3 rows of S items); every
  *                    array pointer is a DEVICE pointer owned by the caller
  *   hits             CSR over tracks: hits of track t are hit_offsets[t] ..
@@ -107,6 +111,17 @@ extern "C" {
 #define KF_SURF_PLANE 0        /* local (u.(r - c), v.(r - c)) */
 #define KF_SURF_DISC 1         /* local polar (|d|, atan2(v.d, u.d)), d = (u.(r - c), v.(r - c)): radius
                                   and azimuth about the centre in the surface's plane */
+#define KF_SURF_CYLINDER 2     /* axis through c along n, radius rho (kf_surfaces.radius): local
+                                  (n.(r - c), atan2(v.(r - c), u.(r - c))), position along the axis and
+                                  azimuth; r = c + rho (cos l1 u + sin l1 v) + l0 n.  The landing is the
+                                  crossing where the track moves outward (the larger root of the
+                                  straight-line distance to go) */
+#define KF_SURF_LINE 3         /* straw: wire through c along n; loc0 = e.(r - c), e = (n x T)/|n x T|,
+                                  the signed distance of closest approach (the only measured
+                                  coordinate: a 1-D hit, loc[1] and cov[1..2] are not read), loc1 =
+                                  n.(r - c) along the wire.  The landing is the closest approach
+                                  (Newton steps on (r - c)_perp . T = 0); the material is crossed across
+                                  the wire (path x/X0 / |n x T|) */
 
 #define KF_MAX_SURFACES 512     /* the surface table is staged in LDS (14 doubles each) */
 #define KF_MAX_HITS 64         /* per track */
@@ -121,10 +136,17 @@ typedef struct {
                                   centre c + (dx, dy, dz) and rotation R Rx(alpha) Ry(beta) Rz(gamma)
                                   (turned about its own u, v, n axes) */
     const int32_t *type;       /* [S] optional (NULL = all planes): KF_SURF_* per surface.  The seed
-                                  surface must be a plane and every hit's surface a plane or a disc
-                                  (else that track gets KF_ST_BAD_INPUT).  On a disc the measured
-                                  azimuth, its residual and the filtered and smoothed azimuths are
-                                  taken in (-pi, pi].  kf_fit_tracks_vjp requires NULL */
+                                  surface must be a plane and every hit's surface a plane or a disc,
+                                  or, with `radius` given, also a cylinder (radius > 0) or a line
+                                  (else that track gets KF_ST_BAD_INPUT).  On a disc or a cylinder
+                                  the measured azimuth, its residual and the filtered and smoothed
+                                  azimuths are taken in (-pi, pi].  kf_fit_tracks_vjp requires NULL */
+    const double *radius;      /* [S] optional: cylinder radii (mm; read for KF_SURF_CYLINDER only).
+                                  Give it (any values for other types) to fit cylinders and lines:
+                                  with type and radius set the fit runs the kernels built for every
+                                  surface type, one wave per SIMD (kf_config.occupancy 0 or 1; others
+                                  give KF_E_VALUE).  NULL: types 2 and 3 are unknown types.
+                                  kf_fit_tracks_vjp requires NULL */
 } kf_surfaces;
 
 typedef struct {
@@ -211,7 +233,8 @@ typedef struct {
     double *tgt_par;           /* [6][N] fitted parameters on the seed/target surface */
     double *tgt_cov;           /* [21][N] */
     double *chi2;              /* [N] sum of predicted-residual chi2 increments */
-    int32_t *ndf;              /* [N] 2 n - 5 with field, 2 n - 4 without */
+    int32_t *ndf;              /* [N] measured coordinates (2 per hit, 1 on a line) less 5 with field,
+                                  less 4 without */
     uint8_t *status;           /* [N] KF_ST_* */
     int32_t *trials;           /* [H] optional (NULL): RKN trials taken to reach each hit */
     double *filt_par;          /* [6][H] optional (NULL): filtered parameters */

@@ -16,7 +16,10 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libkfmi.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = [os.path.join(CSRC, "kf_fit.hip"), os.path.join(CSRC, "kf_vjp.hip")]
+# the fit kernels of each field kind and stepping precision compile in a
+# translation unit of their own, all in parallel
+FIT_UNITS = [f"kf_fit_{fk}_{p}.hip" for fk in ("uniform", "solenoid", "map") for p in ("fp64", "mixed")]
+SOURCES = [os.path.join(CSRC, f) for f in ["kf_fit.hip", "kf_vjp.hip", *FIT_UNITS]]
 OBJDIR = os.path.join(ROOT, "_build")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

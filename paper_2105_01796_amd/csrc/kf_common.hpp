@@ -179,10 +179,22 @@ __device__ inline void apply_alignment(const double al[6], double s[SURF_STRIDE]
     for (int i = 0; i < 3; ++i) s[i] += al[i];
 }
 
-// Surface table in LDS: c[3], R[9] row-major, x/X0, type (1: disc) per
-// surface (14 doubles).
+// Surface table in LDS: c[3], R[9] row-major, x/X0, type per surface (14
+// doubles).  Type slot: 1 for a disc, else 0; with `radius` given (the
+// kernels built for cylinders and lines) also 3 for a line and minus the
+// radius for a cylinder.
+__device__ inline double table_type_slot(const int32_t* stype, const double* radius, int s) {
+    if (!stype) return 0.0;
+    const int ty = stype[s];
+    if (ty == 1) return 1.0;
+    if (radius && ty == 3) return 3.0;
+    if (radius && ty == 2) return -radius[s];
+    return 0.0;
+}
+
 __device__ inline void stage_surfaces(int S, const double* center, const double* rot, const double* x0,
-                                      const double* align, const int32_t* stype, double* sm) {
+                                      const double* align, const int32_t* stype, double* sm,
+                                      const double* radius = nullptr) {
     if (!align) {
         for (int i = threadIdx.x; i < S * SURF_STRIDE; i += blockDim.x) {
             const int s = i / SURF_STRIDE, f = i - s * SURF_STRIDE;
@@ -190,7 +202,7 @@ __device__ inline void stage_surfaces(int S, const double* center, const double*
             if (f < 3) v = center[f * S + s];
             else if (f < 12) v = rot[(f - 3) * S + s];
             else if (f == 12) v = x0[s];
-            else v = (stype && stype[s] == 1) ? 1.0 : 0.0;
+            else v = table_type_slot(stype, radius, s);
             sm[i] = v;
         }
     } else {
@@ -201,7 +213,7 @@ __device__ inline void stage_surfaces(int S, const double* center, const double*
 #pragma unroll
             for (int f = 0; f < 9; ++f) v[3 + f] = rot[f * S + s];
             v[12] = x0[s];
-            v[13] = (stype && stype[s] == 1) ? 1.0 : 0.0;
+            v[13] = table_type_slot(stype, radius, s);
 #pragma unroll
             for (int c = 0; c < 6; ++c) al[c] = align[c * S + s];
             apply_alignment(al, v);

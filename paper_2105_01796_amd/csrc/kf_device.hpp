@@ -32,9 +32,10 @@ __host__ __device__ constexpr int sy(int i, int j) {
 __host__ __device__ constexpr int frow(int i) { return i < 4 ? i : 4; }
 
 // surface table entry in LDS: c[3], R[9] (row-major, columns u v n), x/X0,
-// type (0 plane, 1 disc)
+// type (0 plane, 1 disc; the kernels built for cylinders and lines also hold
+// 3 for a line and minus the radius for a cylinder there)
 constexpr int SURF_STRIDE = 14;
-__device__ inline bool is_disc(const double* __restrict__ s) { return s[13] != 0.0; }
+__device__ inline bool is_disc(const double* __restrict__ s) { return s[13] == 1.0; }
 
 struct FieldDef {
     int kind;

@@ -32,570 +32,10 @@
 #include <mutex>
 #include <map>
 #include <limits.h>
-#include "kf_common.hpp"
+#include "kf_fit_kernels.hpp"
 
 namespace {
-
-// workspace doubles per hit: predicted state xp 6, Cp 21; transport Jacobian
-// F into this hit (25 stored entries) unless the smoother recomputes it
-constexpr int NC = 52;
-constexpr int NC_RECOMPUTE = 27;
-constexpr int OFF_XP = 0, OFF_CP = 6, OFF_F = 27;
-template <bool STOREF>
-constexpr int nc_of() { return STOREF ? NC : NC_RECOMPUTE; }
-// LDS per wave: the carried filtered covariance [21][64 lanes] during the
-// filter; after the smoother the same area holds the output transpose of
-// flush_tile (FLUSH_GROUP components x FLUSH_HITS hits x 64 lanes doubles,
-// then two int lists of FLUSH_HITS x 64 entries)
-constexpr int CARRY = 21;
-constexpr int FLUSH_HITS = 4;
-constexpr int FLUSH_GROUP = 5;
-constexpr int FLUSH_DOUBLES = FLUSH_GROUP * FLUSH_HITS * TILE + FLUSH_HITS * TILE;
-constexpr int WAVE_LDS_DOUBLES = CARRY * TILE > FLUSH_DOUBLES ? CARRY * TILE : FLUSH_DOUBLES;
-
-struct FitArgs {
-    int n_tracks;
-    int n_surf;
-    int seed_sid;
-    int max_hits;
-    int64_t n_hits;
-    int64_t tile_doubles;       // workspace doubles per 64-track tile = max_hits * (NC or NC_RECOMPUTE) * 64
-    const int32_t* off;
-    const int32_t* sid;
-    const double* loc;
-    const double* cov;
-    const double* center;
-    const double* rot;
-    const double* x0;
-    const double* align;        // [6][S] alignment corrections or NULL
-    const int32_t* stype;       // [S] surface types (0 plane, 1 disc) or NULL
-    const double* seed;
-    const double* seed_cov;
-    FieldDef field;
-    Cfg cfg;
-    int bnz;                    // field is not identically zero
-    double* par;
-    double* pcov;
-    double* tgt_par;
-    double* tgt_cov;
-    double* chi2;
-    int32_t* ndf;
-    uint8_t* status;
-    int32_t* trials;
-    double* filt_par;
-    double* filt_cov;
-    double* ws;
-    const int32_t* order;       // slot -> track (SORTED) or NULL
-    int32_t* tile_counter;      // SORTED queue heads: [0] forward pass, [1] backward pass
-    int n_tiles;
-    double bwd_scale;           // two-filter smoother: inflation of the backward filter's start
-    double perigee[3];          // perigee target: a point of the line (parallel to z)
-};
-
-// Hit k of the track at CSR offset o lies on a disc (its azimuth wraps).
-__device__ inline bool disc_hit(const FitArgs& a, int o, int k) {
-    return a.stype && a.stype[a.sid[o + k]] == 1;
-}
-
-// Forward filter of the track held by workspace slot `slot` (track index t):
-// per hit propagation, covariance transport and the gain-matrix update.
-// Each hit is checked when the loop reaches it, with its surface id and
-// measurement loaded one hit ahead so the loads overlap the propagation; if
-// the filter fails before the last hit, the remaining hits are checked too,
-// so that a bad input anywhere wins over a filter failure (the CPU reference
-// checks every hit before it fits).  `cl` is this lane's LDS slot for the
-// filtered covariance between hits (component c at cl[c * 64]).  Writes
-// chi2, ndf and status; a failed track gets NaN outputs here (the backward
-// pass skips it).  STOREF: store the transport Jacobians for the smoother.
-template <class P, int FK, bool STOREF>
-__device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double* cl, int64_t slot, int t) {
-    constexpr int NW = nc_of<STOREF>();
-    const int64_t H = a.n_hits;
-    const int64_t N = a.n_tracks;
-    int o, n;
-    int status = check_head(a.off, a.seed, a.seed_cov, H, N, a.max_hits, t, o, n);
-    if (status == ST_OK && !seed_surface_ok(a.stype, a.seed_sid)) status = ST_BAD_INPUT;
-    double x[6];
-    load_rows(a.seed + t, N, x);
-    Field<P, FK> fl;
-    fl.init(a.field);
-    // this lane's column of its tile: component c of hit k at wl[(k * NW + c) * TILE]
-    double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
-    double chi2 = 0.0;
-    // hit k's surface and measurement, loaded during hit k-1
-    int s_nx = 0;
-    double m_nx[2] = {0.0, 0.0}, V_nx[3] = {0.0, 0.0, 0.0};
-    if (status == ST_OK) {
-        s_nx = a.sid[o];
-        load_rows(a.loc + o, H, m_nx);
-        load_rows(a.cov + o, H, V_nx);
-    }
-    // ---- forward filter ----
-    int prev = a.seed_sid;
-    int k = 0;
-    for (; k < n && status == ST_OK; ++k) {
-        const int s = s_nx;
-        const double m[2] = {m_nx[0], m_nx[1]};
-        const double V[3] = {V_nx[0], V_nx[1], V_nx[2]};
-        if (!hit_ok(s, a.n_surf, m, V, a.stype)) { status = ST_BAD_INPUT; break; }
-        if (k + 1 < n) {
-            s_nx = a.sid[o + k + 1];
-            load_rows(a.loc + o + k + 1, H, m_nx);
-            load_rows(a.cov + o + k + 1, H, V_nx);
-        }
-        phase_boundary();
-        const double* sa = sm + prev * SURF_STRIDE;
-        const double* sb = sm + s * SURF_STRIDE;
-        double q22 = 0.0, q33 = 0.0;
-        if (a.cfg.ms) highland(sa, x, a.cfg.mass, &q22, &q33);
-        double xp[6], F[25];
-        int tr = 0;
-        status = transport<P, FK>(fl, a.field, a.cfg, sa, sb, x, xp, F, &tr);
-        if (a.trials) a.trials[o + k] = tr;
-        if (status != ST_OK) break;
-        phase_boundary();
-        double* w = wl + k * (NW * TILE);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) w[(OFF_XP + i) * TILE] = xp[i];
-        if (STOREF) {
-#pragma unroll
-            for (int q = 0; q < 25; ++q) w[(OFF_F + q) * TILE] = F[q];
-        }
-        // the previous filtered covariance waits in LDS during the propagation
-        double Cp[21];
-        {
-            double CQ[21];
-            if (k == 0) {
-                load_rows(a.seed_cov + t, N, CQ);
-            } else {
-#pragma unroll
-                for (int q = 0; q < 21; ++q) CQ[q] = cl[q * TILE];
-            }
-            CQ[sy(2, 2)] += q22;
-            CQ[sy(3, 3)] += q33;
-            phase_boundary();
-            transport_cov(F, CQ, Cp);
-        }
-#pragma unroll
-        for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = Cp[q];
-        double ck, C[21];
-        phase_boundary();
-        status = kalman_update(xp, Cp, m, V, x, C, &ck, is_disc(sb));
-        if (status != ST_OK) break;
-        phase_boundary();
-        chi2 += ck;
-#pragma unroll
-        for (int q = 0; q < 21; ++q) cl[q * TILE] = C[q];
-        if (a.filt_par) {
-            store_rows(a.filt_par + o + k, H, x);
-            store_rows(a.filt_cov + o + k, H, C);
-        }
-        prev = s;
-    }
-    if (status != ST_OK && status != ST_BAD_INPUT && status != ST_TOO_FEW &&
-        any_bad_hit(a.sid, a.loc, a.cov, H, a.n_surf, o, k + 1, n, a.stype))
-        status = ST_BAD_INPUT;
-    if (status == ST_OK) {
-        a.chi2[t] = chi2;
-    } else {
-        const double nan = __longlong_as_double(0x7ff8000000000000LL);
-        for (int k = 0; k < n; ++k) {
-            fill_rows<6>(a.par + o + k, H, nan);
-            fill_rows<21>(a.pcov + o + k, H, nan);
-            if (a.filt_par) {
-                fill_rows<6>(a.filt_par + o + k, H, nan);
-                fill_rows<21>(a.filt_cov + o + k, H, nan);
-            }
-        }
-        fill_rows<6>(a.tgt_par + t, N, nan);
-        fill_rows<21>(a.tgt_cov + t, N, nan);
-        a.chi2[t] = nan;
-    }
-    a.ndf[t] = 2 * n - (a.bnz ? 5 : 4);
-    a.status[t] = (uint8_t)status;
-}
-
-// RTS smoother of one track (Sect. 2), fused after the forward pass or run by
-// a separate streaming kernel: the smoothed state of the last hit is its
-// filtered state; every earlier state, and finally the seed/target state,
-// follows from the next hit's stored prediction and Jacobian with the gain
-// A = Cf F^T Cp^-1 solved in FP64.  The smoothed state of hit k replaces the
-// prediction in slot k once that has been read for the last time; flush_tile
-// then writes the tile's CSR outputs.  Without stored Jacobians (STOREF
-// false; fused only, sm is the surface table) F of the gap k -> k+1 comes from
-// propagating the recomputed filtered state of hit k (or the seed) again with
-// the forward pass's routine.  Returns true if the track's smoothed states are
-// in its slots (false: not fitted, or failed here with NaN outputs).
-template <class P, int FK, bool STOREF>
-__device__ bool bwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
-    constexpr int NW = nc_of<STOREF>();
-    if (a.status[t] != ST_OK) return false;
-    const int o = a.off[t];
-    const int n = a.off[t + 1] - o;
-    const int64_t H = a.n_hits;
-    const int64_t N = a.n_tracks;
-    double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
-    Field<P, FK> fl;
-    if (!STOREF) fl.init(a.field);
-    // prediction of hit k+1 (carried from one step to the next)
-    double xp1[6], Cp1[21];
-    double x[6], C[21];
-    {
-        const double* w = wl + (n - 1) * (NW * TILE);
-        double m[2], V[3], ck;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) xp1[i] = w[(OFF_XP + i) * TILE];
-#pragma unroll
-        for (int q = 0; q < 21; ++q) Cp1[q] = w[(OFF_CP + q) * TILE];
-        load_rows(a.loc + o + n - 1, H, m);
-        load_rows(a.cov + o + n - 1, H, V);
-        kalman_update(xp1, Cp1, m, V, x, C, &ck, disc_hit(a, o, n - 1));
-    }
-    bool ang1 = disc_hit(a, o, n - 1);                 // hit k+1 is on a disc
-    bool spd = true;
-    int fail = ST_OK;
-    int s1 = STOREF ? 0 : a.sid[o + n - 1];          // surface of hit k+1
-    for (int k = n - 2; k >= -1; --k) {
-        double* w1 = wl + (k + 1) * (NW * TILE);
-        // every load of this step at once: F of hit k+1 (if stored), the
-        // prediction and measurement of hit k (or the seed)
-        double F[25], xp[6], Cp[21], m[2], V[3], xf[6], Cf[21];
-        if (STOREF) {
-#pragma unroll
-            for (int q = 0; q < 25; ++q) F[q] = w1[(OFF_F + q) * TILE];
-        }
-        int s0 = a.seed_sid;
-        if (k >= 0) {
-            const double* w = wl + k * (NW * TILE);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) xp[i] = w[(OFF_XP + i) * TILE];
-#pragma unroll
-            for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
-            load_rows(a.loc + o + k, H, m);
-            load_rows(a.cov + o + k, H, V);
-            if (!STOREF) s0 = a.sid[o + k];
-        } else {
-            load_rows(a.seed + t, N, xf);
-            load_rows(a.seed_cov + t, N, Cf);
-        }
-        // slot k+1 is done: it now keeps the smoothed state of hit k+1
-#pragma unroll
-        for (int i = 0; i < 6; ++i) w1[(OFF_XP + i) * TILE] = x[i];
-#pragma unroll
-        for (int q = 0; q < 21; ++q) w1[(OFF_CP + q) * TILE] = C[q];
-        double dx[6], L[21], id[6];
-        spd = chol6(Cp1, L, id) && spd;
-        rts_diff(x, C, xp1, Cp1, dx, ang1);              // C now holds D = Cs1 - Cp1
-        const bool ang0 = k >= 0 && disc_hit(a, o, k);
-        if (k >= 0) {
-            double ck;
-            kalman_update(xp, Cp, m, V, xf, Cf, &ck, ang0);   // filtered state of hit k, as in the forward pass
-#pragma unroll
-            for (int i = 0; i < 6; ++i) xp1[i] = xp[i];
-#pragma unroll
-            for (int q = 0; q < 21; ++q) Cp1[q] = Cp[q];
-        }
-        if (!STOREF) {
-            // F of the gap from hit k (or the seed) to hit k+1, as the forward pass propagated it
-            phase_boundary();
-            double xq[6];
-            int tr = 0;
-            const int st = transport<P, FK>(fl, a.field, a.cfg, sm + s0 * SURF_STRIDE, sm + s1 * SURF_STRIDE, xf,
-                                            xq, F, &tr);
-            if (st != ST_OK && fail == ST_OK) fail = st;
-            s1 = s0;
-        }
-        phase_boundary();
-        double A[36];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            double g[6];
-            smoother_gain_row(F, Cf, L, id, c, g);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) A[6 * c + i] = g[i];
-        }
-        phase_boundary();
-        rts_mean(xf, A, dx, x, ang0);
-        rts_cov(A, C, Cf);
-        ang1 = ang0;
-#pragma unroll
-        for (int q = 0; q < 21; ++q) C[q] = Cf[q];
-        phase_boundary();
-    }
-    if (spd && fail == ST_OK) {
-        store_rows(a.tgt_par + t, N, x);
-        store_rows(a.tgt_cov + t, N, C);
-        return true;
-    }
-    // a predicted covariance that is not positive definite (or a propagation
-    // that did not repeat): the track fails
-    const double nan = __longlong_as_double(0x7ff8000000000000LL);
-    for (int k = 0; k < n; ++k) {
-        fill_rows<6>(a.par + o + k, H, nan);
-        fill_rows<21>(a.pcov + o + k, H, nan);
-    }
-    fill_rows<6>(a.tgt_par + t, N, nan);
-    fill_rows<21>(a.tgt_cov + t, N, nan);
-    a.chi2[t] = nan;
-    a.status[t] = (uint8_t)(fail != ST_OK ? fail : ST_NOT_SPD);
-    return false;
-}
-
-// Two-filter smoother of one track (Sect. 2, Fig. 2), fused after the forward
-// pass (which kept only the predictions: 27 doubles per hit).  The backward
-// filter starts at the last hit from the forward filtered state with its
-// covariance times bwd_scale and takes in that hit; then for k = n-2 .. 0 and
-// finally the seed surface it propagates back to surface k (against the
-// direction of flight, the forward pass's transport routine), adds the
-// scatterer of surface k as the forward filter evaluated it (at the forward
-// filtered state of hit k, or the seed), combines that prediction with the
-// forward filtered state of hit k (recomputed from the stored prediction and
-// the hit, bit for bit as in the forward pass) into the smoothed state, which
-// replaces slot k, and takes in hit k.  The last hit keeps its filtered
-// state.  Returns true if the track's smoothed states are in its slots.
-template <class P, int FK>
-__device__ bool bwd_two_filter(const FitArgs& a, const double* __restrict__ sm, int64_t slot, int t) {
-    constexpr int NW = NC_RECOMPUTE;
-    if (a.status[t] != ST_OK) return false;
-    const int o = a.off[t];
-    const int n = a.off[t + 1] - o;
-    const int64_t H = a.n_hits;
-    const int64_t N = a.n_tracks;
-    double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
-    Field<P, FK> fl;
-    fl.init(a.field);
-    int fail = ST_OK;
-    double xb[6], Cb[21];
-    // surface types from the LDS table (the azimuth of a disc hit wraps)
-    const bool ang_last = is_disc(sm + a.sid[o + n - 1] * SURF_STRIDE);
-    {
-        double* w = wl + (n - 1) * (NW * TILE);
-        double xp[6], Cp[21], m[2], V[3], x[6], C[21], ck;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) xp[i] = w[(OFF_XP + i) * TILE];
-#pragma unroll
-        for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
-        load_rows(a.loc + o + n - 1, H, m);
-        load_rows(a.cov + o + n - 1, H, V);
-        kalman_update(xp, Cp, m, V, x, C, &ck, ang_last);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) w[(OFF_XP + i) * TILE] = x[i];
-#pragma unroll
-        for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = C[q];
-#pragma unroll
-        for (int q = 0; q < 21; ++q) C[q] *= a.bwd_scale;
-        if (kalman_update(x, C, m, V, xb, Cb, &ck, ang_last) != ST_OK) fail = ST_NOT_SPD;
-    }
-    int s1 = a.sid[o + n - 1];
-    double xs[6], Cs[21];
-    for (int k = n - 2; k >= -1 && fail == ST_OK; --k) {
-        double xf[6], Cf[21], m[2], V[3];
-        int s0 = a.seed_sid;
-        double* w = wl + (k >= 0 ? k : 0) * (NW * TILE);
-        const bool ang = k >= 0 && is_disc(sm + a.sid[o + k] * SURF_STRIDE);
-        if (k >= 0) {
-            double xp[6], Cp[21], ck;
-#pragma unroll
-            for (int i = 0; i < 6; ++i) xp[i] = w[(OFF_XP + i) * TILE];
-#pragma unroll
-            for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
-            load_rows(a.loc + o + k, H, m);
-            load_rows(a.cov + o + k, H, V);
-            s0 = a.sid[o + k];
-            kalman_update(xp, Cp, m, V, xf, Cf, &ck, ang);
-        } else {
-            load_rows(a.seed + t, N, xf);
-            load_rows(a.seed_cov + t, N, Cf);
-        }
-        double q22 = 0.0, q33 = 0.0;
-        if (a.cfg.ms) highland(sm + s0 * SURF_STRIDE, xf, a.cfg.mass, &q22, &q33);
-        phase_boundary();
-        double xq[6], G[25];
-        int tr = 0;
-        fail = transport<P, FK>(fl, a.field, a.cfg, sm + s1 * SURF_STRIDE, sm + s0 * SURF_STRIDE, xb, xq, G, &tr);
-        if (fail != ST_OK) break;
-        phase_boundary();
-        double Cq[21];
-        transport_cov(G, Cb, Cq);
-        Cq[sy(2, 2)] += q22;
-        Cq[sy(3, 3)] += q33;
-        phase_boundary();
-        if (!two_filter_combine(xf, Cf, xq, Cq, xs, Cs, ang)) { fail = ST_NOT_SPD; break; }
-        phase_boundary();
-        if (k >= 0) {
-#pragma unroll
-            for (int i = 0; i < 6; ++i) w[(OFF_XP + i) * TILE] = xs[i];
-#pragma unroll
-            for (int q = 0; q < 21; ++q) w[(OFF_CP + q) * TILE] = Cs[q];
-            double ck;
-            if (kalman_update(xq, Cq, m, V, xb, Cb, &ck, ang) != ST_OK) { fail = ST_NOT_SPD; break; }
-        }
-        s1 = s0;
-    }
-    if (fail == ST_OK) {
-        store_rows(a.tgt_par + t, N, xs);
-        store_rows(a.tgt_cov + t, N, Cs);
-        return true;
-    }
-    const double nan = __longlong_as_double(0x7ff8000000000000LL);
-    for (int k = 0; k < n; ++k) {
-        fill_rows<6>(a.par + o + k, H, nan);
-        fill_rows<21>(a.pcov + o + k, H, nan);
-    }
-    fill_rows<6>(a.tgt_par + t, N, nan);
-    fill_rows<21>(a.tgt_cov + t, N, nan);
-    a.chi2[t] = nan;
-    a.status[t] = (uint8_t)fail;
-    return false;
-}
-
-// All lanes of the wave, in step: LDS written by one lane is then visible to
-// the others (the waves of a workgroup run different tiles, so no workgroup
-// barrier may be used here).
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// Write the smoothed states of a tile's tracks (left in their workspace slots
-// by bwd_one) to the CSR outputs.  One lane per track computed them; a store
-// from each lane would touch a different cache line per lane.  Instead, for a
-// block of FLUSH_HITS hits: every lane loads its 27 x FLUSH_HITS values at
-// once (coalesced: the slots are tile-major), the wave lists which (lane,
-// hit) owns each entry of the block's CSR ranges, and then, FLUSH_GROUP
-// components at a time, the values pass through LDS so that consecutive
-// lanes store consecutive CSR entries.  Every lane of the wave must call it
-// (done: this lane's track has results; o, n: its CSR range).  lw: this
-// wave's LDS area (free once the smoother has finished).  NW: workspace
-// doubles per hit.
-template <int NW>
-__device__ void flush_tile(const FitArgs& a, double* lw, const double* wtile, bool done, int o, int n) {
-    const int lane = threadIdx.x & (TILE - 1);
-    double* tb = lw;                                                    // [FLUSH_GROUP][FLUSH_HITS][64]
-    int32_t* own = (int32_t*)(lw + FLUSH_GROUP * FLUSH_HITS * TILE);   // [FLUSH_HITS * 64]: lane | hit << 6
-    int32_t* dst = own + FLUSH_HITS * TILE;                             // [FLUSH_HITS * 64]: CSR index
-    const int nl = done ? n : 0;
-    int nmax = nl;
-#pragma unroll
-    for (int d = 1; d < TILE; d <<= 1) {
-        const int v = __shfl_xor(nmax, d, TILE);
-        nmax = v > nmax ? v : nmax;
-    }
-    const int64_t H = a.n_hits;
-    for (int hb = 0; hb < nmax; hb += FLUSH_HITS) {
-        const int cnt = nl - hb < 0 ? 0 : (nl - hb > FLUSH_HITS ? FLUSH_HITS : nl - hb);
-        // every value of this block first: one wait for all of them
-        double v[27][FLUSH_HITS];
-        const double* src = wtile + (int64_t)hb * (NW * TILE) + OFF_XP * TILE + lane;
-#pragma unroll
-        for (int c = 0; c < 27; ++c)
-#pragma unroll
-            for (int h = 0; h < FLUSH_HITS; ++h)
-                v[c][h] = h < cnt ? src[(int64_t)h * (NW * TILE) + c * TILE] : 0.0;
-        // exclusive prefix of cnt over the wave
-        int inc = cnt;
-#pragma unroll
-        for (int d = 1; d < TILE; d <<= 1) {
-            const int u = __shfl_up(inc, d, TILE);
-            if (lane >= d) inc += u;
-        }
-        const int start = inc - cnt;
-        const int total = __shfl(inc, TILE - 1, TILE);
-#pragma unroll
-        for (int h = 0; h < FLUSH_HITS; ++h)
-            if (h < cnt) {
-                own[start + h] = lane | (h << 6);
-                dst[start + h] = o + hb + h;
-            }
-#pragma unroll
-        for (int c0 = 0; c0 < 27; c0 += FLUSH_GROUP) {
-#pragma unroll
-            for (int c = c0; c < c0 + FLUSH_GROUP && c < 27; ++c)
-#pragma unroll
-                for (int h = 0; h < FLUSH_HITS; ++h)
-                    if (h < cnt) tb[((c - c0) * FLUSH_HITS + h) * TILE + lane] = v[c][h];
-            wave_sync();
-            for (int g = lane; g < total; g += TILE) {
-                const int e = own[g];
-                const int64_t d = dst[g];
-                const int from = (e >> 6) * TILE + (e & 63);
-#pragma unroll
-                for (int c = c0; c < c0 + FLUSH_GROUP && c < 27; ++c) {
-                    double* out = c < 6 ? a.par + (int64_t)c * H : a.pcov + (int64_t)(c - 6) * H;
-                    out[d] = tb[(c - c0) * FLUSH_HITS * TILE + from];
-                }
-            }
-            wave_sync();
-        }
-    }
-}
-
-// Filter (+ smoother).  SORTED selects the schedule at compile time; OCC is
-// the occupancy target in waves per SIMD, which caps the registers per lane;
-// FUSED runs the smoother for a track right after its forward pass, while
-// its workspace column is still cache-hot (otherwise k_bwd does it); STOREF
-// (always with a split smoother) stores the transport Jacobians, otherwise the
-// fused smoother recomputes them; TWOF (fused, no stored Jacobians) runs the
-// two-filter smoother instead of RTS.
-// Dynamic LDS: the surface table, then per wave the carried covariances.
-template <class P, int FK, int OCC, bool SORTED, bool FUSED, bool STOREF, bool TWOF>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
-k_fwd(FitArgs a) {
-    static_assert(FUSED || STOREF, "the split smoother reads stored Jacobians");
-    static_assert(!TWOF || (FUSED && !STOREF), "the two-filter smoother is fused and stores no Jacobians");
-    extern __shared__ double sm[];
-    stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, a.stype, sm);
-    const int lane = threadIdx.x & (TILE - 1);
-    double* cl = sm + a.n_surf * SURF_STRIDE + (threadIdx.x / TILE) * WAVE_LDS_DOUBLES + lane;
-    int iter = 0;
-    for (;;) {
-        const int tile = next_tile<SORTED>(a.tile_counter, iter);
-        if (tile >= a.n_tiles) break;
-        const int64_t i = (int64_t)tile * TILE + lane;
-        bool done = false;
-        int o = 0, n = 0;
-        if (i < a.n_tracks) {
-            const int t = SORTED ? a.order[i] : (int)i;
-            fwd_one<P, FK, STOREF>(a, sm, cl, i, t);
-            if constexpr (TWOF) {
-                done = bwd_two_filter<P, FK>(a, sm, i, t);
-                o = a.off[t];
-                n = a.off[t + 1] - o;
-            } else if constexpr (FUSED) {
-                done = bwd_one<P, FK, STOREF>(a, sm, i, t);
-                o = a.off[t];
-                n = a.off[t + 1] - o;
-            }
-        }
-        if (FUSED) flush_tile<nc_of<STOREF>()>(a, cl - lane, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
-    }
-}
-
-// Backward (smoother) pass as its own kernel.  Dynamic LDS: per wave the
-// output transpose.
-template <bool SORTED>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_bwd(FitArgs a) {
-    extern __shared__ double sm[];
-    const int lane = threadIdx.x & (TILE - 1);
-    double* lw = sm + (threadIdx.x / TILE) * WAVE_LDS_DOUBLES;
-    int iter = 0;
-    for (;;) {
-        const int tile = next_tile<SORTED>(a.tile_counter + 1, iter);
-        if (tile >= a.n_tiles) break;
-        const int64_t i = (int64_t)tile * TILE + lane;
-        bool done = false;
-        int o = 0, n = 0;
-        if (i < a.n_tracks) {
-            const int t = SORTED ? a.order[i] : (int)i;
-            done = bwd_one<double, FIELD_UNIFORM, true>(a, nullptr, i, t);
-            o = a.off[t];
-            n = a.off[t + 1] - o;
-        }
-        flush_tile<NC>(a, lw, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
-    }
-}
+using namespace kffit;
 
 // Perigee target: one lane per track carries the fitted state on the seed
 // surface (tgt_*) to the perigee of the line through a.perigee parallel to z
@@ -678,64 +118,40 @@ int validate(const kf_config* cfg, const kf_surfaces* surf, const kf_field* fiel
     if (!out->cov && meas->n_hits > 0) return KF_E_NULL;
     if (!out->tgt_par || !out->tgt_cov || !out->chi2 || !out->ndf || !out->status) return KF_E_NULL;
     if ((out->filt_par == nullptr) != (out->filt_cov == nullptr)) return KF_E_NULL;
+    // cylinders and lines: the kernels are built for one wave per SIMD only
+    if (surf->type && surf->radius && cfg->occupancy != 0 && cfg->occupancy != 1) return KF_E_VALUE;
     return KF_OK;
 }
 
-template <class P, int FK, int OCC, bool STOREF, bool TWOF>
-hipError_t launch_fit_fused(const FitArgs& a, int sched, int block, int waves_per_cu, size_t shm,
-                            hipStream_t stream) {
+// The split smoother's kernel, after the filter kernel on the same stream
+// (SORTED: up to 8 persistent waves per CU pull the tiles again).
+hipError_t launch_bwd(const FitArgs& a, int sched, int block, bool curved, hipStream_t stream) {
+    const size_t shm = (size_t)(block / TILE) * WAVE_LDS_DOUBLES * sizeof(double);
     const int need = (a.n_tiles * TILE + block - 1) / block;
+    int grid = need;
+    if (sched == KF_SCHED_SORTED) {
+        grid = num_cu() * 8 * TILE / block;
+        grid = grid > need ? need : (grid < 1 ? 1 : grid);
+    }
     hipError_t e = hipSuccess;
     if (sched == KF_SCHED_SORTED) {
-        int grid = num_cu() * waves_per_cu * TILE / block;
-        grid = grid > need ? need : (grid < 1 ? 1 : grid);
-        if ((e = allow_lds(k_fwd<P, FK, OCC, true, true, STOREF, TWOF>, shm)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, true, STOREF, TWOF>), dim3(grid), dim3(block), shm, stream, a);
+        if (curved) {
+            if ((e = allow_lds(k_bwd<true, true>, shm)) != hipSuccess) return e;
+            hipLaunchKernelGGL((k_bwd<true, true>), dim3(grid), dim3(block), shm, stream, a);
+        } else {
+            if ((e = allow_lds(k_bwd<true, false>, shm)) != hipSuccess) return e;
+            hipLaunchKernelGGL((k_bwd<true, false>), dim3(grid), dim3(block), shm, stream, a);
+        }
     } else {
-        if ((e = allow_lds(k_fwd<P, FK, OCC, false, true, STOREF, TWOF>, shm)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, true, STOREF, TWOF>), dim3(need), dim3(block), shm, stream,
-                           a);
+        if (curved) {
+            if ((e = allow_lds(k_bwd<false, true>, shm)) != hipSuccess) return e;
+            hipLaunchKernelGGL((k_bwd<false, true>), dim3(grid), dim3(block), shm, stream, a);
+        } else {
+            if ((e = allow_lds(k_bwd<false, false>, shm)) != hipSuccess) return e;
+            hipLaunchKernelGGL((k_bwd<false, false>), dim3(grid), dim3(block), shm, stream, a);
+        }
     }
     return hipGetLastError();
-}
-
-template <class P, int FK, int OCC>
-hipError_t launch_fit_occ(const FitArgs& a, int sched, int block, int waves_per_cu, bool split, bool storef,
-                          bool twof, hipStream_t stream) {
-    const size_t shm = ((size_t)a.n_surf * SURF_STRIDE + (size_t)(block / TILE) * WAVE_LDS_DOUBLES) * sizeof(double);
-    const size_t shm_b = (size_t)(block / TILE) * WAVE_LDS_DOUBLES * sizeof(double);
-    const int need = (a.n_tiles * TILE + block - 1) / block;
-    hipError_t e = hipSuccess;
-    if (twof) return launch_fit_fused<P, FK, OCC, false, true>(a, sched, block, waves_per_cu, shm, stream);
-    if (!split)
-        return storef ? launch_fit_fused<P, FK, OCC, true, false>(a, sched, block, waves_per_cu, shm, stream)
-                      : launch_fit_fused<P, FK, OCC, false, false>(a, sched, block, waves_per_cu, shm, stream);
-    if (sched == KF_SCHED_SORTED) {
-        int grid = num_cu() * waves_per_cu * TILE / block;
-        grid = grid > need ? need : (grid < 1 ? 1 : grid);
-        int gridb = num_cu() * 8 * TILE / block;
-        gridb = gridb > need ? need : (gridb < 1 ? 1 : gridb);
-        if ((e = allow_lds(k_fwd<P, FK, OCC, true, false, true, false>, shm)) != hipSuccess) return e;
-        if ((e = allow_lds(k_bwd<true>, shm_b)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_fwd<P, FK, OCC, true, false, true, false>), dim3(grid), dim3(block), shm, stream, a);
-        hipLaunchKernelGGL((k_bwd<true>), dim3(gridb), dim3(block), shm_b, stream, a);
-    } else {
-        if ((e = allow_lds(k_fwd<P, FK, OCC, false, false, true, false>, shm)) != hipSuccess) return e;
-        if ((e = allow_lds(k_bwd<false>, shm_b)) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_fwd<P, FK, OCC, false, false, true, false>), dim3(need), dim3(block), shm, stream, a);
-        hipLaunchKernelGGL((k_bwd<false>), dim3(need), dim3(block), shm_b, stream, a);
-    }
-    return hipGetLastError();
-}
-
-template <class P, int FK>
-hipError_t launch_fit(const FitArgs& a, int sched, int block, int waves_per_cu, int occ, bool split, bool storef,
-                      bool twof, hipStream_t stream) {
-    switch (occ) {
-        case 1: return launch_fit_occ<P, FK, 1>(a, sched, block, waves_per_cu, split, storef, twof, stream);
-        case 3: return launch_fit_occ<P, FK, 3>(a, sched, block, waves_per_cu, split, storef, twof, stream);
-        default: return launch_fit_occ<P, FK, 2>(a, sched, block, waves_per_cu, split, storef, twof, stream);
-    }
 }
 
 // Enqueue one fit with every launch setting resolved (no AUTO fields).
@@ -766,6 +182,9 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     a.x0 = surf->x_over_X0;
     a.align = surf->align;
     a.stype = surf->type;
+    // cylinders and lines: the kernels built for every surface type
+    const bool curved = surf->type && surf->radius;
+    a.radius = curved ? surf->radius : nullptr;
     a.seed = seeds->par;
     a.seed_cov = seeds->cov;
     a.field = field_def(field);
@@ -789,6 +208,8 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     const int sched = cfg->schedule;
     const int block = cfg->block;
     const int wpc = cfg->waves_per_cu;
+    // the kernels for cylinders and lines are built for one wave per SIMD only
+    if (curved && cfg->occupancy != 1) return KF_E_VALUE;
 
     hipError_t e = hipSuccess;
     if (sched == KF_SCHED_SORTED) {
@@ -802,15 +223,18 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     const bool storef = cfg->jacobians != KF_JAC_RECOMPUTE && !twof;
     if ((!storef || twof) && split) return KF_E_VALUE;
     if (field->kind == KF_FIELD_UNIFORM)
-        e = mixed ? launch_fit<float, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, storef, twof, stream)
-                  : launch_fit<double, FIELD_UNIFORM>(a, sched, block, wpc, occ, split, storef, twof, stream);
+        e = mixed ? launch_fwd_uniform_mixed(a, sched, block, wpc, occ, split, storef, twof, curved, stream)
+                  : launch_fwd_uniform_fp64(a, sched, block, wpc, occ, split, storef, twof, curved, stream);
     else if (field->kind == KF_FIELD_SOLENOID)
-        e = mixed ? launch_fit<float, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, twof, stream)
-                  : launch_fit<double, FIELD_SOLENOID>(a, sched, block, wpc, occ, split, storef, twof, stream);
+        e = mixed ? launch_fwd_solenoid_mixed(a, sched, block, wpc, occ, split, storef, twof, curved, stream)
+                  : launch_fwd_solenoid_fp64(a, sched, block, wpc, occ, split, storef, twof, curved, stream);
     else
-        e = mixed ? launch_fit<float, FIELD_MAP>(a, sched, block, wpc, occ, split, storef, twof, stream)
-                  : launch_fit<double, FIELD_MAP>(a, sched, block, wpc, occ, split, storef, twof, stream);
-    if (e == hipErrorInvalidValue) return KF_E_VALUE;     // workgroup needs more LDS than the device has
+        e = mixed ? launch_fwd_map_mixed(a, sched, block, wpc, occ, split, storef, twof, curved, stream)
+                  : launch_fwd_map_fp64(a, sched, block, wpc, occ, split, storef, twof, curved, stream);
+    if (e == hipSuccess && split) e = launch_bwd(a, sched, block, curved, stream);
+    // a workgroup needing more LDS than the device has, or an occupancy the
+    // kernels for cylinders and lines are not built for
+    if (e == hipErrorInvalidValue) return KF_E_VALUE;
     if (e == hipSuccess && cfg->target == KF_TARGET_PERIGEE) {
         const dim3 grid((unsigned)((a.n_tracks + 255) / 256));
         if (field->kind == KF_FIELD_UNIFORM)
@@ -826,11 +250,13 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
 
 
 // ---- autotuned launch settings ----
-// Key: precision, field kind, max hits per track, track count rounded to a
-// power of two.  Filled by kf_autotune, read when a setting is AUTO (0).
+// Key: precision, field kind, smoother, surfaces with cylinders or lines,
+// max hits per track, track count rounded to a power of two.  Filled by
+// kf_autotune, read when a setting is AUTO (0).
 struct TuneKey {
-    int precision, field_kind, smoother, max_hits, log2n;
+    int precision, field_kind, smoother, curved, max_hits, log2n;
     bool operator<(const TuneKey& o) const {
+        if (curved != o.curved) return curved < o.curved;
         if (precision != o.precision) return precision < o.precision;
         if (field_kind != o.field_kind) return field_kind < o.field_kind;
         if (smoother != o.smoother) return smoother < o.smoother;
@@ -841,16 +267,17 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, kf_config> g_tune;
 
-TuneKey tune_key(const kf_config* cfg, const kf_field* field, const kf_measurements* meas) {
+TuneKey tune_key(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field, const kf_measurements* meas) {
     int l = 0;
     while ((1LL << (l + 1)) <= (long long)meas->n_tracks) ++l;
-    return TuneKey{cfg->precision, field->kind, cfg->smoother, meas->max_hits, l};
+    const int curved = surf->type && surf->radius ? 1 : 0;
+    return TuneKey{cfg->precision, field->kind, cfg->smoother, curved, meas->max_hits, l};
 }
 
 // Fill AUTO (0) launch settings from the tuning table, else the defaults
 // (length-sorted persistent schedule, 64-thread groups, one wave per SIMD,
 // 8 resident waves per CU, smoother fused into the filter kernel).
-kf_config resolve(const kf_config* cfg, const kf_field* field, const kf_measurements* meas) {
+kf_config resolve(const kf_config* cfg, const kf_surfaces* surf, const kf_field* field, const kf_measurements* meas) {
     kf_config r = *cfg;
     kf_config d = r;
     d.schedule = KF_SCHED_SORTED;
@@ -859,7 +286,7 @@ kf_config resolve(const kf_config* cfg, const kf_field* field, const kf_measurem
     d.waves_per_cu = 8;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune.find(tune_key(cfg, field, meas));
+        auto it = g_tune.find(tune_key(cfg, surf, field, meas));
         if (it != g_tune.end()) d = it->second;
     }
     if (r.schedule == KF_SCHED_AUTO) {
@@ -1008,7 +435,7 @@ int kf_fit_tracks(const kf_config* cfg, const kf_surfaces* surf, const kf_field*
     rc = check_ws(meas, workspace, workspace_bytes);
     if (rc != KF_OK) return rc;
     num_cu();
-    const kf_config r = resolve(cfg, field, meas);
+    const kf_config r = resolve(cfg, surf, field, meas);
     return enqueue_fit(&r, surf, field, meas, seeds, out, workspace, (hipStream_t)stream);
 }
 
@@ -1021,7 +448,7 @@ int kf_fit_tracks_noalloc(const kf_config* cfg, const kf_surfaces* surf, const k
     void* ws = noalloc_scratch();
     if (!ws) return KF_E_HIP;
     num_cu();
-    const kf_config r = resolve(cfg, field, meas);
+    const kf_config r = resolve(cfg, surf, field, meas);
     return enqueue_fit(&r, surf, field, meas, seeds, out, ws, (hipStream_t)stream);
 }
 
@@ -1045,7 +472,7 @@ int kf_plan_create(const kf_config* cfg, const kf_surfaces* surf, const kf_field
     rc = check_ws(meas, workspace, workspace_bytes);
     if (rc != KF_OK) { delete p; return rc; }
     num_cu();
-    const kf_config r = resolve(cfg, field, meas);
+    const kf_config r = resolve(cfg, surf, field, meas);
     if (hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess) { delete p; return KF_E_HIP; }
     if (hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipStreamDestroy(p->capture);
@@ -1094,7 +521,7 @@ int kf_autotune(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     if (!best) return KF_E_NULL;
     int rc = validate(cfg, surf, field, meas, seeds, out);
     if (rc != KF_OK) return rc;
-    *best = resolve(cfg, field, meas);
+    *best = resolve(cfg, surf, field, meas);
     if (best_ms) *best_ms = 0.0f;
     if (meas->n_tracks == 0) return KF_OK;
     rc = check_ws(meas, workspace, workspace_bytes);
@@ -1144,7 +571,7 @@ int kf_autotune(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     if (rc != KF_OK) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[tune_key(cfg, field, meas)] = win;
+        g_tune[tune_key(cfg, surf, field, meas)] = win;
     }
     *best = win;
     if (best_ms) *best_ms = best_t;
@@ -1216,7 +643,7 @@ int kf_fit_tracks_staged(const kf_config* cfg, const kf_surfaces* surf, const kf
         oc.chi2 = (double*)(slot + L.chi2);
         oc.ndf = (int32_t*)(slot + L.ndf);
         oc.status = (uint8_t*)(slot + L.status);
-        const kf_config r = resolve(cfg, field, &mc);
+        const kf_config r = resolve(cfg, surf, field, &mc);
         rc = enqueue_fit(&r, surf, field, &mc, &sc, &oc, slot + L.fit, st);
         if (rc != KF_OK) return rc;
         e = copy_rows(out->par + h0, (size_t)H * 8, slot + L.par, hb, hb, 6, outk, st);

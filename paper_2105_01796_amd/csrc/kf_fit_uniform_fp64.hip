@@ -1,0 +1,8 @@
+// The fit kernels for a uniform field with FP64 stepping.
+#include "kf_fit_kernels.hpp"
+
+namespace kffit {
+hipError_t launch_fwd_uniform_fp64(KF_FWD_ARGS) {
+    return launch_fwd<double, FIELD_UNIFORM>(a, sched, block, waves_per_cu, occ, split, storef, twof, curved, stream);
+}
+}  // namespace kffit

@@ -51,6 +51,10 @@ constexpr int V_XF = 0, V_CF = 6, V_XP = 27, V_CP = 33, V_F = 54, V_Q = 79, V_U 
 //   contribution of hit k's surface from gap k+1.
 constexpr int SX_XS = 0, SX_XPB = 6, SX_CB = 12, SX_FB = 33, SX_QB = 58, SX_AV = 60, SX_X0 = 66, SX_AA = 72,
               SX_N = 78;
+// the stash's fields are disjoint and fill [0, SX_N) (6, 6, 21, 25, 2, 6, 6, 6 doubles)
+static_assert(SX_XPB == SX_XS + 6 && SX_CB == SX_XPB + 6 && SX_FB == SX_CB + 21 && SX_QB == SX_FB + 25 &&
+              SX_AV == SX_QB + 2 && SX_X0 == SX_AV + 6 && SX_AA == SX_X0 + 6 && SX_N == SX_AA + 6,
+              "stash layout");
 typedef __attribute__((address_space(3))) double ldouble;
 
 struct VjpArgs {
@@ -684,7 +688,7 @@ int kf_fit_tracks_vjp(const kf_config* cfg, const kf_surfaces* surf, const kf_fi
     if (cfg->smoother != KF_SMOOTHER_RTS) return KF_E_VALUE;     // the reverse pass is that of RTS
     if (cfg->target != KF_TARGET_SEED_SURFACE) return KF_E_VALUE;  // ... ending on the seed surface
     if (field->kind == KF_FIELD_MAP) return KF_E_VALUE;            // analytic fields only
-    if (surf->type) return KF_E_VALUE;                             // planes only
+    if (surf->type || surf->radius) return KF_E_VALUE;             // planes only
     if (meas->n_hits > 0 && !grad->meas) return KF_E_NULL;
     const VjpLayout L = vjp_layout(meas->n_tracks, meas->n_hits, meas->max_hits, surf->n);
     if (!workspace) return KF_E_WS;

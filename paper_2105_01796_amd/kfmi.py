@@ -14,6 +14,7 @@ import ctypes as C
 import os
 from dataclasses import dataclass, replace
 
+import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
@@ -30,14 +31,14 @@ KF_SCHED_AUTO, KF_SCHED_DIRECT, KF_SCHED_SORTED = 0, 1, 2
 KF_JAC_STORE, KF_JAC_RECOMPUTE = 0, 1
 KF_SMOOTHER_RTS, KF_SMOOTHER_TWO_FILTER = 0, 1
 KF_TARGET_SEED_SURFACE, KF_TARGET_PERIGEE = 0, 1
-KF_SURF_PLANE, KF_SURF_DISC = 0, 1
+KF_SURF_PLANE, KF_SURF_DISC, KF_SURF_CYLINDER, KF_SURF_LINE = 0, 1, 2, 3
 KF_MAX_SURFACES = 512
 KF_MAX_HITS = 64
 
 
 class kf_surfaces(C.Structure):
     _fields_ = [("n", C.c_int32), ("center", C.c_void_p), ("rot", C.c_void_p), ("x_over_X0", C.c_void_p),
-                ("align", C.c_void_p), ("type", C.c_void_p)]
+                ("align", C.c_void_p), ("type", C.c_void_p), ("radius", C.c_void_p)]
 
 
 class kf_field(C.Structure):
@@ -168,6 +169,7 @@ class Batch:
     max_hits: int = 0             # 0: computed from hit_offsets
     align: torch.Tensor | None = None   # (6, S) f64 alignment corrections, or None
     surface_type: torch.Tensor | None = None   # (S,) int32 KF_SURF_* per surface, or None (all planes)
+    surface_radius: torch.Tensor | None = None   # (S,) f64 cylinder radii: set to fit cylinders and lines
     field_map: torch.Tensor | None = None   # KF_FIELD_MAP: (nz, ny, nx, 3) f64 on the device
     map_origin: tuple = (0.0, 0.0, 0.0)
     map_spacing: tuple = (1.0, 1.0, 1.0)
@@ -204,9 +206,22 @@ class Batch:
                    mass=float(ev.mass), max_hits=int(max(counts)) if len(counts) else 1,
                    align=None if align is None else _dev(align, f64, device),
                    surface_type=None if getattr(det, "stype", None) is None else _dev(det.stype, i32, device),
+                   surface_radius=_radius(det, device),
                    field_map=None if int(ev.field.kind) != KF_FIELD_MAP else _dev(ev.field.map_values, f64, device),
                    map_origin=tuple(float(v) for v in getattr(ev.field, "map_origin", (0.0, 0.0, 0.0))),
                    map_spacing=tuple(float(v) for v in getattr(ev.field, "map_spacing", (1.0, 1.0, 1.0))))
+
+
+def _radius(det, device):
+    """The detector's cylinder radii on the device when it has cylinders or
+    lines (zeros where it gives none), else None."""
+    st = getattr(det, "stype", None)
+    rad = getattr(det, "radius", None)
+    if st is None or not (np.asarray(st) >= KF_SURF_CYLINDER).any():
+        return None
+    if rad is None:
+        rad = np.zeros(len(st))
+    return _dev(rad, torch.float64, device)
 
 
 @dataclass
@@ -256,7 +271,7 @@ def _structs(b: Batch, opt: Options):
     if b.align is not None and tuple(b.align.shape) != (6, b.center.shape[1]):
         raise ValueError("align must have shape (6, S)")
     surf = kf_surfaces(b.center.shape[1], _ptr(b.center), _ptr(b.rot), _ptr(b.x_over_X0), _ptr(b.align),
-                       _ptr(b.surface_type))
+                       _ptr(b.surface_type), _ptr(b.surface_radius))
     if b.field_kind == KF_FIELD_MAP:
         if b.field_map is None or b.field_map.dim() != 4 or b.field_map.shape[3] != 3:
             raise ValueError("field_map must have shape (nz, ny, nx, 3)")

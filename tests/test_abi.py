@@ -113,6 +113,14 @@ def test_argument_validation(kf):
     assert _call(kf, *a) == kf.KF_E_VALUE
     cfg.perigee[1] = 0.0
     cfg.target = kf.KF_TARGET_SEED_SURFACE
+    # cylinders and lines (surface types with radii) run one wave per SIMD only
+    surf.type = C.c_void_p(0x1000)
+    surf.radius = C.c_void_p(0x1000)
+    cfg.occupancy = 2
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.occupancy = 0
+    surf.type = None
+    surf.radius = None
     # tabulated field: pointer, grid size and spacing are checked
     fld.kind = kf.KF_FIELD_MAP
     assert _call(kf, *a) == kf.KF_E_NULL
@@ -234,6 +242,9 @@ def test_vjp_argument_validation(kf):
     surf.type = C.c_void_p(0x4000)              # ... on planes
     assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_VALUE
     surf.type = None
+    surf.radius = C.c_void_p(0x4000)            # (no cylinders)
+    assert _vjp_call(kf, cfg, surf, fld, meas, seeds, cot, grad) == kf.KF_E_VALUE
+    surf.radius = None
     fld.kind = kf.KF_FIELD_MAP                  # ... in an analytic field
     fld.map = C.c_void_p(0x3000)
     fld.map_n[0] = fld.map_n[1] = fld.map_n[2] = 4
