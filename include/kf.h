@@ -100,6 +100,16 @@ extern "C" {
 #define KF_JAC_STORE 0         /* transport Jacobians stored by the filter, read by the smoother */
 #define KF_JAC_RECOMPUTE 1     /* smoother re-propagates the filtered state (less memory traffic) */
 
+#define KF_OUT_AUTO 0          /* from the autotune table, else STAGED */
+#define KF_OUT_STAGED 1        /* RTS: the wave's smoothed states are staged in LDS and written to the
+                                  outputs every two smoother steps (no round trip through the
+                                  workspace) */
+#define KF_OUT_SLOTS 2         /* RTS: each smoothed state replaces its hit's prediction in the
+                                  workspace; a tile's outputs are then written four hits at a time
+                                  (longer runs per track, one more workspace round trip).  The two
+                                  paths give the same outputs bit for bit; the two-filter smoother
+                                  always writes through its slots */
+
 #define KF_SMOOTHER_RTS 0         /* Rauch-Tung-Striebel with the forward pass's transport Jacobians */
 #define KF_SMOOTHER_TWO_FILTER 1  /* a second Kalman filter from the last hit back to the seed surface,
                                      propagating against the direction of flight, combined with the
@@ -225,6 +235,7 @@ typedef struct {
                                     KF_ST_NO_INTERSECT / KF_ST_STEP_CAP and NaN outputs.
                                     kf_fit_tracks_vjp supports the seed surface only */
     double perigee[3];           /* PERIGEE: a point c of the line (mm) */
+    int32_t output;              /* KF_OUT_*: how the RTS smoother's states reach the outputs */
 } kf_config;
 
 typedef struct {
@@ -277,13 +288,15 @@ void kf_plan_destroy(kf_plan *plan);
 /* Launch-shape autotuner (the paper's grid/block/register studies, Sect. 5.3,
  * made automatic): times every candidate schedule (direct / length-sorted
  * persistent), workgroup size, register budget (waves per SIMD), fused or
- * separate smoother kernel, stored or recomputed transport Jacobians (RTS
- * only: a two-filter fit tries the fused kernel alone) and
+ * separate smoother kernel, stored or recomputed transport Jacobians, the
+ * output path (RTS only: a two-filter fit tries the fused kernel alone; a
+ * fixed cfg->output is kept) and
  * persistent waves per CU on these very buffers
  * (outputs are overwritten), synchronising `stream`.  Writes the fastest
  * setting to *best (and its time per fit to *best_ms if not NULL) and
  * remembers it: later calls with AUTO (0) settings and the same precision,
- * field kind, smoother, max_hits and track count (to a power of two) use it. */
+ * field kind, smoother, surface kinds (with or without cylinders and lines),
+ * max_hits and track count (to a power of two) use it. */
 int kf_autotune(const kf_config *cfg, const kf_surfaces *surf, const kf_field *field,
                 const kf_measurements *meas, const kf_seeds *seeds, const kf_outputs *out,
                 void *workspace, size_t workspace_bytes, void *stream, kf_config *best, float *best_ms);

@@ -419,6 +419,7 @@ inline int validate_inputs(const kf_config* cfg, const kf_surfaces* surf, const 
         (cfg->split_smoother || !(cfg->bwd_scale == 0.0 || (cfg->bwd_scale > 1.0 && isfinite(cfg->bwd_scale)))))
         return KF_E_VALUE;
     if (cfg->target != KF_TARGET_SEED_SURFACE && cfg->target != KF_TARGET_PERIGEE) return KF_E_VALUE;
+    if (cfg->output != KF_OUT_AUTO && cfg->output != KF_OUT_STAGED && cfg->output != KF_OUT_SLOTS) return KF_E_VALUE;
     if (cfg->target == KF_TARGET_PERIGEE &&
         !(isfinite(cfg->perigee[0]) && isfinite(cfg->perigee[1]) && isfinite(cfg->perigee[2])))
         return KF_E_VALUE;

@@ -126,7 +126,7 @@ int validate(const kf_config* cfg, const kf_surfaces* surf, const kf_field* fiel
 // The split smoother's kernel, after the filter kernel on the same stream
 // (SORTED: up to 8 persistent waves per CU pull the tiles again).
 hipError_t launch_bwd(const FitArgs& a, int sched, int block, bool curved, hipStream_t stream) {
-    const size_t shm = (size_t)(block / TILE) * WAVE_LDS_DOUBLES * sizeof(double);
+    const size_t shm = (size_t)(block / TILE) * a.wave_lds * sizeof(double);
     const int need = (a.n_tiles * TILE + block - 1) / block;
     int grid = need;
     if (sched == KF_SCHED_SORTED) {
@@ -210,6 +210,19 @@ int enqueue_fit(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     const int wpc = cfg->waves_per_cu;
     // the kernels for cylinders and lines are built for one wave per SIMD only
     if (curved && cfg->occupancy != 1) return KF_E_VALUE;
+    // LDS per wave: the output transpose of the two-filter smoother and of
+    // KF_OUT_SLOTS, or the RTS smoother's output stage (KF_OUT_STAGED) of two
+    // steps where the workgroups of a CU at the kernel's occupancy (4 x
+    // occupancy waves) still fit beside their surface tables, else of one step
+    if (twof || cfg->output == KF_OUT_SLOTS) {
+        a.stage_hits = 0;
+        a.wave_lds = WAVE_LDS_DOUBLES;
+    } else {
+        const int wgs = 4 * cfg->occupancy / (block / TILE) > 0 ? 4 * cfg->occupancy / (block / TILE) : 1;
+        const size_t two = (size_t)wgs * fwd_lds_bytes(surf->n, block, wave_lds_doubles(STAGE_MAX_HITS));
+        a.stage_hits = two <= lds_cap() ? STAGE_MAX_HITS : 1;
+        a.wave_lds = wave_lds_doubles(a.stage_hits);
+    }
 
     hipError_t e = hipSuccess;
     if (sched == KF_SCHED_SORTED) {
@@ -294,6 +307,7 @@ kf_config resolve(const kf_config* cfg, const kf_surfaces* surf, const kf_field*
         r.split_smoother = r.smoother == KF_SMOOTHER_TWO_FILTER ? 0 : d.split_smoother;
         r.jacobians = d.jacobians;
     }
+    if (r.output == KF_OUT_AUTO) r.output = d.output == KF_OUT_AUTO ? KF_OUT_STAGED : d.output;
     if (r.block == 0) r.block = d.block;
     if (r.occupancy == 0) r.occupancy = d.occupancy;
     if (r.waves_per_cu == 0) r.waves_per_cu = d.waves_per_cu;
@@ -536,15 +550,19 @@ int kf_autotune(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
     static const int occs[] = {1, 2, 3};
     static const int splits[] = {0, 1, 2};     // 2: fused smoother recomputing the Jacobians
     static const int wpcs[] = {4, 8};
+    static const int outputs[] = {KF_OUT_STAGED, KF_OUT_SLOTS};
+    const bool twof = cfg->smoother == KF_SMOOTHER_TWO_FILTER;
     float best_t = 1e30f;
     kf_config win = *best;
     for (int sc : scheds)
         for (int bl : blocks)
             for (int oc : occs)
                 for (int sp : splits)
-                    for (int wp : wpcs) {
+                    for (int wp : wpcs)
+                        for (int op : outputs) {
                         if (sc == KF_SCHED_DIRECT && wp != wpcs[0]) continue;   // unused by DIRECT
-                        if (cfg->smoother == KF_SMOOTHER_TWO_FILTER && sp != 0) continue;   // fused only
+                        if (twof && (sp != 0 || op != outputs[0])) continue;   // fused, through its slots
+                        if (!twof && cfg->output != KF_OUT_AUTO && op != cfg->output) continue;   // fixed
                         kf_config c = *cfg;
                         c.schedule = sc;
                         c.block = bl;
@@ -552,6 +570,7 @@ int kf_autotune(const kf_config* cfg, const kf_surfaces* surf, const kf_field* f
                         c.split_smoother = sp == 1;
                         c.jacobians = sp == 2 ? KF_JAC_RECOMPUTE : KF_JAC_STORE;
                         c.waves_per_cu = wp;
+                        c.output = op;
                         rc = enqueue_fit(&c, surf, field, meas, seeds, out, workspace, stream);   // warm-up
                         if (rc == KF_E_VALUE) { rc = KF_OK; continue; }   // does not fit this device
                         if (rc != KF_OK) break;

@@ -30,6 +30,15 @@ constexpr int FLUSH_HITS = 4;
 constexpr int FLUSH_GROUP = 5;
 constexpr int FLUSH_DOUBLES = FLUSH_GROUP * FLUSH_HITS * TILE + FLUSH_HITS * TILE;
 constexpr int WAVE_LDS_DOUBLES = CARRY * TILE > FLUSH_DOUBLES ? CARRY * TILE : FLUSH_DOUBLES;
+// The RTS smoother's output stage (smooth_staged): sh smoother steps of the
+// wave's 64 smoothed states [27][sh][64] doubles, then the (lane, row) list
+// and the CSR indices of one write-out (2 x sh x 64 ints); sh is 2 where the
+// LDS holds it, else 1.
+constexpr int STAGE_MAX_HITS = 2;
+__host__ __device__ constexpr int stage_doubles(int sh) { return 27 * sh * TILE + sh * TILE; }
+__host__ __device__ constexpr int wave_lds_doubles(int sh) {
+    return stage_doubles(sh) > WAVE_LDS_DOUBLES ? stage_doubles(sh) : WAVE_LDS_DOUBLES;
+}
 
 struct FitArgs {
     int n_tracks;
@@ -69,6 +78,8 @@ struct FitArgs {
     int n_tiles;
     double bwd_scale;           // two-filter smoother: inflation of the backward filter's start
     double perigee[3];          // perigee target: a point of the line (parallel to z)
+    int stage_hits;             // RTS smoother: steps staged in LDS per write-out (1 or 2; 0: through the slots)
+    int wave_lds;               // doubles of LDS per wave (carry, stage or flush area)
 };
 
 // Hit k of the track at CSR offset o lies on a disc (its azimuth wraps).
@@ -281,7 +292,8 @@ __device__ void fwd_one(const FitArgs& a, const double* __restrict__ sm, double*
 // follows from the next hit's stored prediction and Jacobian with the gain
 // A = Cf F^T Cp^-1 solved in FP64.  The smoothed state of hit k replaces the
 // prediction in slot k once that has been read for the last time; flush_tile
-// then writes the tile's CSR outputs.  Without stored Jacobians (STOREF
+// then writes the tile's CSR outputs (output path KF_OUT_SLOTS; smooth_staged
+// is the same smoother with KF_OUT_STAGED).  Without stored Jacobians (STOREF
 // false; fused only, sm is the surface table) F of the gap k -> k+1 comes from
 // propagating the recomputed filtered state of hit k (or the seed) again with
 // the forward pass's routine.  Returns true if the track's smoothed states are
@@ -384,6 +396,214 @@ __device__ bool bwd_one(const FitArgs& a, const double* __restrict__ sm, int64_t
         for (int q = 0; q < 21; ++q) C[q] = Cf[q];
         phase_boundary();
     }
+    if (spd && fail == ST_OK) {
+        store_rows(a.tgt_par + t, N, x);
+        store_rows(a.tgt_cov + t, N, C);
+        return true;
+    }
+    // a predicted covariance that is not positive definite (or a propagation
+    // that did not repeat): the track fails
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    for (int k = 0; k < n; ++k) {
+        fill_rows<6>(a.par + o + k, H, nan);
+        fill_rows<21>(a.pcov + o + k, H, nan);
+    }
+    fill_rows<6>(a.tgt_par + t, N, nan);
+    fill_rows<21>(a.tgt_cov + t, N, nan);
+    a.chi2[t] = nan;
+    a.status[t] = (uint8_t)(fail != ST_OK ? fail : ST_NOT_SPD);
+    return false;
+}
+
+// All lanes of the wave, in step: LDS written by one lane is then visible to
+// the others (the waves of a workgroup run different tiles, so no workgroup
+// barrier may be used here).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Write-out of the smoothing stage: every lane's entries of the last `rows`
+// steps (steps it - rows + 1 .. it; step i holds the smoothed state of hit
+// n - 1 - i of the lane's track, from row i % sh) go to the CSR outputs.  The
+// wave lists the (lane, row) pairs in the order of their CSR indices (a
+// lane's entries are consecutive hits), then for each component consecutive
+// lanes store consecutive entries of that list.  Every lane of the wave calls
+// it (fitted: the lane's track has smoothed states; o, n: its CSR range).
+__device__ inline void stage_write(const FitArgs& a, double* stg, int sh, int rows, int it, bool fitted, int o,
+                                   int n) {
+    const int lane = threadIdx.x & (TILE - 1);
+    int32_t* own = (int32_t*)(stg + 27 * sh * TILE);      // [sh * 64]: lane | row << 6
+    int32_t* dst = own + sh * TILE;                        // [sh * 64]: CSR index
+    const int i0 = it - rows + 1;
+    const int i1 = it < n - 1 ? it : n - 1;
+    const int cnt = fitted && i1 >= i0 ? i1 - i0 + 1 : 0;
+    int inc = cnt;
+#pragma unroll
+    for (int d = 1; d < TILE; d <<= 1) {
+        const int u = __shfl_up(inc, d, TILE);
+        if (lane >= d) inc += u;
+    }
+    const int start = inc - cnt;
+    const int total = __shfl(inc, TILE - 1, TILE);
+    for (int e = 0; e < cnt; ++e) {
+        const int i = i1 - e;                              // ascending hit index
+        own[start + e] = lane | ((i % sh) << 6);
+        dst[start + e] = o + n - 1 - i;
+    }
+    wave_sync();
+    const int64_t H = a.n_hits;
+    for (int g = lane; g < total; g += TILE) {
+        const int e = own[g];
+        const int64_t d = dst[g];
+        const double* src = stg + (e >> 6) * TILE + (e & 63);
+#pragma unroll
+        for (int c = 0; c < 27; ++c) {
+            double* out = c < 6 ? a.par + (int64_t)c * H : a.pcov + (int64_t)(c - 6) * H;
+            out[d] = src[c * sh * TILE];
+        }
+    }
+    wave_sync();
+}
+
+// RTS smoother of the wave's tracks (Sect. 2), fused after the forward pass
+// or run by a separate streaming kernel: the smoothed state of the last hit
+// is its filtered state; every earlier state, and finally the seed/target
+// state, follows from the next hit's stored prediction and Jacobian with the
+// gain A = Cf F^T Cp^-1 solved in FP64.  Without stored Jacobians (STOREF
+// false; fused only, sm is the surface table) F of the gap k -> k+1 comes from
+// propagating the recomputed filtered state of hit k (or the seed) again with
+// the forward pass's routine.  The lanes step together (step `it` smooths
+// hit n - 1 - it of each lane's track), each lane puts its smoothed state
+// into the wave's LDS stage, and every `sh` steps the wave writes the stage to
+// the CSR outputs (stage_write): the states never travel through the
+// workspace.  Every lane of the wave calls it (have: the lane holds track t
+// in workspace slot `slot`; lw: the wave's LDS area).  Returns true if the
+// track was smoothed (false: not fitted, or failed here with NaN outputs).
+// CV: surfaces of every type.
+template <class P, int FK, bool STOREF, bool CV>
+__device__ bool smooth_staged(const FitArgs& a, const double* __restrict__ sm, double* lw, int64_t slot, int t,
+                              bool have) {
+    constexpr int NW = nc_of<STOREF>();
+    const int lane = threadIdx.x & (TILE - 1);
+    const int sh = a.stage_hits;
+    const int64_t H = a.n_hits;
+    const int64_t N = a.n_tracks;
+    const bool fitted = have && a.status[t] == ST_OK;
+    int o = 0, n = 0;
+    if (fitted) {
+        o = a.off[t];
+        n = a.off[t + 1] - o;
+    }
+    int nmax = n;
+#pragma unroll
+    for (int d = 1; d < TILE; d <<= 1) {
+        const int v = __shfl_xor(nmax, d, TILE);
+        nmax = v > nmax ? v : nmax;
+    }
+    double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
+    Field<P, FK> fl;
+    if (!STOREF) fl.init(a.field);
+    // prediction of hit k+1 (carried from one step to the next)
+    double xp1[6], Cp1[21];
+    double x[6], C[21];
+    bool ang1 = false;
+    int s1 = 0;                                         // surface of hit k+1
+    if (fitted) {
+        const double* w = wl + (n - 1) * (NW * TILE);
+        double m[2], V[3], ck;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) xp1[i] = w[(OFF_XP + i) * TILE];
+#pragma unroll
+        for (int q = 0; q < 21; ++q) Cp1[q] = w[(OFF_CP + q) * TILE];
+        load_rows(a.loc + o + n - 1, H, m);
+        load_rows(a.cov + o + n - 1, H, V);
+        const int kind1 = hit_kind<CV>(a, o, n - 1);
+        update_kind<CV>(kind1, xp1, Cp1, m, V, x, C, &ck);
+        ang1 = kind_ang<CV>(kind1);
+        if (!STOREF) s1 = a.sid[o + n - 1];
+    }
+    bool spd = true;
+    int fail = ST_OK;
+    // step `it` smooths hit k = n - 1 - it (k = -1: the seed/target surface);
+    // step 0 is the last hit, whose smoothed state is its filtered state
+    for (int it = 0; it <= nmax; ++it) {
+        const int k = n - 1 - it;
+        if (fitted && it > 0 && k >= -1) {
+            double* w1 = wl + (k + 1) * (NW * TILE);
+            // every load of this step at once: F of hit k+1 (if stored), the
+            // prediction and measurement of hit k (or the seed)
+            double F[25], xp[6], Cp[21], m[2], V[3], xf[6], Cf[21];
+            if (STOREF) {
+#pragma unroll
+                for (int q = 0; q < 25; ++q) F[q] = w1[(OFF_F + q) * TILE];
+            }
+            int s0 = a.seed_sid;
+            if (k >= 0) {
+                const double* w = wl + k * (NW * TILE);
+#pragma unroll
+                for (int i = 0; i < 6; ++i) xp[i] = w[(OFF_XP + i) * TILE];
+#pragma unroll
+                for (int q = 0; q < 21; ++q) Cp[q] = w[(OFF_CP + q) * TILE];
+                load_rows(a.loc + o + k, H, m);
+                load_rows(a.cov + o + k, H, V);
+                if (!STOREF) s0 = a.sid[o + k];
+            } else {
+                load_rows(a.seed + t, N, xf);
+                load_rows(a.seed_cov + t, N, Cf);
+            }
+            double dx[6], L[21], id[6];
+            spd = chol6(Cp1, L, id) && spd;
+            rts_diff(x, C, xp1, Cp1, dx, ang1);              // C now holds D = Cs1 - Cp1
+            const int kind0 = k >= 0 ? hit_kind<CV>(a, o, k) : 0;
+            const bool ang0 = kind_ang<CV>(kind0);
+            if (k >= 0) {
+                double ck;
+                update_kind<CV>(kind0, xp, Cp, m, V, xf, Cf, &ck);   // filtered state of hit k, as in the forward pass
+#pragma unroll
+                for (int i = 0; i < 6; ++i) xp1[i] = xp[i];
+#pragma unroll
+                for (int q = 0; q < 21; ++q) Cp1[q] = Cp[q];
+            }
+            if (!STOREF) {
+                // F of the gap from hit k (or the seed) to hit k+1, as the forward pass propagated it
+                phase_boundary();
+                double xq[6];
+                int tr = 0;
+                const int st = transport_any<CV>(fl, a.field, a.cfg, sm + s0 * SURF_STRIDE, sm + s1 * SURF_STRIDE,
+                                                 xf, xq, F, &tr);
+                if (st != ST_OK && fail == ST_OK) fail = st;
+                s1 = s0;
+            }
+            phase_boundary();
+            double A[36];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                double g[6];
+                smoother_gain_row(F, Cf, L, id, c, g);
+#pragma unroll
+                for (int i = 0; i < 6; ++i) A[6 * c + i] = g[i];
+            }
+            phase_boundary();
+            rts_mean(xf, A, dx, x, ang0);
+            rts_cov(A, C, Cf);
+            ang1 = ang0;
+#pragma unroll
+            for (int q = 0; q < 21; ++q) C[q] = Cf[q];
+            phase_boundary();
+        }
+        // the smoothed state of hit k into this step's row of the stage
+        const int row = it % sh;
+        if (fitted && k >= 0) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) lw[(i * sh + row) * TILE + lane] = x[i];
+#pragma unroll
+            for (int q = 0; q < 21; ++q) lw[((6 + q) * sh + row) * TILE + lane] = C[q];
+        }
+        if (row == sh - 1 || it == nmax) stage_write(a, lw, sh, row + 1, it, fitted, o, n);
+    }
+    if (!fitted) return false;
     if (spd && fail == ST_OK) {
         store_rows(a.tgt_par + t, N, x);
         store_rows(a.tgt_cov + t, N, C);
@@ -513,17 +733,9 @@ __device__ bool bwd_two_filter(const FitArgs& a, const double* __restrict__ sm, 
     return false;
 }
 
-// All lanes of the wave, in step: LDS written by one lane is then visible to
-// the others (the waves of a workgroup run different tiles, so no workgroup
-// barrier may be used here).
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 // Write the smoothed states of a tile's tracks (left in their workspace slots
-// by bwd_one) to the CSR outputs.  One lane per track computed them; a store
+// by the two-filter smoother, or by bwd_one) to the CSR outputs.  One lane per track computed them; a store
 // from each lane would touch a different cache line per lane.  Instead, for a
 // block of FLUSH_HITS hits: every lane loads its 27 x FLUSH_HITS values at
 // once (coalesced: the slots are tile-major), the wave lists which (lane,
@@ -612,67 +824,83 @@ k_fwd(FitArgs a) {
     extern __shared__ double sm[];
     stage_surfaces(a.n_surf, a.center, a.rot, a.x0, a.align, a.stype, sm, CV ? a.radius : nullptr);
     const int lane = threadIdx.x & (TILE - 1);
-    double* cl = sm + a.n_surf * SURF_STRIDE + (threadIdx.x / TILE) * WAVE_LDS_DOUBLES + lane;
+    double* lw = sm + a.n_surf * SURF_STRIDE + (threadIdx.x / TILE) * a.wave_lds;
+    double* cl = lw + lane;
     int iter = 0;
     for (;;) {
         const int tile = next_tile<SORTED>(a.tile_counter, iter);
         if (tile >= a.n_tiles) break;
         const int64_t i = (int64_t)tile * TILE + lane;
-        bool done = false;
-        int o = 0, n = 0;
-        if (i < a.n_tracks) {
-            const int t = SORTED ? a.order[i] : (int)i;
-            fwd_one<P, FK, STOREF, CV>(a, sm, cl, i, t);
-            if constexpr (TWOF) {
+        const bool have = i < a.n_tracks;
+        const int t = have ? (SORTED ? a.order[i] : (int)i) : 0;
+        if (have) fwd_one<P, FK, STOREF, CV>(a, sm, cl, i, t);
+        if constexpr (TWOF) {
+            bool done = false;
+            int o = 0, n = 0;
+            if (have) {
                 done = bwd_two_filter<P, FK, CV>(a, sm, i, t);
                 o = a.off[t];
                 n = a.off[t + 1] - o;
-            } else if constexpr (FUSED) {
-                done = bwd_one<P, FK, STOREF, CV>(a, sm, i, t);
-                o = a.off[t];
-                n = a.off[t + 1] - o;
+            }
+            flush_tile<NC_RECOMPUTE>(a, lw, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
+        } else if constexpr (FUSED) {
+            if (a.stage_hits > 0) {
+                smooth_staged<P, FK, STOREF, CV>(a, sm, lw, i, t, have);
+            } else {
+                bool done = false;
+                int o = 0, n = 0;
+                if (have) {
+                    done = bwd_one<P, FK, STOREF, CV>(a, sm, i, t);
+                    o = a.off[t];
+                    n = a.off[t + 1] - o;
+                }
+                flush_tile<nc_of<STOREF>()>(a, lw, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
             }
         }
-        if (FUSED) flush_tile<nc_of<STOREF>()>(a, cl - lane, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
     }
 }
 
 // Backward (smoother) pass as its own kernel (launched after k_fwd<..., FUSED
-// false, ...>).  Dynamic LDS: per wave the output transpose.  CV: hits on
-// surfaces of every type.
+// false, ...>).  Dynamic LDS: per wave the smoother's output stage or the
+// output transpose.  CV: hits on surfaces of every type.
 template <bool SORTED, bool CV>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 k_bwd(FitArgs a) {
     extern __shared__ double sm[];
     const int lane = threadIdx.x & (TILE - 1);
-    double* lw = sm + (threadIdx.x / TILE) * WAVE_LDS_DOUBLES;
+    double* lw = sm + (threadIdx.x / TILE) * a.wave_lds;
     int iter = 0;
     for (;;) {
         const int tile = next_tile<SORTED>(a.tile_counter + 1, iter);
         if (tile >= a.n_tiles) break;
         const int64_t i = (int64_t)tile * TILE + lane;
-        bool done = false;
-        int o = 0, n = 0;
-        if (i < a.n_tracks) {
-            const int t = SORTED ? a.order[i] : (int)i;
-            done = bwd_one<double, FIELD_UNIFORM, true, CV>(a, nullptr, i, t);
-            o = a.off[t];
-            n = a.off[t + 1] - o;
+        const bool have = i < a.n_tracks;
+        const int t = have ? (SORTED ? a.order[i] : (int)i) : 0;
+        if (a.stage_hits > 0) {
+            smooth_staged<double, FIELD_UNIFORM, true, CV>(a, nullptr, lw, i, t, have);
+        } else {
+            bool done = false;
+            int o = 0, n = 0;
+            if (have) {
+                done = bwd_one<double, FIELD_UNIFORM, true, CV>(a, nullptr, i, t);
+                o = a.off[t];
+                n = a.off[t + 1] - o;
+            }
+            flush_tile<NC>(a, lw, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
         }
-        flush_tile<NC>(a, lw, a.ws + (int64_t)tile * a.tile_doubles, done, o, n);
     }
 }
 
 // Dynamic LDS of k_fwd: the surface table and one area per wave
-inline size_t fwd_lds_bytes(int n_surf, int block) {
-    return ((size_t)n_surf * SURF_STRIDE + (size_t)(block / TILE) * WAVE_LDS_DOUBLES) * sizeof(double);
+inline size_t fwd_lds_bytes(int n_surf, int block, int wave_lds) {
+    return ((size_t)n_surf * SURF_STRIDE + (size_t)(block / TILE) * wave_lds) * sizeof(double);
 }
 
 // Launch k_fwd for one schedule: SORTED runs min(tiles, CUs x waves_per_cu)
 // persistent waves, DIRECT one wave per tile.
 template <class P, int FK, int OCC, bool FUSED, bool STOREF, bool TWOF, bool CV>
 hipError_t launch_fwd_kernel(const FitArgs& a, int sched, int block, int waves_per_cu, hipStream_t stream) {
-    const size_t shm = fwd_lds_bytes(a.n_surf, block);
+    const size_t shm = fwd_lds_bytes(a.n_surf, block, a.wave_lds);
     const int need = (a.n_tiles * TILE + block - 1) / block;
     hipError_t e = hipSuccess;
     if (sched == KF_SCHED_SORTED) {

@@ -29,6 +29,7 @@ KF_FIELD_UNIFORM, KF_FIELD_SOLENOID, KF_FIELD_MAP = 0, 1, 2
 KF_PREC_FP64, KF_PREC_MIXED = 0, 1
 KF_SCHED_AUTO, KF_SCHED_DIRECT, KF_SCHED_SORTED = 0, 1, 2
 KF_JAC_STORE, KF_JAC_RECOMPUTE = 0, 1
+KF_OUT_AUTO, KF_OUT_STAGED, KF_OUT_SLOTS = 0, 1, 2
 KF_SMOOTHER_RTS, KF_SMOOTHER_TWO_FILTER = 0, 1
 KF_TARGET_SEED_SURFACE, KF_TARGET_PERIGEE = 0, 1
 KF_SURF_PLANE, KF_SURF_DISC, KF_SURF_CYLINDER, KF_SURF_LINE = 0, 1, 2, 3
@@ -62,7 +63,7 @@ class kf_config(C.Structure):
                 ("schedule", C.c_int32), ("block", C.c_int32), ("waves_per_cu", C.c_int32),
                 ("occupancy", C.c_int32), ("split_smoother", C.c_int32), ("jacobians", C.c_int32),
                 ("smoother", C.c_int32), ("bwd_scale", C.c_double), ("target", C.c_int32),
-                ("perigee", C.c_double * 3)]
+                ("perigee", C.c_double * 3), ("output", C.c_int32)]
 
 
 class kf_outputs(C.Structure):
@@ -254,6 +255,7 @@ class Options:
     bwd_scale: float = 0.0      # two-filter: backward start covariance inflation (0 = 1e3)
     target: int = 0             # KF_TARGET_SEED_SURFACE / KF_TARGET_PERIGEE
     perigee: tuple = (0.0, 0.0, 0.0)   # perigee target: a point of the line parallel to z (mm)
+    output: int = 0             # KF_OUT_AUTO / KF_OUT_STAGED / KF_OUT_SLOTS (RTS smoother's output path)
 
 
 def _max_hits(b: Batch) -> int:
@@ -267,7 +269,7 @@ def _structs(b: Batch, opt: Options):
     """kf_config, kf_surfaces, kf_field, kf_measurements, kf_seeds for a batch."""
     cfg = kf_config(opt.precision, int(b.multiple_scattering), b.mass, opt.rk_tol, opt.land_tol, opt.max_steps,
                     opt.schedule, opt.block, opt.waves_per_cu, opt.occupancy, opt.split_smoother, opt.jacobians,
-                    opt.smoother, opt.bwd_scale, opt.target, (C.c_double * 3)(*opt.perigee))
+                    opt.smoother, opt.bwd_scale, opt.target, (C.c_double * 3)(*opt.perigee), opt.output)
     if b.align is not None and tuple(b.align.shape) != (6, b.center.shape[1]):
         raise ValueError("align must have shape (6, S)")
     surf = kf_surfaces(b.center.shape[1], _ptr(b.center), _ptr(b.rot), _ptr(b.x_over_X0), _ptr(b.align),
@@ -347,7 +349,7 @@ class Plan:
         self.release()
         o = Options(best.precision, best.rk_tol, best.land_tol, best.max_steps, best.schedule, best.block,
                     best.waves_per_cu, best.occupancy, best.split_smoother, best.jacobians, best.smoother,
-                    best.bwd_scale, best.target, tuple(best.perigee))
+                    best.bwd_scale, best.target, tuple(best.perigee), best.output)
         return o, ms.value
 
     def release(self):

@@ -113,6 +113,9 @@ def test_argument_validation(kf):
     assert _call(kf, *a) == kf.KF_E_VALUE
     cfg.perigee[1] = 0.0
     cfg.target = kf.KF_TARGET_SEED_SURFACE
+    cfg.output = 3                               # KF_OUT_* out of range
+    assert _call(kf, *a) == kf.KF_E_VALUE
+    cfg.output = kf.KF_OUT_SLOTS
     # cylinders and lines (surface types with radii) run one wave per SIMD only
     surf.type = C.c_void_p(0x1000)
     surf.radius = C.c_void_p(0x1000)
