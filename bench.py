@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--jacobians", choices=("store", "recompute"), default="store",
                     help="without --autotune: transport Jacobians stored for the smoother or recomputed by it")
+    ap.add_argument("--output", choices=("auto", "staged", "slots"), default="auto",
+                    help="RTS smoother output path (auto: the autotuner's, else staged)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the fit + adjoint leg")
     ap.add_argument("--no-two-filter", action="store_true", help="skip the two-filter smoother leg")
@@ -208,7 +210,9 @@ def main():
     N = ev.n_tracks
     base_opt = dict(schedule=args.schedule, block=args.block, occupancy=args.occupancy,
                     waves_per_cu=args.waves_per_cu,
-                    jacobians=kfmi.KF_JAC_RECOMPUTE if args.jacobians == "recompute" else kfmi.KF_JAC_STORE)
+                    jacobians=kfmi.KF_JAC_RECOMPUTE if args.jacobians == "recompute" else kfmi.KF_JAC_STORE,
+                    output={"auto": kfmi.KF_OUT_AUTO, "staged": kfmi.KF_OUT_STAGED,
+                            "slots": kfmi.KF_OUT_SLOTS}[args.output])
 
     if args.copy_calibration:
         src = torch.empty(1 << 26, dtype=torch.float64, device=dev).fill_(1.0)
@@ -226,6 +230,7 @@ def main():
             tuned = {"schedule": opt.schedule, "block": opt.block, "occupancy": opt.occupancy,
                      "waves_per_cu": opt.waves_per_cu, "split_smoother": opt.split_smoother,
                      "jacobians": "recompute" if opt.jacobians == kfmi.KF_JAC_RECOMPUTE else "store",
+                     "output": "slots" if opt.output == kfmi.KF_OUT_SLOTS else "staged",
                      "tuner_ms": round(tune_ms, 4)}
         if not args.no_graph:
             plan.capture()
@@ -285,6 +290,7 @@ def main():
         if tuned64:
             opt_st.update({k: tuned64[k] for k in ("schedule", "block", "occupancy", "waves_per_cu", "split_smoother")})
             opt_st["jacobians"] = kfmi.KF_JAC_RECOMPUTE if tuned64["jacobians"] == "recompute" else kfmi.KF_JAC_STORE
+            opt_st["output"] = kfmi.KF_OUT_SLOTS if tuned64["output"] == "slots" else kfmi.KF_OUT_STAGED
         runs = {}
         for chunks, streams in ((1, 1), (4, 2), (8, 2), (8, 3)):
             sp = kfmi.StagedPlan(bh, kfmi.Options(**opt_st), n_chunks=chunks, n_streams=streams)
