@@ -180,7 +180,12 @@ struct Surf {                 // R columns: u, v, n; x0 = thickness in X0
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
+// Angle into (-pi, pi].  An angle of 64 rad or more (ten turns) is no angle
+// a fit of inputs at the detector's scale produces (only absurd hit or seed
+// values lead there): it becomes NaN, the track then fails, and no input keeps
+// the loops going (reading r28).
 template <class S> inline S wrap_phi(S phi) {
+    if (!(std::fabs(val(phi)) < 64.0)) return S(NAN);
     while (val(phi) > kPi) phi = phi - 2.0 * kPi;
     while (val(phi) <= -kPi) phi = phi + 2.0 * kPi;
     return phi;

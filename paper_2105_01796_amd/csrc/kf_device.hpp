@@ -128,7 +128,12 @@ __device__ inline void cross(const P a[3], const P b[3], P o[3]) {
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// Angle into (-pi, pi].  Every angle a fit of inputs at the detector's scale
+// produces lies within a few turns; one of 64 rad or more (ten turns; only
+// absurd hit or seed values lead there) becomes NaN, which ends both loops at
+// once, so no input can keep a lane looping (the track then fails).
 __device__ inline double wrap_phi(double p) {
+    p = ::fabs(p) < 64.0 ? p : __longlong_as_double(0x7ff8000000000000LL);
     while (p > kPi) p -= 2.0 * kPi;
     while (p <= -kPi) p += 2.0 * kPi;
     return p;

@@ -292,3 +292,23 @@ def test_autotuner_picks_a_valid_shape(kf):
     rng = np.random.default_rng(7)
     idx = np.unique(rng.choice(ev.n_tracks, 300, replace=False))
     compare(_sampled(out, ev, idx), _ref(ev.subset(idx)), label="autotuned")
+
+
+@pytest.mark.parametrize("cfg,comp", [(7, 1), (2, 0)])
+def test_absurd_hit_value_ends(kf, cfg, comp):
+    """A finite but absurd hit coordinate (1e200 mm or rad) passes the input
+    checks; the angle wrap turns the resulting angle into NaN (reading r28)
+    instead of looping, so the track fails (the propagation that follows
+    reaches its step cap) exactly as in the oracle, and every other track is
+    fitted as usual."""
+    _announce(f"absurd hit value: C{cfg} loc{comp} = 1e200")
+    ev = synth.make_config(cfg, 200)
+    off = ev.hit_offsets
+    ev.loc = ev.loc.copy()
+    for t in (3, 17):
+        ev.loc[comp, off[t] + 4] = 1e200
+    ref = _ref(ev)
+    assert ref.status[3] == ref.status[17] == kf.KF_ST_STEP_CAP
+    for sched in (1, 2):
+        out = _fit(kf, ev, schedule=sched)
+        compare(out, ref, label=f"absurd hit C{cfg} sched {sched}")
