@@ -1,8 +1,9 @@
 """kf_fit_tracks_noalloc (the fit with the library's static scratch as its
 workspace) against kf_fit_tracks, through the C ABI.
 
-Two calls in a row on one device, the second with a smaller input (fewer
-tracks and fewer hits per track), both schedules: the outputs equal those of
+Three calls in a row on one device, each with a smaller input than the one
+before (fewer tracks; the last also fewer hits per track), the middle one on
+cylinders and straws, both schedules: the outputs equal those of
 kf_fit_tracks with a caller workspace bit for bit, and both meet the oracle's
 FP64 bar (relative 1e-9 per element).  A batch larger than the scratch is
 refused with KF_E_SCRATCH.
@@ -53,8 +54,9 @@ def _same(a, b):
 def test_noalloc_equals_workspace_fit_on_two_calls(kf, schedule):
     import torch
     # first call: 3000 ragged tracks of up to 30 hits (the larger input), then
-    # 100 tracks of 10 hits in a uniform field with material
-    for step, (cfg, n) in enumerate(((3, 3000), (2, 100))):
+    # 1000 tracks through five cylinders and five layers of straws, then 100
+    # tracks of 10 hits on planes in a uniform field with material
+    for step, (cfg, n) in enumerate(((3, 3000), (8, 1000), (2, 100))):
         print(f"noalloc: call {step + 1}, C{cfg} n={n} schedule={schedule}", flush=True)
         ev = synth.make_config(cfg, n)
         b = kf.Batch.from_event(ev)
