@@ -120,7 +120,8 @@ __device__ inline void stl(ldouble* x, int off, const double (&v)[N]) {
 // forward sweep: filter recompute + reverse RTS mean recursion
 // ---------------------------------------------------------------------------
 template <class P, int FK>
-__device__ __attribute__((always_inline)) int vjp_fwd(const VjpArgs& a, const double* __restrict__ sm, double* wl, int t, int o, int n) {
+__device__ __attribute__((always_inline)) int vjp_fwd(const VjpArgs& a, const double* __restrict__ sm, double* wl,
+                                                      ldouble* sx, int t, int o, int n) {
     const int64_t H = a.n_hits, N = a.n_tracks;
     Field<P, FK> fl;
     fl.init(a.field);
@@ -132,10 +133,37 @@ __device__ __attribute__((always_inline)) int vjp_fwd(const VjpArgs& a, const do
 #pragma unroll
         for (int i = 0; i < 6; ++i) as[i] = 0.0;
     }
+    // The filtered covariance of the previous hit waits in the (still unused)
+    // LDS stash during each propagation, and hit k's surface, measurement and
+    // smoothed-state cotangent are loaded during hit k-1: no load of this
+    // sweep is issued behind its own workspace stores (on gfx9 one counter
+    // covers loads and stores, so such a load would wait for them).
+    {
+        double C0[21];
+        load_rows(a.seed_cov + t, N, C0);
+        stl(sx, 0, C0);
+    }
+    int s_nx = gbl(a.sid)[o];
+    double m_nx[2], V_nx[3], gp_nx[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    load_rows(a.loc + o, H, m_nx);
+    load_rows(a.cov + o, H, V_nx);
+    if (a.g_par) load_rows(a.g_par + o, H, gp_nx);
     int prev = a.seed_sid;
     int status = ST_OK;
     for (int k = 0; k < n; ++k) {
-        const int s = gbl(a.sid)[o + k];
+        const int s = s_nx;
+        const double m[2] = {m_nx[0], m_nx[1]};
+        const double V[3] = {V_nx[0], V_nx[1], V_nx[2]};
+        double gp[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) gp[i] = gp_nx[i];
+        if (k + 1 < n) {
+            s_nx = gbl(a.sid)[o + k + 1];
+            load_rows(a.loc + o + k + 1, H, m_nx);
+            load_rows(a.cov + o + k + 1, H, V_nx);
+            if (a.g_par) load_rows(a.g_par + o + k + 1, H, gp_nx);
+        }
+        phase_boundary();
         const double* sa = sm + prev * SURF_STRIDE;
         const double* sb = sm + s * SURF_STRIDE;
         double q[2] = {0.0, 0.0};
@@ -149,34 +177,28 @@ __device__ __attribute__((always_inline)) int vjp_fwd(const VjpArgs& a, const do
         st(w, V_XP, xp);
         st(w, V_F, F);
         st(w, V_Q, q);
-        double C[21];
-        if (k == 0) load_rows(a.seed_cov + t, N, C);
-        else ld(w - NCV * TILE, V_CF, C);
-        phase_boundary();
+        double C[21], Cp[21];
+        ldl(sx, 0, C);
         {
             double CQ[21];
 #pragma unroll
             for (int i = 0; i < 21; ++i) CQ[i] = C[i];
             CQ[sy(2, 2)] += q[0];
             CQ[sy(3, 3)] += q[1];
-            double Cp[21];
             transport_cov(F, CQ, Cp);
             st(w, V_CP, Cp);
         }
         phase_boundary();
         {
             // u = A^T as = Cp^-1 F C as
-            double y[6], v[6], Cp[21], L[21], id[6];
+            double y[6], v[6], L[21], id[6];
             symv(C, as, y);
             fy(F, y, v);
-            ld(w, V_CP, Cp);
             const bool spd = chol6(Cp, L, id);
             chol_solve6(L, id, v);
             st(w, V_U, v);
             if (!spd) { status = ST_NOT_SPD; break; }
             if (a.g_par) {
-                double gp[6];
-                load_rows(a.g_par + o + k, H, gp);
 #pragma unroll
                 for (int i = 0; i < 6; ++i) as[i] = v[i] + gp[i];
             } else {
@@ -186,14 +208,12 @@ __device__ __attribute__((always_inline)) int vjp_fwd(const VjpArgs& a, const do
         }
         phase_boundary();
         {
-            double Cp[21], m[2], V[3], ck;
-            ld(w, V_CP, Cp);
-            load_rows(a.loc + o + k, H, m);
-            load_rows(a.cov + o + k, H, V);
+            double ck;
             status = kalman_update(xp, Cp, m, V, x, C, &ck);
             if (status != ST_OK) break;
             st(w, V_XF, x);
             st(w, V_CF, C);
+            stl(sx, 0, C);
         }
         phase_boundary();
         prev = s;
@@ -294,19 +314,30 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
     for (int i = 0; i < 6; ++i) { xfb[i] = 0.0; aab[i] = 0.0; }
 #pragma unroll
     for (int q = 0; q < 21; ++q) Cfb[q] = 0.0;
+    // The two per-hit outputs (the hit's gradient and its alignment
+    // contribution) are stored at the start of the next iteration, after that
+    // iteration's first loads: a load issued behind a store waits for it (on
+    // gfx9 one counter covers loads and stores).
+    double mb_pend[2], c_pend[6];
 
     for (int k = n - 1; k >= 0; --k) {
         double* w = wl + k * (NCV * TILE);
         const double* wp = w - NCV * TILE;           // slot k-1 (used only for k > 0)
         const int s = gbl(a.sid)[o + k];
         const int prev = k > 0 ? gbl(a.sid)[o + k - 1] : a.seed_sid;
-        double xpb[6], Cpb[21], wv[6];
+        double xpb[6], Cpb[21], wv[6], mb[2];
         // ---- update adjoint, and w = Cp^-1 (xs_k - xp_k) ----
         {
-            double xp[6], Cp[21], m[2], V[3], mb[2];
+            double xp[6], Cp[21], m[2], V[3];
             ld(w, V_XP, xp);
             ld(w, V_CP, Cp);
             ld(w, V_U, xpb);
+            load_rows(a.loc + o + k, H, m);
+            load_rows(a.cov + o + k, H, V);
+            if (k < n - 1) {
+                store_rows(a.g_meas + o + k + 1, H, mb_pend);
+                store_rows(a.contrib + o + k + 1, a.n_items, c_pend);
+            }
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
                 xpb[i] = -xpb[i];                     // from the smoother: -A^T xsb_{k-1}
@@ -316,10 +347,7 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
             wv[2] = wrap_phi(wv[2]);
 #pragma unroll
             for (int q = 0; q < 21; ++q) Cpb[q] = 0.0;
-            load_rows(a.loc + o + k, H, m);
-            load_rows(a.cov + o + k, H, V);
             update_vjp(xp, Cp, m, V, xfb, Cfb, chi2b, xpb, Cpb, mb);
-            store_rows(a.g_meas + o + k, H, mb);
             double L[21], id[6];
             chol6(Cp, L, id);
             chol_solve6(L, id, wv);
@@ -396,7 +424,10 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
             ldl(sx, SX_AA, c);
 #pragma unroll
             for (int i = 0; i < 6; ++i) c[i] += gb[i];
-            store_rows(a.contrib + o + k, a.n_items, c);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) c_pend[i] = c[i];
+            mb_pend[0] = mb[0];
+            mb_pend[1] = mb[1];
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
@@ -408,6 +439,8 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
         ldl(sx, SX_AV, xsb);
         phase_boundary();
     }
+    store_rows(a.g_meas + o, H, mb_pend);
+    store_rows(a.contrib + o, a.n_items, c_pend);
     if (a.g_seed) {
         double g[6];
 #pragma unroll
@@ -432,7 +465,7 @@ __device__ __attribute__((noinline)) void vjp_one(const VjpArgs& ag, const ldoub
     int o, n;
     int status = check_track(a.off, a.sid, a.loc, a.cov, a.seed, a.seed_cov, H, N, a.n_surf, a.max_hits, t, o, n);
     double* wl = a.ws + (slot / TILE) * a.tile_doubles + (slot % TILE);
-    if (status == ST_OK) status = vjp_fwd<P, FK>(a, sm, wl, t, o, n);
+    if (status == ST_OK) status = vjp_fwd<P, FK>(a, sm, wl, sx, t, o, n);
     if (status == ST_OK) {
         vjp_bwd<P, FK>(a, sm, wl, sx, t, o, n);
     } else {
