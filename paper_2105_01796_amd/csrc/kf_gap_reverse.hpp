@@ -224,16 +224,46 @@ struct GapBar {
     double Mr[3][5], MT[3][5];
     double Mtl;
     double lam, gd, gpd;
+};
+
+// Adjoints of the two surfaces' placements.  Between the gap's end and its
+// start they wait in memory (in gap_reverse: the slots of F's adjoint, read
+// by then), which takes 42 registers off the reverse of the steps; only a
+// capped step adds to them (PK_NB, PK_CB).
+struct PlaceBar {
     double cb[3], ub[3], vb[3], nb[3];   // surface b placement
     double ca[3], ua[3], va[3];          // surface a placement (n_a enters only the noise)
 };
+constexpr int PK_CB = 0, PK_NB = 3, PK_UB = 6, PK_VB = 9, PK_CA = 12, PK_UA = 15, PK_VA = 18, PK_N = 21;
+
+template <class MP>
+__device__ inline void park_store(MP m, int64_t fs, const PlaceBar& pb) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        m[(PK_CB + i) * fs] = pb.cb[i]; m[(PK_NB + i) * fs] = pb.nb[i];
+        m[(PK_UB + i) * fs] = pb.ub[i]; m[(PK_VB + i) * fs] = pb.vb[i];
+        m[(PK_CA + i) * fs] = pb.ca[i]; m[(PK_UA + i) * fs] = pb.ua[i];
+        m[(PK_VA + i) * fs] = pb.va[i];
+    }
+}
+
+template <class MP>
+__device__ inline void park_load(MP m, int64_t fs, PlaceBar& pb) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        pb.cb[i] = m[(PK_CB + i) * fs]; pb.nb[i] = m[(PK_NB + i) * fs];
+        pb.ub[i] = m[(PK_UB + i) * fs]; pb.vb[i] = m[(PK_VB + i) * fs];
+        pb.ca[i] = m[(PK_CA + i) * fs]; pb.ua[i] = m[(PK_UA + i) * fs];
+        pb.va[i] = m[(PK_VA + i) * fs];
+    }
+}
 
 // Reverse of one accepted step.  Inputs: the state at the step start (g), its
 // h, capped flag and stage accelerations k; gb holds the adjoints of the step's outputs
 // on entry and of its inputs on return.
-template <int FK>
+template <int FK, class MP>
 __device__ inline void step_reverse(const Field<double, FK>& fl, const double* sb, const GapRun<double, FK>& g,
-                                    double h, bool capped, const double k[4][3], GapBar& gb) {
+                                    double h, bool capped, const double k[4][3], GapBar& gb, MP pk, int64_t fs) {
     // explicit q/p dependence of stage k_i = (q/p) kappa T_i x B_i: kappa T_i x B_i
     // (one form for every q/p, q/p = 0 included; reversed through T_i and B_i)
     const double lam = g.lam, lk = lam * kKappa;
@@ -471,8 +501,8 @@ __device__ inline void step_reverse(const Field<double, FK>& fl, const double* s
         const double db = hb / nT, nTb = -hb * dist / (nT * nT);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            gb.nb[i] += db * (sb[i] - r[i]) + nTb * T[i];
-            gb.cb[i] += db * g.nb[i];
+            pk[(PK_NB + i) * fs] += db * (sb[i] - r[i]) + nTb * T[i];
+            pk[(PK_CB + i) * fs] += db * g.nb[i];
             gb.r[i] -= db * g.nb[i];
             gb.T[i] += nTb * g.nb[i];
         }
@@ -488,7 +518,7 @@ __device__ inline void step_reverse(const Field<double, FK>& fl, const double* s
 template <int FK, class FbP>
 __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa, const double* sb,
                                    const GapRun<double, FK>& g, double t0, const double xpb[6], FbP Fb, int64_t fs,
-                                   GapBar& gb) {
+                                   GapBar& gb, PlaceBar& pb) {
     const double lam = g.lam, lk = lam * kKappa;
     // landed state and the final move
     double rp[3], Tp[3];
@@ -518,8 +548,8 @@ __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         gb.r[i] = 0.0; gb.T[i] = 0.0;
-        gb.cb[i] = 0.0; gb.ub[i] = 0.0; gb.vb[i] = 0.0; gb.nb[i] = 0.0;
-        gb.ca[i] = 0.0; gb.ua[i] = 0.0; gb.va[i] = 0.0;
+        pb.cb[i] = 0.0; pb.ub[i] = 0.0; pb.vb[i] = 0.0; pb.nb[i] = 0.0;
+        pb.ca[i] = 0.0; pb.ua[i] = 0.0; pb.va[i] = 0.0;
 #pragma unroll
         for (int j = 0; j < 5; ++j) { gb.Mr[i][j] = 0.0; gb.MT[i][j] = 0.0; }
     }
@@ -533,10 +563,10 @@ __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa
     double rb[3], Tb[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        gb.ub[i] += xpb[0] * dd[i];
-        gb.vb[i] += xpb[1] * dd[i];
+        pb.ub[i] += xpb[0] * dd[i];
+        pb.vb[i] += xpb[1] * dd[i];
         rb[i] = xpb[0] * u[i] + xpb[1] * v[i];
-        gb.cb[i] -= rb[i];
+        pb.cb[i] -= rb[i];
         Tb[i] = 0.0;
     }
     const double rho2 = T[0] * T[0] + T[1] * T[1];
@@ -576,8 +606,8 @@ __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa
         double mrpb[3], mtpb[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            gb.ub[i] += F0b * mrp[i];
-            gb.vb[i] += F1b * mrp[i];
+            pb.ub[i] += F0b * mrp[i];
+            pb.vb[i] += F1b * mrp[i];
             mrpb[i] = F0b * u[i] + F1b * v[i];
         }
         // F2 = (T0 mt1 - T1 mt0) ip
@@ -616,15 +646,15 @@ __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa
         double mrb[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            gb.nb[i] += qb * mr[i];
+            pb.nb[i] += qb * mr[i];
             mrb[i] = mrpb[i] + qb * nb[i];
         }
         if (fixed) {
             // the loc0 / loc1 columns are (u_a, v_a) of surface a
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                if (j == 0) gb.ua[i] += mrb[i];
-                else gb.va[i] += mrb[i];
+                if (j == 0) pb.ua[i] += mrb[i];
+                else pb.va[i] += mrb[i];
             }
         } else {
 #pragma unroll
@@ -640,7 +670,7 @@ __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa
     const double nTb = inTb * (-1.0 / (nTd * nTd));
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        gb.nb[i] += nTb * T[i];
+        pb.nb[i] += nTb * T[i];
         Tb[i] += nTb * nb[i] + 2.0 * n2b * T[i];
     }
     Tb[0] += rhob * T[0] / rho;
@@ -678,8 +708,8 @@ __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa
         const double distb = remb / nT0, nT0b = -remb * rem / nT0;
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            gb.nb[i] += distb * (sb[i] - rp[i]) + nT0b * Tp[i];
-            gb.cb[i] += distb * nb[i];
+            pb.nb[i] += distb * (sb[i] - rp[i]) + nT0b * Tp[i];
+            pb.cb[i] += distb * nb[i];
             gb.r[i] -= distb * nb[i];
             gb.T[i] += nT0b * nb[i];
         }
@@ -691,7 +721,7 @@ __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa
 // tangent columns; adds to xb[0..4] and the surface-a adjoints.
 template <int FK>
 __device__ inline void start_reverse(const Cfg& cfg, const double* sa, const double x[6], const GapRun<double, FK>& g,
-                                     GapBar& gb, double xb[6]) {
+                                     const GapBar& gb, PlaceBar& pb, double xb[6]) {
     double sp, cp, st, ct;
     angle_sincos(x[2], &sp, &cp);
     angle_sincos(x[3], &st, &ct);
@@ -700,9 +730,9 @@ __device__ inline void start_reverse(const Cfg& cfg, const double* sa, const dou
     // r0 = c_a + x0 u_a + x1 v_a
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        gb.ca[i] += gb.r[i];
-        gb.ua[i] += x[0] * gb.r[i];
-        gb.va[i] += x[1] * gb.r[i];
+        pb.ca[i] += gb.r[i];
+        pb.ua[i] += x[0] * gb.r[i];
+        pb.va[i] += x[1] * gb.r[i];
     }
     xb[0] += dot3(gb.r, ua);
     xb[1] += dot3(gb.r, va);
@@ -710,8 +740,8 @@ __device__ inline void start_reverse(const Cfg& cfg, const double* sa, const dou
         // the propagated loc0 / loc1 columns start as u_a, v_a
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            gb.ua[i] += gb.Mr[i][0];
-            gb.va[i] += gb.Mr[i][1];
+            pb.ua[i] += gb.Mr[i][0];
+            pb.va[i] += gb.Mr[i][1];
         }
     }
     // T0 = (cp st, sp st, ct); MT col 2 = dT0/dphi, col 3 = dT0/dtheta
@@ -736,9 +766,10 @@ __device__ inline void start_reverse(const Cfg& cfg, const double* sa, const dou
 // Reverse of one gap: xb += dL/dx, sab/sbb (13 each: c, R row-major; x/X0
 // unused) += dL/d(surface placement), for the adjoints xpb of the predicted
 // state and Fb of the stored transport Jacobian (entry q at Fb[q * fs]; FbP
-// as in end_reverse).  P: the forward pass's stepping precision, which the
-// replay uses.  Returns false if the replay did not reproduce a successful
-// gap.
+// as in end_reverse, writable: once read, its first PK_N slots hold the
+// placement adjoints, so the caller's Fb is overwritten).  P: the forward
+// pass's stepping precision, which the replay uses.  Returns false if the
+// replay did not reproduce a successful gap.
 template <class P, int FK, class FbP>
 __device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg_in, const double* sa, const double* sb,
                                    const double x[6], const double xpb[6], FbP Fb, int64_t fs, double xb[6],
@@ -759,7 +790,11 @@ __device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg_in, const 
     if (gap_run<P, FK>(flp, cfg, 1 << 30, g, h, capped, S, k) != 0) return false;
     const int n_acc = g.accepted;
     GapBar gb;
-    end_reverse<FK>(fl, sa, sb, widen<FK>(g, gw), x[5], xpb, Fb, fs, gb);
+    {
+        PlaceBar pe;
+        end_reverse<FK>(fl, sa, sb, widen<FK>(g, gw), x[5], xpb, Fb, fs, gb, pe);
+        park_store(Fb, fs, pe);     // F's adjoint has been read: its slots take the placement adjoints
+    }
     for (int s = n_acc - 1; s >= 0; --s) {
         gap_start<P, FK>(cfg, sa, sb, x, g);
         if (gap_run<P, FK>(flp, cfg, s, g, h, capped, S, k) != 1) return false;
@@ -768,21 +803,23 @@ __device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg_in, const 
         for (int st = 0; st < 4; ++st)
 #pragma unroll
             for (int i = 0; i < 3; ++i) kd[st][i] = double(k[st][i]);
-        step_reverse<FK>(fl, sb, widen<FK>(g, gw), double(h), capped, kd, gb);
+        step_reverse<FK>(fl, sb, widen<FK>(g, gw), double(h), capped, kd, gb, Fb, fs);
     }
+    PlaceBar pb;
+    park_load(Fb, fs, pb);
     gap_start<P, FK>(cfg, sa, sb, x, g);
-    start_reverse<FK>(cfg, sa, x, widen<FK>(g, gw), gb, xb);
+    start_reverse<FK>(cfg, sa, x, widen<FK>(g, gw), gb, pb, xb);
     // surface placement adjoints in the 13-value layout: c, then R row-major
     // (columns u, v, n)
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        sab[i] += gb.ca[i];
-        sab[3 + 3 * i + 0] += gb.ua[i];
-        sab[3 + 3 * i + 1] += gb.va[i];
-        sbb[i] += gb.cb[i];
-        sbb[3 + 3 * i + 0] += gb.ub[i];
-        sbb[3 + 3 * i + 1] += gb.vb[i];
-        sbb[3 + 3 * i + 2] += gb.nb[i];
+        sab[i] += pb.ca[i];
+        sab[3 + 3 * i + 0] += pb.ua[i];
+        sab[3 + 3 * i + 1] += pb.va[i];
+        sbb[i] += pb.cb[i];
+        sbb[3 + 3 * i + 0] += pb.ub[i];
+        sbb[3 + 3 * i + 1] += pb.vb[i];
+        sbb[3 + 3 * i + 2] += pb.nb[i];
     }
     // the initial distance d0 = n_b.(c_b - r0) enters only through the
     // capped steps and the final move, whose reverses above use the current

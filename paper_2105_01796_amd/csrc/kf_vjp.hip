@@ -268,11 +268,13 @@ __device__ inline void noise_vjp(const double* sa, const double x[6], double mas
 // the alignment of sa and sb to ga and gb.  sx (LDS) holds the start state
 // (SX_X0) and the adjoints (SX_XPB, SX_FB, SX_QB).  The propagation is
 // reversed by hand (kf_gap_reverse.hpp; it reads the adjoint of F column by
-// column; the replay in the forward pass's stepping precision P), the noise
-// by its closed-form derivative.
+// column, then keeps the surface placement adjoints in those SX_FB slots;
+// the replay in the forward pass's stepping precision P), the noise by its
+// closed-form derivative.
+static_assert(PK_N <= SX_QB - SX_FB, "the placement adjoints fit in the slots of F's adjoint");
 template <class P, int FK>
 __device__ __attribute__((always_inline)) void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const double* __restrict__ sb,
-                        const ldouble* sx, double xb[6], double ga[6], double gb[6]) {
+                        ldouble* sx, double xb[6], double ga[6], double gb[6]) {
     double x[6], xpb[6];
     ldl(sx, SX_X0, x);
     ldl(sx, SX_XPB, xpb);
