@@ -763,8 +763,19 @@ __device__ inline void start_reverse(const Cfg& cfg, const double* sa, const dou
     xb[5] += gb.t;
 }
 
+// The gap's start state x, entry i at xs[i * fs], read afresh at each use (a
+// volatile read, which the compiler may neither merge nor hoist), so that the
+// six values are not held in registers through the reverse of the steps.
+template <class MP>
+__device__ inline void reload_x(MP xs, int64_t fs, double x[6]) {
+    using E = typename std::remove_pointer<MP>::type;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) x[i] = *(volatile E*)(xs + i * fs);
+}
+
 // Reverse of one gap: xb += dL/dx, sab/sbb (13 each: c, R row-major; x/X0
-// unused) += dL/d(surface placement), for the adjoints xpb of the predicted
+// unused) += dL/d(surface placement), for the start state x (memory: entry i
+// at xs[i * fs], as Fb), the adjoints xpb of the predicted
 // state and Fb of the stored transport Jacobian (entry q at Fb[q * fs]; FbP
 // as in end_reverse, writable: once read, its first PK_N slots hold the
 // placement adjoints, so the caller's Fb is overwritten).  P: the forward
@@ -772,7 +783,7 @@ __device__ inline void start_reverse(const Cfg& cfg, const double* sa, const dou
 // replay did not reproduce a successful gap.
 template <class P, int FK, class FbP>
 __device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg_in, const double* sa, const double* sb,
-                                   const double x[6], const double xpb[6], FbP Fb, int64_t fs, double xb[6],
+                                   FbP xs, const double xpb[6], FbP Fb, int64_t fs, double xb[6],
                                    double sab[13], double sbb[13]) {
     // a private copy: the replay loops read these settings from registers
     // instead of reloading them through the reference after every store
@@ -786,17 +797,27 @@ __device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg_in, const 
     Stages<P, FK> S;
     P k[4][3], h;
     bool capped;
-    gap_start<P, FK>(cfg, sa, sb, x, g);
+    {
+        double x[6];
+        reload_x(xs, fs, x);
+        gap_start<P, FK>(cfg, sa, sb, x, g);
+    }
     if (gap_run<P, FK>(flp, cfg, 1 << 30, g, h, capped, S, k) != 0) return false;
     const int n_acc = g.accepted;
     GapBar gb;
     {
         PlaceBar pe;
+        double x[6];
+        reload_x(xs, fs, x);
         end_reverse<FK>(fl, sa, sb, widen<FK>(g, gw), x[5], xpb, Fb, fs, gb, pe);
         park_store(Fb, fs, pe);     // F's adjoint has been read: its slots take the placement adjoints
     }
     for (int s = n_acc - 1; s >= 0; --s) {
-        gap_start<P, FK>(cfg, sa, sb, x, g);
+        {
+            double x[6];
+            reload_x(xs, fs, x);
+            gap_start<P, FK>(cfg, sa, sb, x, g);
+        }
         if (gap_run<P, FK>(flp, cfg, s, g, h, capped, S, k) != 1) return false;
         double kd[4][3];
 #pragma unroll
@@ -807,6 +828,8 @@ __device__ inline bool gap_reverse(const FieldDef& fd, const Cfg& cfg_in, const 
     }
     PlaceBar pb;
     park_load(Fb, fs, pb);
+    double x[6];
+    reload_x(xs, fs, x);
     gap_start<P, FK>(cfg, sa, sb, x, g);
     start_reverse<FK>(cfg, sa, x, widen<FK>(g, gw), gb, pb, xb);
     // surface placement adjoints in the 13-value layout: c, then R row-major

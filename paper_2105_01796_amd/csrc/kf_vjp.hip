@@ -275,13 +275,14 @@ static_assert(PK_N <= SX_QB - SX_FB, "the placement adjoints fit in the slots of
 template <class P, int FK>
 __device__ __attribute__((always_inline)) void gap_vjp(const VjpArgs& a, const double* __restrict__ sa, const double* __restrict__ sb,
                         ldouble* sx, double xb[6], double ga[6], double gb[6]) {
-    double x[6], xpb[6];
-    ldl(sx, SX_X0, x);
+    double xpb[6];
     ldl(sx, SX_XPB, xpb);
     double sab[13], sbb[13];
 #pragma unroll
     for (int i = 0; i < 13; ++i) { sab[i] = 0.0; sbb[i] = 0.0; }
-    gap_reverse<P, FK>(a.field, a.cfg, sa, sb, x, xpb, sx + SX_FB * TILE, TILE, xb, sab, sbb);
+    gap_reverse<P, FK>(a.field, a.cfg, sa, sb, sx + SX_X0 * TILE, xpb, sx + SX_FB * TILE, TILE, xb, sab, sbb);
+    double x[6];
+    ldl(sx, SX_X0, x);
     if (a.cfg.ms && sa[12] > 0.0) noise_vjp(sa, x, a.cfg.mass, sx[SX_QB * TILE], sx[(SX_QB + 1) * TILE], xb, sab);
     double t[6];
     placement_to_alignment(sa, sab, t);
