@@ -260,7 +260,8 @@ __device__ inline void park_load(MP m, int64_t fs, PlaceBar& pb) {
 
 // Reverse of one accepted step.  Inputs: the state at the step start (g), its
 // h, capped flag and stage accelerations k; gb holds the adjoints of the step's outputs
-// on entry and of its inputs on return.
+// on entry and of its inputs on return; a capped step also adds to the parked
+// placement adjoints (PlaceBar layout, entry q at pk[q * fs]).
 template <int FK, class MP>
 __device__ inline void step_reverse(const Field<double, FK>& fl, const double* sb, const GapRun<double, FK>& g,
                                     double h, bool capped, const double k[4][3], GapBar& gb, MP pk, int64_t fs) {
@@ -514,7 +515,8 @@ __device__ inline void step_reverse(const Field<double, FK>& fl, const double* s
 // the tangent columns.  g holds the landed state (before the final move); the
 // adjoints of xp and F are read through xpb[6] and Fb (entry q of F at
 // Fb[q * fs], read one column at a time; FbP is the pointer type, so the
-// caller decides the memory it lives in).  Sets gb.
+// caller decides the memory it lives in).  Sets gb and the placement
+// adjoints pb.
 template <int FK, class FbP>
 __device__ inline void end_reverse(const Field<double, FK>& fl, const double* sa, const double* sb,
                                    const GapRun<double, FK>& g, double t0, const double xpb[6], FbP Fb, int64_t fs,
