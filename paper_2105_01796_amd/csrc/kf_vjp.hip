@@ -32,6 +32,7 @@
 #include <stdint.h>
 #include <string.h>
 #include <math.h>
+#include <type_traits>
 #include "kf_common.hpp"
 #include "kf_adjoint.hpp"
 #include "kf_gap_reverse.hpp"
@@ -457,8 +458,18 @@ __device__ __attribute__((always_inline)) void vjp_bwd(const VjpArgs& a, const d
 // body (the sweeps above are inlined into it).  At two waves per SIMD (half
 // the registers) its spills made the C2 adjoint 1.8x slower (measured), so the
 // kernels are built for one wave per SIMD only.
+// The kernel arguments reach it by reference in the FP64 kernels and as a
+// private copy in the mixed-precision ones.  Through the reference the body
+// reads them with flat loads, which count against the LDS wait counter as
+// well, so every wait for the LDS stash also waits for them; from the copy
+// they are private (scratch) loads, at the price of the copy per track.
+// Measured on 1e5 tracks: the copy made the mixed adjoint 2-6 % faster (C2,
+// C3, C5) and the FP64 one up to 4 % slower (C2, C3).
+template <class P>
+using VjpArgsIn = typename std::conditional<std::is_same<P, float>::value, const VjpArgs, const VjpArgs&>::type;
+
 template <class P, int FK>
-__device__ __attribute__((noinline)) void vjp_one(const VjpArgs& ag, const ldouble* sml, ldouble* sx, int64_t slot,
+__device__ __attribute__((noinline)) void vjp_one(VjpArgsIn<P> ag, const ldouble* sml, ldouble* sx, int64_t slot,
                                                   int t) {
     const VjpArgs& a = ag;
     // the surface table is in LDS; a generic pointer derived from an LDS one
