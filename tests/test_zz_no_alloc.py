@@ -51,7 +51,7 @@ def _same(a, b):
 
 
 @pytest.mark.parametrize("schedule", [1, 2])
-def test_noalloc_equals_workspace_fit_on_two_calls(kf, schedule):
+def test_noalloc_equals_workspace_fit_on_calls_in_a_row(kf, schedule):
     import torch
     # first call: 3000 ragged tracks of up to 30 hits (the larger input), then
     # 1000 tracks through five cylinders and five layers of straws, then 100
